@@ -1,0 +1,129 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that the pins
+of test_oracle_pins catch every one of them."""
+from __future__ import annotations
+
+import math
+
+import pytest
+
+import oracle.paillier as O
+import oracle.quant as Q
+from tests import test_oracle_pins as pins
+
+PINS_CRYPTO = [
+    pins.test_golden_hand_worked_example,
+    lambda: pins.test_bruteforce_bijection(5, 7),
+    lambda: pins.test_bruteforce_homomorphisms(3, 5),
+    pins.test_pow_plain_vs_builtin,
+]
+PINS_QUANT = [
+    pins.test_quantize_error_bound_and_aggregate,
+    pins.test_quantize_ties_round_half_even,
+    pins.test_quantize_range,
+    pins.test_dequantize_rounding_above_2_53,
+]
+
+
+def _caught(checks) -> bool:
+    for chk in checks:
+        try:
+            chk()
+        except (AssertionError, ValueError, ArithmeticError, ZeroDivisionError):
+            return True
+    return False
+
+
+def _pow_square_first(base, exp, mod):
+    t, g, e = 1 % mod, base % mod, exp
+    while e > 0:
+        g = (g * g) % mod          # mistake: squares before using the bit
+        if e & 1:
+            t = (t * g) % mod
+        e >>= 1
+    return t
+
+
+def _pow_drop_last(base, exp, mod):
+    t, g, e = 1 % mod, base % mod, exp
+    while e > 1:                   # mistake: the top bit is never applied
+        if e & 1:
+            t = (t * g) % mod
+        g = (g * g) % mod
+        e >>= 1
+    return t
+
+
+def _enc_g_is_n(pk, m, r):
+    n2 = pk.n2
+    return (O.pow_plain(pk.n, m, n2) * O.pow_plain(r, pk.n, n2)) % n2  # mistake: g = n
+
+
+def _enc_r_exp_m(pk, m, r):
+    n2 = pk.n2
+    return (O.pow_plain(pk.g, m, n2) * O.pow_plain(r, m, n2)) % n2  # mistake: r^m
+
+
+def _L_no_division(x, n):
+    return x - 1  # mistake: forgets the division by n
+
+
+def _add_is_sum(pk, c1, c2):
+    return (c1 + c2) % pk.n2  # mistake: + instead of *
+
+
+def _smul_off_by_one(pk, c, k):
+    return O.pow_plain(c, k + 1, pk.n2)  # mistake: wrong exponent
+
+
+def _derive_phi_and_wrong_mu(p, q):
+    pk, sk = ORIG_DERIVE(p, q)
+    lam = (p - 1) * (q - 1)        # mistake: phi instead of lcm (and mu not recomputed)
+    return pk, O.SecretKey(p=p, q=q, n=sk.n, lam=lam, mu=sk.mu)
+
+
+ORIG_DERIVE = O.derive_keys
+
+
+@pytest.mark.parametrize("name,target,mutant", [
+    ("pow square-first", "pow_plain", _pow_square_first),
+    ("pow drops top bit", "pow_plain", _pow_drop_last),
+    ("g = n", "encrypt", _enc_g_is_n),
+    ("r^m", "encrypt", _enc_r_exp_m),
+    ("L without division", "L", _L_no_division),
+    ("add as sum", "hom_add", _add_is_sum),
+    ("scalar k+1", "hom_scalar_mul", _smul_off_by_one),
+    ("phi for lcm", "derive_keys", _derive_phi_and_wrong_mu),
+])
+def test_crypto_mutants_caught(monkeypatch, name, target, mutant):
+    monkeypatch.setattr(O, target, mutant)
+    assert _caught(PINS_CRYPTO), f"mutant '{name}' survived the pins"
+
+
+def _q_floor(x, k, o):
+    v = math.floor(math.ldexp(x, k))  # mistake: floor instead of round-half-even
+    return v + o
+
+
+def _q_half_up(x, k, o):
+    v = math.floor(math.ldexp(x, k) + 0.5)  # mistake: ties away from even
+    return v + o
+
+
+def _dq_no_weight(M, k, o, W):
+    return math.ldexp(float(M - o), -k)  # mistake: one offset regardless of W
+
+
+def _dq_truncating(M, k, o, W):
+    d = M - W * o
+    return math.ldexp(float(d >> 1 << 1), -k)  # mistake: drops the low bit
+
+
+@pytest.mark.parametrize("name,target,mutant", [
+    ("floor", "quantize", _q_floor),
+    ("half up", "quantize", _q_half_up),
+    ("no weight", "dequantize", _dq_no_weight),
+    ("truncating", "dequantize", _dq_truncating),
+])
+def test_quant_mutants_caught(monkeypatch, name, target, mutant):
+    monkeypatch.setattr(Q, target, mutant)
+    assert _caught(PINS_QUANT), f"mutant '{name}' survived the pins"

@@ -1,0 +1,178 @@
+/*
+ * pc2.h -- C ABI of libpc2: batched Paillier encryption, decryption and
+ * homomorphic aggregation of quantized vectors on one AMD Instinct MI355X
+ * (gfx950), for the privacy-preserving distributed ADMM of
+ * "Parallel Collaborative ADMM Privacy Computing and Adaptive GPU
+ * Acceleration for Distributed Edge Networks" (Xia et al.).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status.     Every function returns an int status: PC2_OK (0) or a negative
+ *             PC2_E_* code.  Nothing aborts, throws or prints.
+ * Integers.   Multi-precision values are little-endian arrays of uint32
+ *             limbs.  For a key with nbits-bit n, L = ceil(nbits / 32);
+ *             plaintexts and randomness have L limbs, ciphertexts 2L limbs.
+ *             Inputs and outputs are canonical residues (in [0, modulus)),
+ *             in normal (not Montgomery) form.
+ * Arrays.     Data calls take DEVICE pointers to element-major arrays
+ *             ([count][limbs]), owned and freed by the caller.  They are
+ *             enqueued on the given HIP stream (NULL = the null stream) and
+ *             return before the work finishes.  Outputs may alias an input
+ *             of identical shape exactly; partial overlap is not allowed.
+ * Keys.       Key material is passed once, as HOST arrays, to the key
+ *             constructors; the library derives and uploads every constant.
+ *             g = n + 1 is implied (the paper admits any g in Z*_{n^2}).
+ * Errors.     Argument errors (NULL pointer with count > 0, unsupported
+ *             size, bad key) are reported synchronously and nothing is
+ *             enqueued.  count == 0 is a no-op returning PC2_OK.  Data errors
+ *             found on the device (a plaintext >= n, r = 0 or r >= n, a
+ *             ciphertext >= n^2, a value outside the quantizer's range, a
+ *             ciphertext that does not decrypt) make that element's output
+ *             all-zero bits (NaN for dequantize) and latch PC2_E_RANGE in the
+ *             context; pc2_ctx_sync returns and clears the latch.
+ * Threads.    A context and its keys are used from one host thread at a
+ *             time.  Calls on one stream run in order; calls that share a
+ *             context on different streams share its scratch memory and
+ *             must not overlap (the library serialises its own launches
+ *             on the stream it is given).
+ * Memory.     Data calls do not allocate once the context's scratch has been
+ *             sized for the largest key class used (pc2_ctx_reserve, or the
+ *             first call of that class).
+ */
+#ifndef PC2_H
+#define PC2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PC2_OK = 0,
+  PC2_E_INVAL = -1,       /* bad argument (NULL, size, mismatched key/context) */
+  PC2_E_RANGE = -2,       /* latched device data error (see Errors above) */
+  PC2_E_NOMEM = -3,       /* device or host allocation failed */
+  PC2_E_DEVICE = -4,      /* HIP runtime error or no usable device */
+  PC2_E_UNSUPPORTED = -5, /* key size or option this build does not support */
+  PC2_E_BUSY = -6         /* resource limit reached (serving admission) */
+};
+
+typedef struct pc2_ctx pc2_ctx;
+typedef struct pc2_pk pc2_pk;
+typedef struct pc2_sk pc2_sk;
+
+/* Affine quantizer (Sec. III-A, Gamma_2 with a common interval and a
+ * power-of-two scale): m = rint(x * 2^log2_scale) + offset. */
+typedef struct {
+  int32_t log2_scale;
+  uint64_t offset;
+} pc2_qparams;
+
+/* ------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `hip_device`.  *out receives the
+ * handle.  PC2_E_DEVICE if the device does not exist or is not gfx950. */
+int pc2_ctx_create(int hip_device, pc2_ctx **out);
+int pc2_ctx_destroy(pc2_ctx *ctx);
+
+/* Wait for all work the library enqueued on `hip_stream`, then return and
+ * clear the latched device data error (PC2_OK or PC2_E_RANGE). */
+int pc2_ctx_sync(pc2_ctx *ctx, void *hip_stream);
+
+/* Return and clear the latched data error without synchronising.  The value
+ * reflects kernels that have completed. */
+int pc2_ctx_take_error(pc2_ctx *ctx);
+
+/* Pre-size the scratch memory for keys of up to `max_nbits` bits so that no
+ * later data call allocates. */
+int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
+
+/* Options.  PC2_OPT_WINDOW: fixed window width w in {0 (auto), 2..6} of the
+ * modular exponentiations.  PC2_OPT_MODMUL: limb-product engine for the
+ * Montgomery products (PC2_MODMUL_VALU or PC2_MODMUL_MFMA). */
+enum { PC2_OPT_WINDOW = 1, PC2_OPT_MODMUL = 2 };
+enum { PC2_MODMUL_VALU = 0, PC2_MODMUL_MFMA = 1 };
+int pc2_ctx_set_option(pc2_ctx *ctx, int option, int64_t value);
+int pc2_ctx_get_option(pc2_ctx *ctx, int option, int64_t *value);
+
+const char *pc2_strerror(int status);
+
+/* ------------------------------------------------------------------ keys */
+
+/* Public key (Sec. III-B key generation: public key (n, g), g = n + 1).
+ * n: host array of ceil(nbits/32) limbs, odd, 15 <= n < 2^nbits, with
+ * 2 <= nbits <= 3072. */
+int pc2_pk_create(pc2_ctx *ctx, uint32_t nbits, const uint32_t *n, pc2_pk **out);
+
+/* Private key from the primes p and q (Sec. III-B: n = pq,
+ * eps = lcm(p-1, q-1)).  p, q: host arrays of ceil(nbits/32) limbs, distinct
+ * odd primes with pq < 2^nbits.  Primality is the caller's contract.  The
+ * key also serves as a public key for the data calls below through
+ * pc2_sk_public. */
+int pc2_sk_create(pc2_ctx *ctx, uint32_t nbits, const uint32_t *p, const uint32_t *q,
+                  pc2_sk **out);
+const pc2_pk *pc2_sk_public(const pc2_sk *sk);
+int pc2_pk_destroy(pc2_pk *pk);
+int pc2_sk_destroy(pc2_sk *sk);
+/* Bit size and limb count L of a key. */
+int pc2_pk_info(const pc2_pk *pk, uint32_t *nbits, uint32_t *limbs);
+
+/* ------------------------------------------------------------ data calls */
+
+/* Quantize (Sec. III-A, Gamma_2 in affine form): m[i] = rint(x[i] * 2^k) + o,
+ * rint = round half to even.  x: double[count]; m: uint64[count] (equal to
+ * two uint32 limbs per element).  Non-finite x or a result outside
+ * [0, 2^64) -> m = 0 and PC2_E_RANGE latched. */
+int pc2_quantize(pc2_ctx *ctx, const pc2_qparams *q, const double *x, uint64_t *m,
+                 size_t count, void *stream);
+
+/* Inverse quantization of an aggregate of `weight` quantized addends
+ * (Sec. III-C inverse quantization, generalised to weight W):
+ * x[i] = double(M_i - W * o) / 2^k with round-to-nearest-even conversion.
+ * m: uint32[count][m_limbs]; limbs above the first two must be zero and
+ * |M_i - W*o| < 2^63, else x = NaN and PC2_E_RANGE latched. */
+int pc2_dequantize(pc2_ctx *ctx, const pc2_qparams *q, const uint32_t *m,
+                   uint32_t m_limbs, uint64_t weight, double *x, size_t count,
+                   void *stream);
+
+/* Encryption (Sec. III-B, f_en): c = g^m r^n mod n^2 with g = n + 1, i.e.
+ * c = (1 + m n) r^n mod n^2.  m: [count][m_limbs] with 1 <= m_limbs <= L,
+ * m < n; r: [count][L], 0 < r < n, one r per element (gcd(r, n) = 1 is the
+ * caller's contract); c: [count][2L]. */
+int pc2_encrypt(const pc2_pk *pk, const uint32_t *m, uint32_t m_limbs, const uint32_t *r,
+                uint32_t *c, size_t count, void *stream);
+
+/* Decryption (Sec. III-C, f_de = L(c^eps mod n^2) mu mod n), evaluated through
+ * the split into Z_{p^2} x Z_{q^2} (Sec. IV, Lemmas 1-2).  c: [count][2L],
+ * c < n^2; m: [count][L]. */
+int pc2_decrypt(const pc2_sk *sk, const uint32_t *c, uint32_t *m, size_t count,
+                void *stream);
+
+/* Homomorphic addition (Definition 1): out = c1 c2 mod n^2.  [count][2L]. */
+int pc2_hom_add(const pc2_pk *pk, const uint32_t *c1, const uint32_t *c2, uint32_t *out,
+                size_t count, void *stream);
+
+/* Multiply by a constant (Definition 2): out = c^k mod n^2, k a uint64 per
+ * element (k = 0 gives 1). */
+int pc2_hom_scalar_mul(const pc2_pk *pk, const uint32_t *c, const uint64_t *k,
+                       uint32_t *out, size_t count, void *stream);
+
+/* K-way aggregation (Definition 1 applied K-1 times): out = prod_k c_k mod n^2.
+ * c_k: HOST array of K device pointers, each [count][2L]; 1 <= K <= 128. */
+int pc2_hom_sum(const pc2_pk *pk, const uint32_t *const *c_k, uint32_t K, uint32_t *out,
+                size_t count, void *stream);
+
+/* Fused encrypt -> aggregate -> decrypt: m_out[j] = Dec(prod_k Enc(m_k[j], r_k[j])).
+ * m_k, r_k: HOST arrays of K device pointers ([count][m_limbs], [count][L]);
+ * m_out: [count][L].  The ciphertexts never reach the caller's memory.
+ * 1 <= K <= 128. */
+int pc2_enc_sum_dec(const pc2_sk *sk, const uint32_t *const *m_k, const uint32_t *const *r_k,
+                    uint32_t K, uint32_t m_limbs, uint32_t *m_out, size_t count,
+                    void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PC2_H */

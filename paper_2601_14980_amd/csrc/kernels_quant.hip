@@ -1,0 +1,81 @@
+// Quantization (Sec. III-A, Gamma_2 in affine form with a power-of-two
+// scale) and inverse quantization of an aggregate (Sec. III-C).  Memory-bound
+// element-wise kernels: 8 B in + 8 B out per element for quantize.
+// Compiled with -ffp-contract=off; with a power-of-two scale both directions
+// round exactly once.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "pc2_types.hpp"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_quantize(int log2_scale, uint64_t offset,
+                                                  const double* __restrict__ x,
+                                                  uint64_t* __restrict__ m, size_t count,
+                                                  int* err) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    double v = rint(ldexp(x[i], log2_scale));  // one rounding, half to even
+    uint64_t out = 0;
+    // v is integer-valued; the result offset + v must lie in [0, 2^64)
+    bool ok = fabs(v) < 18446744073709551616.0;  // false for NaN and infinities
+    if (ok) {
+      if (v >= 0.0) {
+        out = offset + (uint64_t)v;
+        ok = out >= offset;  // no wrap past 2^64
+      } else {
+        uint64_t mag = (uint64_t)(-v);
+        ok = offset >= mag;
+        out = offset - mag;
+      }
+    }
+    m[i] = ok ? out : 0u;
+    bad |= !ok;
+  }
+  if (bad) atomicOr(err, pc2k::ERR_RANGE);
+}
+
+__global__ __launch_bounds__(256) void k_dequantize(int log2_scale, uint64_t offset,
+                                                    const uint32_t* __restrict__ m, int m_limbs,
+                                                    uint64_t weight, double* __restrict__ x,
+                                                    size_t count, int* err) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const uint32_t* mi = m + i * m_limbs;
+    uint32_t hi_or = 0;
+    for (int j = 2; j < m_limbs; ++j) hi_or |= mi[j];
+    uint64_t M = mi[0];
+    if (m_limbs > 1) M |= (uint64_t)mi[1] << 32;
+    // D = M - W*o as a signed 128-bit integer
+    __int128 d = (__int128)(unsigned __int128)M - (__int128)((unsigned __int128)weight * offset);
+    const __int128 lim = (__int128)1 << 63;
+    bool ok = (hi_or == 0) && (d > -lim) && (d < lim);
+    double v = ok ? ldexp((double)(int64_t)d, -log2_scale) : __builtin_nan("");
+    x[i] = v;
+    bad |= !ok;
+  }
+  if (bad) atomicOr(err, pc2k::ERR_RANGE);
+}
+
+}  // namespace
+
+namespace pc2k {
+
+hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, const double* x,
+                           uint64_t* m, size_t count) {
+  hipLaunchKernelGGL(k_quantize, dim3(l.grid), dim3(256), 0, (hipStream_t)l.stream, log2_scale,
+                     offset, x, m, count, l.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_dequantize(const Launch& l, int log2_scale, uint64_t offset, const uint32_t* m,
+                             int m_limbs, uint64_t weight, double* x, size_t count) {
+  hipLaunchKernelGGL(k_dequantize, dim3(l.grid), dim3(256), 0, (hipStream_t)l.stream, log2_scale,
+                     offset, m, m_limbs, weight, x, count, l.err);
+  return hipGetLastError();
+}
+
+}  // namespace pc2k

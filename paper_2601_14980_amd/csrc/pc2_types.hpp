@@ -1,0 +1,91 @@
+// Device-visible key constants and launch plumbing shared by the host code
+// and the kernels.  All pointers are device addresses inside one allocation
+// owned by the key object.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pc2k {
+
+// Error bits latched in the context's device word.
+enum : int { ERR_RANGE = 1 };
+
+constexpr int RK_MAX = 128;  // largest K of a K-way aggregation in one call
+
+// One odd modulus N in D-digit "chunked" layout: a number is CH words, lane t
+// of a tile owns words [t*K4, t*K4 + K).  Nl is N as 32-bit limbs, zero
+// padded to nl limbs.
+struct ModConst {
+  const uint32_t* N;
+  const uint32_t* R1;  // R mod N
+  const uint32_t* R2;  // R^2 mod N
+  const uint32_t* R3;  // R^3 mod N
+  const uint32_t* ONE; // the integer 1 (chunked)
+  const uint32_t* Nl;
+  uint32_t nprime;     // -N^-1 mod 2^D
+  int nl;
+};
+
+struct PkConst {
+  ModConst n2;           // modulus n^2; Nl has 2L limbs
+  const uint32_t* nR;    // n R mod n^2 (chunked)
+  const uint32_t* Rk;    // R^k mod n^2 for k = 0..RK_MAX, entry k at k*CH
+  const uint32_t* n;     // n, L limbs
+  int L;                 // limbs of n (ABI: plaintexts L, ciphertexts 2L)
+  int nbits;             // bit length of n (the exponent of r^n)
+};
+
+// One prime s of the CRT decryption (s = p or q, p > q).
+struct HalfConst {
+  ModConst s2;           // modulus s^2; Nl has Ls2 = s2.nl limbs
+  const uint32_t* s;     // s, Ls limbs
+  const uint32_t* e;     // s - 1, Ls limbs
+  const uint32_t* sinv;  // s^-1 mod 2^(32 Ls)
+  const uint32_t* H;     // h_s 2^(32 Ls) mod s, h_s = L_s(g^(s-1) mod s^2)^-1 mod s
+  uint32_t s_n0;         // -s^-1 mod 2^32
+  int Ls;
+};
+
+struct SkConst {
+  PkConst pk;
+  HalfConst h[2];        // [0] = p, [1] = q
+  const uint32_t* QI;    // q^-1 2^(32 Ls) mod p
+  int ebits;             // max bit length of p-1, q-1
+};
+
+struct PtrList {
+  const uint32_t* p[RK_MAX];
+};
+
+// Key size classes: index by ceil(log2) of the key.  n^2 and s^2 use
+// separate digit geometries (see mont_tile.hpp).
+constexpr int NUM_CLASSES = 8;
+inline int class_for_bits(int nbits) {
+  const int lim[NUM_CLASSES] = {32, 64, 128, 256, 512, 1024, 2048, 3072};
+  for (int i = 0; i < NUM_CLASSES; ++i)
+    if (nbits <= lim[i]) return i;
+  return -1;
+}
+
+// geometry numbers per class (mirrors the template instantiations)
+struct ClassGeo {
+  int nD, nK, nT;  // n^2
+  int pD, pK, pT;  // s^2
+};
+constexpr ClassGeo CLASS_GEO[NUM_CLASSES] = {
+    {28, 2, 2, 28, 2, 1},   {28, 3, 2, 28, 3, 1},   {28, 5, 2, 28, 5, 1},
+    {28, 10, 2, 28, 10, 1}, {28, 19, 2, 28, 19, 1}, {28, 37, 2, 28, 37, 1},
+    {27, 38, 4, 28, 37, 2}, {27, 29, 8, 27, 29, 4},
+};
+
+// Launch configuration chosen by the host for a data call.
+struct Launch {
+  int grid;              // workgroups (one wavefront each)
+  int window;            // window width for the exponentiations
+  uint32_t* scratch;     // per-tile tables
+  size_t slot_words;     // words of one tile's table slot
+  int* err;              // latched error word
+  void* stream;
+};
+
+}  // namespace pc2k

@@ -1,0 +1,330 @@
+"""Thin ctypes binding of libpc2 (include/pc2.h).
+
+Argument marshalling only: every function below checks tensor shapes and
+dtypes, takes device pointers and the current HIP stream from torch, and calls
+the C function of the same name.  All arithmetic runs in the library's HIP
+kernels.  Importing this module fails if libpc2.so has not been built.
+
+Limb arrays are torch tensors of dtype int32 holding the bit patterns of
+little-endian uint32 limbs; uint64 arrays (quantized values, scalars) are int64
+tensors holding the bit patterns.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t
+from ctypes import c_uint32, c_uint64, c_void_p
+from pathlib import Path
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_LIB_PATH = Path(__file__).resolve().parent / "libpc2.so"
+
+PC2_OK = 0
+PC2_E_INVAL = -1
+PC2_E_RANGE = -2
+PC2_E_NOMEM = -3
+PC2_E_DEVICE = -4
+PC2_E_UNSUPPORTED = -5
+PC2_E_BUSY = -6
+PC2_OPT_WINDOW = 1
+PC2_OPT_MODMUL = 2
+PC2_MODMUL_VALU = 0
+PC2_MODMUL_MFMA = 1
+
+EXPORTS = [
+    "pc2_ctx_create", "pc2_ctx_destroy", "pc2_ctx_sync", "pc2_ctx_take_error",
+    "pc2_ctx_reserve", "pc2_ctx_set_option", "pc2_ctx_get_option", "pc2_strerror",
+    "pc2_pk_create", "pc2_sk_create", "pc2_sk_public", "pc2_pk_destroy", "pc2_sk_destroy",
+    "pc2_pk_info", "pc2_quantize", "pc2_dequantize", "pc2_encrypt", "pc2_decrypt",
+    "pc2_hom_add", "pc2_hom_scalar_mul", "pc2_hom_sum", "pc2_enc_sum_dec",
+]
+
+
+class PC2Error(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+class pc2_qparams(ctypes.Structure):
+    _fields_ = [("log2_scale", c_int32), ("offset", c_uint64)]
+
+
+def _load() -> ctypes.CDLL:
+    if not _LIB_PATH.exists():
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_2601_14980_amd.build`")
+    lib = ctypes.CDLL(str(_LIB_PATH))
+    P = c_void_p
+    sig = {
+        "pc2_ctx_create": (c_int, [c_int, POINTER(P)]),
+        "pc2_ctx_destroy": (c_int, [P]),
+        "pc2_ctx_sync": (c_int, [P, P]),
+        "pc2_ctx_take_error": (c_int, [P]),
+        "pc2_ctx_reserve": (c_int, [P, c_uint32]),
+        "pc2_ctx_set_option": (c_int, [P, c_int, c_int64]),
+        "pc2_ctx_get_option": (c_int, [P, c_int, POINTER(c_int64)]),
+        "pc2_strerror": (c_char_p, [c_int]),
+        "pc2_pk_create": (c_int, [P, c_uint32, P, POINTER(P)]),
+        "pc2_sk_create": (c_int, [P, c_uint32, P, P, POINTER(P)]),
+        "pc2_sk_public": (P, [P]),
+        "pc2_pk_destroy": (c_int, [P]),
+        "pc2_sk_destroy": (c_int, [P]),
+        "pc2_pk_info": (c_int, [P, POINTER(c_uint32), POINTER(c_uint32)]),
+        "pc2_quantize": (c_int, [P, POINTER(pc2_qparams), P, P, c_size_t, P]),
+        "pc2_dequantize": (c_int, [P, POINTER(pc2_qparams), P, c_uint32, c_uint64, P,
+                                   c_size_t, P]),
+        "pc2_encrypt": (c_int, [P, P, c_uint32, P, P, c_size_t, P]),
+        "pc2_decrypt": (c_int, [P, P, P, c_size_t, P]),
+        "pc2_hom_add": (c_int, [P, P, P, P, c_size_t, P]),
+        "pc2_hom_scalar_mul": (c_int, [P, P, P, P, c_size_t, P]),
+        "pc2_hom_sum": (c_int, [P, POINTER(P), c_uint32, P, c_size_t, P]),
+        "pc2_enc_sum_dec": (c_int, [P, POINTER(P), POINTER(P), c_uint32, c_uint32, P,
+                                    c_size_t, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def strerror(status: int) -> str:
+    return lib.pc2_strerror(status).decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status != PC2_OK:
+        raise PC2Error(status, what)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype: torch.dtype, what: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what}: expected a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    return t.data_ptr()
+
+
+def limbs_to_host_array(x: int, nlimbs: int) -> np.ndarray:
+    """int -> uint32 numpy array of nlimbs little-endian limbs."""
+    return np.frombuffer(int(x).to_bytes(4 * nlimbs, "little"), dtype="<u4").astype(np.uint32)
+
+
+# ------------------------------------------------------------------ handles
+class Context:
+    """A libpc2 context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = c_void_p()
+        _check(lib.pc2_ctx_create(device, byref(h)), "pc2_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def close(self) -> None:
+        if self.handle:
+            lib.pc2_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self, stream=None) -> int:
+        """Wait for the stream and return the latched data status (0 or PC2_E_RANGE)."""
+        st = lib.pc2_ctx_sync(self.handle, _stream(stream))
+        if st not in (PC2_OK, PC2_E_RANGE):
+            raise PC2Error(st, "pc2_ctx_sync")
+        return st
+
+    def reserve(self, max_nbits: int) -> None:
+        _check(lib.pc2_ctx_reserve(self.handle, max_nbits), "pc2_ctx_reserve")
+
+    def set_option(self, option: int, value: int) -> None:
+        _check(lib.pc2_ctx_set_option(self.handle, option, value), "pc2_ctx_set_option")
+
+    def get_option(self, option: int) -> int:
+        v = c_int64()
+        _check(lib.pc2_ctx_get_option(self.handle, option, byref(v)), "pc2_ctx_get_option")
+        return v.value
+
+
+class PublicKey:
+    def __init__(self, ctx: Context, nbits: int, n: int):
+        self.ctx, self.nbits, self.n = ctx, nbits, n
+        self.L = (nbits + 31) // 32
+        arr = limbs_to_host_array(n, self.L)
+        h = c_void_p()
+        _check(lib.pc2_pk_create(ctx.handle, nbits, arr.ctypes.data, byref(h)), "pc2_pk_create")
+        self.handle = h
+        self._owned = True
+
+    def close(self) -> None:
+        if self.handle and self._owned:
+            lib.pc2_pk_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SecretKey:
+    def __init__(self, ctx: Context, nbits: int, p: int, q: int):
+        self.ctx, self.nbits, self.p, self.q = ctx, nbits, p, q
+        self.n = p * q
+        self.L = (nbits + 31) // 32
+        pa, qa = limbs_to_host_array(p, self.L), limbs_to_host_array(q, self.L)
+        h = c_void_p()
+        _check(lib.pc2_sk_create(ctx.handle, nbits, pa.ctypes.data, qa.ctypes.data, byref(h)),
+               "pc2_sk_create")
+        self.handle = h
+        pub = PublicKey.__new__(PublicKey)
+        pub.ctx, pub.nbits, pub.n, pub.L = ctx, nbits, self.n, self.L
+        pub.handle = c_void_p(lib.pc2_sk_public(h))
+        pub._owned = False
+        self.public = pub
+
+    def close(self) -> None:
+        if self.handle:
+            lib.pc2_sk_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- data calls
+def _rows(t: torch.Tensor, width: int, what: str) -> int:
+    if t.dim() != 2 or t.shape[1] != width:
+        raise ValueError(f"{what}: expected shape [count, {width}], got {tuple(t.shape)}")
+    return t.shape[0]
+
+
+def pc2_quantize(ctx: Context, log2_scale: int, offset: int, x: torch.Tensor,
+                 m: torch.Tensor, stream=None) -> None:
+    """m (int64 bit patterns of uint64) <- rint(x 2^k) + offset."""
+    if x.shape != m.shape or x.dim() != 1:
+        raise ValueError("x and m must be 1-D tensors of equal length")
+    q = pc2_qparams(log2_scale, offset)
+    _check(lib.pc2_quantize(ctx.handle, byref(q), _dev_ptr(x, torch.float64, "x"),
+                            _dev_ptr(m, torch.int64, "m"), x.numel(), _stream(stream)),
+           "pc2_quantize")
+
+
+def pc2_dequantize(ctx: Context, log2_scale: int, offset: int, m: torch.Tensor, weight: int,
+                   x: torch.Tensor, stream=None) -> None:
+    """x <- (M - weight*offset) / 2^k for M given as int32 limb rows [count, m_limbs]."""
+    count = m.shape[0]
+    if m.dim() != 2 or x.shape != (count,):
+        raise ValueError("m must be [count, m_limbs] and x [count]")
+    q = pc2_qparams(log2_scale, offset)
+    _check(lib.pc2_dequantize(ctx.handle, byref(q), _dev_ptr(m, torch.int32, "m"), m.shape[1],
+                              weight, _dev_ptr(x, torch.float64, "x"), count, _stream(stream)),
+           "pc2_dequantize")
+
+
+def pc2_encrypt(pk: PublicKey, m: torch.Tensor, r: torch.Tensor, c: torch.Tensor,
+                stream=None) -> None:
+    count = _rows(r, pk.L, "r")
+    if m.dim() != 2 or m.shape[0] != count:
+        raise ValueError("m must be [count, m_limbs]")
+    _rows(c, 2 * pk.L, "c")
+    _check(lib.pc2_encrypt(pk.handle, _dev_ptr(m, torch.int32, "m"), m.shape[1],
+                           _dev_ptr(r, torch.int32, "r"), _dev_ptr(c, torch.int32, "c"), count,
+                           _stream(stream)), "pc2_encrypt")
+
+
+def pc2_decrypt(sk: SecretKey, c: torch.Tensor, m: torch.Tensor, stream=None) -> None:
+    count = _rows(c, 2 * sk.L, "c")
+    _rows(m, sk.L, "m")
+    if m.shape[0] != count:
+        raise ValueError("m and c must have the same count")
+    _check(lib.pc2_decrypt(sk.handle, _dev_ptr(c, torch.int32, "c"),
+                           _dev_ptr(m, torch.int32, "m"), count, _stream(stream)), "pc2_decrypt")
+
+
+def pc2_hom_add(pk: PublicKey, c1: torch.Tensor, c2: torch.Tensor, out: torch.Tensor,
+                stream=None) -> None:
+    count = _rows(c1, 2 * pk.L, "c1")
+    _rows(c2, 2 * pk.L, "c2")
+    _rows(out, 2 * pk.L, "out")
+    _check(lib.pc2_hom_add(pk.handle, _dev_ptr(c1, torch.int32, "c1"),
+                           _dev_ptr(c2, torch.int32, "c2"), _dev_ptr(out, torch.int32, "out"),
+                           count, _stream(stream)), "pc2_hom_add")
+
+
+def pc2_hom_scalar_mul(pk: PublicKey, c: torch.Tensor, k: torch.Tensor, out: torch.Tensor,
+                       stream=None) -> None:
+    count = _rows(c, 2 * pk.L, "c")
+    _rows(out, 2 * pk.L, "out")
+    if k.shape != (count,):
+        raise ValueError("k must be [count]")
+    _check(lib.pc2_hom_scalar_mul(pk.handle, _dev_ptr(c, torch.int32, "c"),
+                                  _dev_ptr(k, torch.int64, "k"),
+                                  _dev_ptr(out, torch.int32, "out"), count, _stream(stream)),
+           "pc2_hom_scalar_mul")
+
+
+def pc2_hom_sum(pk: PublicKey, cs: Sequence[torch.Tensor], out: torch.Tensor,
+                stream=None) -> None:
+    count = _rows(out, 2 * pk.L, "out")
+    ptrs = (c_void_p * len(cs))()
+    for i, c in enumerate(cs):
+        if _rows(c, 2 * pk.L, f"c[{i}]") != count:
+            raise ValueError("all inputs must have the output's count")
+        ptrs[i] = _dev_ptr(c, torch.int32, f"c[{i}]")
+    _check(lib.pc2_hom_sum(pk.handle, ptrs, len(cs), _dev_ptr(out, torch.int32, "out"), count,
+                           _stream(stream)), "pc2_hom_sum")
+
+
+def pc2_enc_sum_dec(sk: SecretKey, ms: Sequence[torch.Tensor], rs: Sequence[torch.Tensor],
+                    m_out: torch.Tensor, stream=None) -> None:
+    count = _rows(m_out, sk.L, "m_out")
+    if len(ms) != len(rs) or not ms:
+        raise ValueError("need K >= 1 plaintext and randomness arrays")
+    m_limbs = ms[0].shape[1]
+    mp, rp = (c_void_p * len(ms))(), (c_void_p * len(rs))()
+    for i, (m, r) in enumerate(zip(ms, rs)):
+        if _rows(m, m_limbs, f"m[{i}]") != count or _rows(r, sk.L, f"r[{i}]") != count:
+            raise ValueError("all inputs must have the output's count")
+        mp[i] = _dev_ptr(m, torch.int32, f"m[{i}]")
+        rp[i] = _dev_ptr(r, torch.int32, f"r[{i}]")
+    _check(lib.pc2_enc_sum_dec(sk.handle, mp, rp, len(ms), m_limbs,
+                               _dev_ptr(m_out, torch.int32, "m_out"), count, _stream(stream)),
+           "pc2_enc_sum_dec")
+
+
+# ---------------------------------------------------------------- marshalling
+def to_device_limbs(arr: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint32 [count][limbs] numpy array -> int32 CUDA tensor (same bits)."""
+    a = np.ascontiguousarray(arr, dtype=np.uint32)
+    return torch.from_numpy(a.view(np.int32)).to(device)
+
+
+def from_device_limbs(t: torch.Tensor) -> np.ndarray:
+    """int32 tensor -> uint32 numpy array (same bits)."""
+    return t.detach().cpu().numpy().view(np.uint32)

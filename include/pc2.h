@@ -172,6 +172,70 @@ int pc2_enc_sum_dec(const pc2_sk *sk, const uint32_t *const *m_k, const uint32_t
                     uint32_t K, uint32_t m_limbs, uint32_t *m_out, size_t count,
                     void *stream);
 
+/* ------------------------------------------------------ batched launches */
+
+/* One job of a batch.  A batch runs one phase of many edge nodes' work --
+ * all their encryptions, all their aggregations or all their decryptions --
+ * in ONE persistent launch, whatever the vector lengths, under keys of up to
+ * two size classes (supported mixes: one class of 256, 1024, 2048 or 3072
+ * bits, or 1024 with 2048 bits).  Results are identical to the one-call-per-
+ * job entry points above. */
+enum { PC2_OP_ENCRYPT = 1, PC2_OP_HOM_SUM = 2, PC2_OP_DECRYPT = 3 };
+typedef struct {
+  int op;                        /* PC2_OP_*; every job of a batch has the same op */
+  const pc2_pk *pk;              /* encrypt, hom_sum */
+  const pc2_sk *sk;              /* decrypt */
+  const uint32_t *in0;           /* encrypt: m [count][m_limbs]; decrypt: c [count][2L] */
+  const uint32_t *in1;           /* encrypt: r [count][L] */
+  uint32_t m_limbs;              /* encrypt */
+  uint32_t *out;                 /* encrypt: c [count][2L]; decrypt: m [count][L];
+                                    hom_sum: product [count][2L] */
+  size_t count;                  /* output elements (0: the job is skipped) */
+  uint32_t K;                    /* hom_sum: number of inputs, 1..128 */
+  const uint32_t *const *inputs; /* hom_sum: HOST array of K device pointers */
+  const size_t *lengths;         /* hom_sum: HOST array of K input lengths or NULL; element j
+                                    multiplies the inputs k with j < lengths[k] (ragged
+                                    aggregation), or all K inputs when NULL */
+} pc2_job;
+typedef struct pc2_batch pc2_batch;
+
+/* Plan a batch: validates the jobs, uploads job descriptors and a work
+ * queue, and allocates the batch's own scratch (so that later calls never
+ * allocate).  The device arrays named by the jobs must stay valid for the
+ * life of the batch; their contents may change between runs. */
+int pc2_batch_create(pc2_ctx *ctx, const pc2_job *jobs, size_t njobs, pc2_batch **out);
+
+/* Run a planned batch on a stream.  On a non-null stream the first run
+ * captures the launch in a HIP graph and later runs replay it. */
+int pc2_batch_run(pc2_batch *batch, void *hip_stream);
+int pc2_batch_destroy(pc2_batch *batch);
+
+/* A reusable persistent launcher for schedulers that form a new batch at
+ * every launch (continuous batching, see the serving loop): descriptor and
+ * work-queue buffers (device and pinned host) and scratch are allocated once,
+ * for up to max_jobs jobs and max_groups element groups per launch, with keys
+ * of at most max_nbits bits. */
+typedef struct pc2_runner pc2_runner;
+int pc2_runner_create(pc2_ctx *ctx, int op, uint32_t max_nbits, size_t max_jobs,
+                      size_t max_groups, pc2_runner **out);
+/* Elements per group (one wavefront's share) for a key and op. */
+int pc2_runner_group_size(const pc2_pk *pk, int op, uint32_t *elems);
+/* One persistent launch over element groups [first[i], first[i] + ngroups[i])
+ * of each job i (jobs as for pc2_batch_create; the key classes of one launch
+ * must form a supported mix).  Asynchronous on the stream; the launcher's
+ * staging buffers are reused by the next launch once this one's copies are
+ * done. */
+int pc2_runner_launch(pc2_runner *runner, const pc2_job *jobs, const size_t *first,
+                      const size_t *ngroups, size_t njobs, void *hip_stream);
+int pc2_runner_destroy(pc2_runner *runner);
+
+/* Autotuner: times the exponentiation window w in {4, 5, 6} for encryption
+ * and decryption under this key's size class on a device-filling synthetic
+ * sample, keeps the fastest in the context (used by later calls and
+ * batches of that class) and reports them.  Synchronises the stream;
+ * allocates temporary buffers. */
+int pc2_autotune(const pc2_sk *sk, void *hip_stream, int *w_enc, int *w_dec);
+
 #ifdef __cplusplus
 }
 #endif

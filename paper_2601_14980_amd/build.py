@@ -29,6 +29,7 @@ COMMON = [
 ]
 UNITS = {
     "kernels_paillier.hip": [],
+    "kernels_batch.hip": [],
     "kernels_quant.hip": ["-ffp-contract=off"],
     "api.cpp": [],
 }

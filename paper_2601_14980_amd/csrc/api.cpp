@@ -24,6 +24,35 @@ struct pc2_ctx {
   int window = 0;              // 0 = automatic
   int modmul = PC2_MODMUL_VALU;
   int occ[pc2k::NUM_CLASSES][pc2k::OP_COUNT] = {};  // workgroups per CU (0 = not queried)
+  int tuned[pc2k::NUM_CLASSES][pc2k::OP_COUNT] = {};  // autotuned windows (0 = none)
+};
+
+struct pc2_runner {
+  pc2_ctx* ctx = nullptr;
+  int op = 0, max_cls = 0;
+  size_t max_jobs = 0, max_groups = 0, max_ptrs = 0;
+  size_t slot_words = 0;
+  int grid_cap = 0;
+  void* dev = nullptr;   // jobs | items | pointers | queue
+  void* host = nullptr;  // pinned staging, same layout
+  size_t jobs_b = 0, items_b = 0, ptr_b = 0;
+  uint32_t* scratch = nullptr;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+};
+
+struct pc2_batch {
+  pc2_ctx* ctx = nullptr;
+  int op = 0, pair = 0, grid = 0, nitems = 0;
+  int w_a = 5, w_b = 5;
+  size_t slot_words = 0;
+  void* dev = nullptr;  // jobs, items, pointer/length arrays, queue
+  pc2k::BatchJob* jobs = nullptr;
+  pc2k::BatchItem* items = nullptr;
+  int* queue = nullptr;
+  uint32_t* scratch = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* graph_stream = nullptr;
 };
 
 struct pc2_pk {
@@ -221,6 +250,12 @@ int auto_window(int cls, int op) {
   return cls >= 5 ? 5 : (cls >= 3 ? 4 : 3);
 }
 
+int window_for(const pc2_ctx* ctx, int cls, int op) {
+  if (ctx->window) return ctx->window;
+  const int t = ctx->tuned[cls][op == pc2k::OP_FUSED ? pc2k::OP_ENC : op];
+  return t ? t : auto_window(cls, op);
+}
+
 int occupancy(pc2_ctx* ctx, int cls, int op) {
   int& o = ctx->occ[cls][op];
   if (o == 0) {
@@ -237,7 +272,7 @@ int occupancy(pc2_ctx* ctx, int cls, int op) {
 // grid + scratch for a Paillier launch over `count` elements
 int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::Launch* l,
             void* stream) {
-  const int w = ctx->window ? ctx->window : auto_window(cls, op);
+  const int w = window_for(ctx, cls, op);
   const size_t epb = (size_t)pc2k::elems_per_block(cls);
   const size_t groups = (count + epb - 1) / epb;
   const size_t cap = (size_t)ctx->cus * occupancy(ctx, cls, op);
@@ -597,6 +632,444 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
   if (rc) return rc;
   return status_of(
       pc2k::launch_fused(sk->pk.cls, l, sk->c, ms, rs, (int)K, (int)m_limbs, m_out, count));
+}
+
+// ---------------------------------------------------------------- batches
+int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch** out) {
+  if (!ctx || !jobs || !out || njobs == 0) return PC2_E_INVAL;
+  *out = nullptr;
+  const int op_abi = jobs[0].op;
+  int op;
+  if (op_abi == PC2_OP_ENCRYPT) op = pc2k::OP_ENC;
+  else if (op_abi == PC2_OP_DECRYPT) op = pc2k::OP_DEC;
+  else if (op_abi == PC2_OP_HOM_SUM) op = pc2k::OP_SUM;
+  else return PC2_E_INVAL;
+  // validate and collect classes
+  int ca = -1, cb = -1, Ls = 0;
+  size_t ptr_words = 0;
+  for (size_t i = 0; i < njobs; ++i) {
+    const pc2_job& j = jobs[i];
+    if (j.op != op_abi) return PC2_E_INVAL;
+    if (j.count == 0) continue;
+    const pc2_pk* pk = (op == pc2k::OP_DEC) ? (j.sk ? &j.sk->pk : nullptr) : j.pk;
+    if (!pk || pk->ctx != ctx || !j.out) return PC2_E_INVAL;
+    if (op == pc2k::OP_ENC &&
+        (!j.in0 || !j.in1 || j.m_limbs < 1 || (int)j.m_limbs > pk->L))
+      return PC2_E_INVAL;
+    if (op == pc2k::OP_DEC && !j.in0) return PC2_E_INVAL;
+    if (op == pc2k::OP_SUM) {
+      if (!j.inputs || j.K < 1 || j.K > (uint32_t)pc2k::RK_MAX) return PC2_E_INVAL;
+      for (uint32_t k = 0; k < j.K; ++k)
+        if (!j.inputs[k] || (j.lengths && j.lengths[k] > j.count)) return PC2_E_INVAL;
+      ptr_words += 2 * (size_t)j.K;
+    }
+    if (op == pc2k::OP_DEC) Ls = std::max(Ls, j.sk->c.h[0].Ls);
+    const int c = pk->cls;
+    if (ca < 0 || ca == c) ca = c;
+    else if (cb < 0 || cb == c) cb = c;
+    else return PC2_E_UNSUPPORTED;
+  }
+  if (ca < 0) return PC2_E_INVAL;  // every job empty
+  if (cb < 0) cb = ca;
+  const int pair = pc2k::batch_pair(ca, cb);
+  if (pair < 0) return PC2_E_UNSUPPORTED;
+  const int pa = pc2k::batch_pair_class(pair, 0), pb = pc2k::batch_pair_class(pair, 1);
+  pc2_batch* b = new (std::nothrow) pc2_batch();
+  if (!b) return PC2_E_NOMEM;
+  b->ctx = ctx;
+  b->op = op;
+  b->pair = pair;
+  b->w_a = window_for(ctx, pa, op);
+  b->w_b = window_for(ctx, pb, op);
+  // descriptors and items (most expensive class first)
+  std::vector<pc2k::BatchJob> dj;
+  std::vector<pc2k::BatchItem> items;
+  std::vector<size_t> ptrbuf;  // per hom_sum job: K pointers then K lengths
+  std::vector<size_t> ptr_off;
+  for (size_t i = 0; i < njobs; ++i) {
+    const pc2_job& j = jobs[i];
+    if (j.count == 0) continue;
+    pc2k::BatchJob d{};
+    const pc2_pk* pk = (op == pc2k::OP_DEC) ? &j.sk->pk : j.pk;
+    d.cls = pk->cls;
+    d.op = op;
+    d.m_limbs = (int)j.m_limbs;
+    d.K = (int)j.K;
+    d.pk = pk->c;
+    if (op == pc2k::OP_DEC) d.sk = j.sk->c;
+    d.in0 = j.in0;
+    d.in1 = j.in1;
+    d.out = j.out;
+    d.count = j.count;
+    size_t off = ptrbuf.size();
+    if (op == pc2k::OP_SUM) {
+      for (uint32_t k = 0; k < j.K; ++k) ptrbuf.push_back((size_t)j.inputs[k]);
+      for (uint32_t k = 0; k < j.K; ++k) ptrbuf.push_back(j.lengths ? j.lengths[k] : j.count);
+    }
+    ptr_off.push_back(off);
+    dj.push_back(d);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    const int want = pass == 0 ? std::max(pa, pb) : std::min(pa, pb);
+    if (pass == 1 && pa == pb) break;
+    for (size_t ji = 0; ji < dj.size(); ++ji) {
+      if (dj[ji].cls != want) continue;
+      const size_t epw = (size_t)pc2k::elems_per_block(dj[ji].cls);
+      const size_t groups = (dj[ji].count + epw - 1) / epw;
+      for (size_t g = 0; g < groups; ++g) items.push_back(pc2k::BatchItem{(int)ji, 0, g});
+    }
+  }
+  b->nitems = (int)items.size();
+  // one device allocation: jobs | items | pointer/length arrays | queue
+  const size_t jobs_b = (dj.size() * sizeof(pc2k::BatchJob) + 255) & ~(size_t)255;
+  const size_t items_b = (items.size() * sizeof(pc2k::BatchItem) + 255) & ~(size_t)255;
+  const size_t ptr_b = (ptrbuf.size() * sizeof(size_t) + 255) & ~(size_t)255;
+  const size_t total = jobs_b + items_b + ptr_b + 256;
+  int rc = PC2_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) rc = PC2_E_DEVICE;
+  if (!rc && hipMalloc(&b->dev, total) != hipSuccess) rc = PC2_E_NOMEM;
+  if (!rc) {
+    char* base = (char*)b->dev;
+    b->jobs = (pc2k::BatchJob*)base;
+    b->items = (pc2k::BatchItem*)(base + jobs_b);
+    size_t* dptr = (size_t*)(base + jobs_b + items_b);
+    b->queue = (int*)(base + jobs_b + items_b + ptr_b);
+    for (size_t ji = 0; ji < dj.size(); ++ji)
+      if (op == pc2k::OP_SUM) {
+        dj[ji].inputs = (const uint32_t* const*)(dptr + ptr_off[ji]);
+        dj[ji].lengths = dptr + ptr_off[ji] + dj[ji].K;
+      }
+    if (hipMemcpy(b->jobs, dj.data(), dj.size() * sizeof(pc2k::BatchJob),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->items, items.data(), items.size() * sizeof(pc2k::BatchItem),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        (!ptrbuf.empty() && hipMemcpy(dptr, ptrbuf.data(), ptrbuf.size() * sizeof(size_t),
+                                      hipMemcpyHostToDevice) != hipSuccess))
+      rc = PC2_E_DEVICE;
+  }
+  // grid and the batch's own scratch
+  if (!rc) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pc2k::batch_kernel(op, pair), 64, 0) !=
+            hipSuccess ||
+        occ <= 0)
+      occ = 1;
+    b->grid = std::max(1, std::min(ctx->cus * occ, b->nitems));
+    int ta = 0, tb = 0;
+    size_t wa = 0, wb = 0;
+    pc2k::batch_slot_shape(op, pa, b->w_a, Ls, &ta, &wa);
+    pc2k::batch_slot_shape(op, pb, b->w_b, Ls, &tb, &wb);
+    const int tiles = std::max(ta, tb);
+    b->slot_words = (std::max(wa, wb) + 3) & ~(size_t)3;
+    const size_t bytes = (size_t)b->grid * tiles * b->slot_words * 4;
+    if (bytes && hipMalloc(&b->scratch, bytes) != hipSuccess) rc = PC2_E_NOMEM;
+  }
+  if (rc) {
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->scratch) (void)hipFree(b->scratch);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return PC2_OK;
+}
+
+int pc2_batch_run(pc2_batch* b, void* hip_stream) {
+  if (!b || !b->ctx) return PC2_E_INVAL;
+  if (hipSetDevice(b->ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  auto launch = [&](void* st) {
+    return pc2k::launch_batch(b->op, b->pair, b->grid, b->jobs, b->items, b->nitems, b->queue,
+                              b->scratch, b->slot_words, b->w_a, b->w_b, b->ctx->err, st);
+  };
+  if (!hip_stream) return status_of(launch(nullptr));
+  if (!b->exec || b->graph_stream != hip_stream) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return PC2_E_DEVICE;
+    hipError_t le = launch(hip_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(st, &g);
+    if (le != hipSuccess || ee != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return PC2_E_DEVICE;
+    }
+    hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      b->exec = nullptr;
+      return PC2_E_DEVICE;
+    }
+    b->graph_stream = hip_stream;
+  }
+  return status_of(hipGraphLaunch(b->exec, (hipStream_t)hip_stream));
+}
+
+int pc2_batch_destroy(pc2_batch* b) {
+  if (!b || !b->ctx) return PC2_E_INVAL;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->dev) (void)hipFree(b->dev);
+  if (b->scratch) (void)hipFree(b->scratch);
+  delete b;
+  return PC2_OK;
+}
+
+// -------------------------------------------------------------- autotune
+int pc2_autotune(const pc2_sk* sk, void* hip_stream, int* w_enc, int* w_dec) {
+  if (!sk || !sk->ctx) return PC2_E_INVAL;
+  pc2_ctx* ctx = sk->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  const int cls = sk->pk.cls, L = sk->pk.L;
+  // one device-filling wave of elements per trial
+  const size_t count = (size_t)ctx->cus * occupancy(ctx, cls, pc2k::OP_ENC) *
+                       (size_t)pc2k::elems_per_block(cls);
+  // the work of a fixed-window exponentiation does not depend on the data:
+  // m = 0, r = 1 is valid under every key
+  std::vector<uint32_t> hm(count, 0), hr(count * L, 0);
+  for (size_t i = 0; i < count; ++i) hr[i * L] = 1;
+  uint32_t *m = nullptr, *r = nullptr, *c = nullptr, *d = nullptr;
+  int rc = PC2_OK;
+  if (hipMalloc(&m, count * 4) != hipSuccess || hipMalloc(&r, count * L * 4) != hipSuccess ||
+      hipMalloc(&c, count * 2 * L * 4) != hipSuccess || hipMalloc(&d, count * L * 4) != hipSuccess)
+    rc = PC2_E_NOMEM;
+  if (!rc && (hipMemcpy(m, hm.data(), count * 4, hipMemcpyHostToDevice) != hipSuccess ||
+              hipMemcpy(r, hr.data(), count * L * 4, hipMemcpyHostToDevice) != hipSuccess))
+    rc = PC2_E_DEVICE;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = PC2_E_DEVICE;
+  const int saved_window = ctx->window;
+  int best[2] = {0, 0};
+  for (int which = 0; which < 2 && !rc; ++which) {
+    float best_ms = 1e30f;
+    for (int w = 4; w <= 6 && !rc; ++w) {
+      ctx->window = w;
+      for (int rep = 0; rep < 2 && !rc; ++rep) {  // rep 0 warms up (and sizes scratch)
+        if (hipEventRecord(e0, (hipStream_t)hip_stream) != hipSuccess) rc = PC2_E_DEVICE;
+        int st = which == 0 ? pc2_encrypt(&sk->pk, m, 1, r, c, count, hip_stream)
+                            : pc2_decrypt(sk, c, d, count, hip_stream);
+        if (st) rc = st;
+        if (!rc && (hipEventRecord(e1, (hipStream_t)hip_stream) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess))
+          rc = PC2_E_DEVICE;
+        float ms = 0;
+        if (!rc && rep == 1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+          best_ms = ms;
+          best[which] = w;
+        }
+      }
+    }
+  }
+  ctx->window = saved_window;
+  if (!rc) {
+    ctx->tuned[cls][pc2k::OP_ENC] = best[0];
+    ctx->tuned[cls][pc2k::OP_DEC] = best[1];
+    if (w_enc) *w_enc = best[0];
+    if (w_dec) *w_dec = best[1];
+    rc = pc2_ctx_take_error(ctx);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (m) (void)hipFree(m);
+  if (r) (void)hipFree(r);
+  if (c) (void)hipFree(c);
+  if (d) (void)hipFree(d);
+  return rc;
+}
+
+// ---------------------------------------------------------------- runners
+namespace {
+int op_from_abi(int op_abi) {
+  if (op_abi == PC2_OP_ENCRYPT) return pc2k::OP_ENC;
+  if (op_abi == PC2_OP_DECRYPT) return pc2k::OP_DEC;
+  if (op_abi == PC2_OP_HOM_SUM) return pc2k::OP_SUM;
+  return -1;
+}
+}  // namespace
+
+int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_jobs,
+                      size_t max_groups, pc2_runner** out) {
+  if (!ctx || !out || max_jobs == 0 || max_groups == 0) return PC2_E_INVAL;
+  *out = nullptr;
+  const int op = op_from_abi(op_abi);
+  const int cls = pc2k::class_for_bits((int)max_nbits);
+  if (op < 0) return PC2_E_INVAL;
+  if (cls < 0) return PC2_E_UNSUPPORTED;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  pc2_runner* r = new (std::nothrow) pc2_runner();
+  if (!r) return PC2_E_NOMEM;
+  r->ctx = ctx;
+  r->op = op;
+  r->max_cls = cls;
+  r->max_jobs = max_jobs;
+  r->max_groups = max_groups;
+  r->max_ptrs = op == pc2k::OP_SUM ? 2 * (size_t)pc2k::RK_MAX * max_jobs : 0;
+  r->jobs_b = (max_jobs * sizeof(pc2k::BatchJob) + 255) & ~(size_t)255;
+  r->items_b = (max_groups * sizeof(pc2k::BatchItem) + 255) & ~(size_t)255;
+  r->ptr_b = (r->max_ptrs * sizeof(size_t) + 255) & ~(size_t)255;
+  const size_t total = r->jobs_b + r->items_b + r->ptr_b + 256;
+  int rc = PC2_OK;
+  if (hipMalloc(&r->dev, total) != hipSuccess || hipHostMalloc(&r->host, total) != hipSuccess ||
+      hipEventCreateWithFlags(&r->copied, hipEventDisableTiming) != hipSuccess)
+    rc = PC2_E_NOMEM;
+  // scratch for the widest pair this runner may launch
+  if (!rc) {
+    int tiles = 0;
+    size_t words = 0;
+    int occ_max = 1;
+    const int L = (int)((max_nbits + 31) / 32);
+    const int Ls = L / 2 + 2;
+    for (int c = 0; c <= cls; ++c) {
+      const int pair = pc2k::batch_pair(c, c);
+      if (pair < 0) continue;
+      const int w = std::max(window_for(ctx, c, op), 6);
+      int t = 0;
+      size_t wd = 0;
+      pc2k::batch_slot_shape(op, c, w, Ls, &t, &wd);
+      tiles = std::max(tiles, t);
+      words = std::max(words, wd);
+    }
+    for (int pair = 0; pair < 8; ++pair) {
+      const void* k = pc2k::batch_kernel(op, pair);
+      if (!k) break;
+      int occ = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 64, 0) == hipSuccess)
+        occ_max = std::max(occ_max, occ);
+    }
+    r->grid_cap = ctx->cus * occ_max;
+    r->slot_words = (words + 3) & ~(size_t)3;
+    const size_t bytes = (size_t)r->grid_cap * tiles * r->slot_words * 4;
+    if (bytes && hipMalloc(&r->scratch, bytes) != hipSuccess) rc = PC2_E_NOMEM;
+  }
+  if (rc) {
+    if (r->dev) (void)hipFree(r->dev);
+    if (r->host) (void)hipHostFree(r->host);
+    if (r->scratch) (void)hipFree(r->scratch);
+    if (r->copied) (void)hipEventDestroy(r->copied);
+    delete r;
+    return rc;
+  }
+  *out = r;
+  return PC2_OK;
+}
+
+int pc2_runner_group_size(const pc2_pk* pk, int op_abi, uint32_t* elems) {
+  if (!pk || !elems || op_from_abi(op_abi) < 0) return PC2_E_INVAL;
+  *elems = (uint32_t)pc2k::elems_per_block(pk->cls);
+  return PC2_OK;
+}
+
+int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
+                      const size_t* ngroups, size_t njobs, void* hip_stream) {
+  if (!r || !r->ctx || !jobs || !first || !ngroups || njobs == 0) return PC2_E_INVAL;
+  if (njobs > r->max_jobs) return PC2_E_BUSY;
+  pc2_ctx* ctx = r->ctx;
+  const int op = r->op;
+  int ca = -1, cb = -1;
+  size_t nitems = 0, nptrs = 0;
+  for (size_t i = 0; i < njobs; ++i) {
+    const pc2_job& j = jobs[i];
+    if (op_from_abi(j.op) != op) return PC2_E_INVAL;
+    const pc2_pk* pk = (op == pc2k::OP_DEC) ? (j.sk ? &j.sk->pk : nullptr) : j.pk;
+    if (!pk || pk->ctx != ctx || !j.out || pk->cls > r->max_cls) return PC2_E_INVAL;
+    const size_t epw = (size_t)pc2k::elems_per_block(pk->cls);
+    if (first[i] + ngroups[i] > (j.count + epw - 1) / epw) return PC2_E_INVAL;
+    if (op == pc2k::OP_ENC && (!j.in0 || !j.in1 || j.m_limbs < 1 || (int)j.m_limbs > pk->L))
+      return PC2_E_INVAL;
+    if (op == pc2k::OP_DEC && !j.in0) return PC2_E_INVAL;
+    if (op == pc2k::OP_SUM) {
+      if (!j.inputs || j.K < 1 || j.K > (uint32_t)pc2k::RK_MAX) return PC2_E_INVAL;
+      for (uint32_t k = 0; k < j.K; ++k)
+        if (!j.inputs[k] || (j.lengths && j.lengths[k] > j.count)) return PC2_E_INVAL;
+      nptrs += 2 * (size_t)j.K;
+    }
+    nitems += ngroups[i];
+    const int c = pk->cls;
+    if (ca < 0 || ca == c) ca = c;
+    else if (cb < 0 || cb == c) cb = c;
+    else return PC2_E_UNSUPPORTED;
+  }
+  if (nitems == 0) return PC2_OK;
+  if (nitems > r->max_groups) return PC2_E_BUSY;
+  if (cb < 0) cb = ca;
+  const int pair = pc2k::batch_pair(ca, cb);
+  if (pair < 0) return PC2_E_UNSUPPORTED;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  // the previous launch's copies must have read the staging buffers
+  if (r->pending && hipEventSynchronize(r->copied) != hipSuccess) return PC2_E_DEVICE;
+  char* hb = (char*)r->host;
+  char* db = (char*)r->dev;
+  auto* hj = (pc2k::BatchJob*)hb;
+  auto* hi = (pc2k::BatchItem*)(hb + r->jobs_b);
+  auto* hp = (size_t*)(hb + r->jobs_b + r->items_b);
+  auto* dp = (size_t*)(db + r->jobs_b + r->items_b);
+  size_t pofs = 0, it = 0;
+  const int pa = pc2k::batch_pair_class(pair, 0), pb = pc2k::batch_pair_class(pair, 1);
+  for (size_t i = 0; i < njobs; ++i) {
+    const pc2_job& j = jobs[i];
+    const pc2_pk* pk = (op == pc2k::OP_DEC) ? &j.sk->pk : j.pk;
+    pc2k::BatchJob d{};
+    d.cls = pk->cls;
+    d.op = op;
+    d.m_limbs = (int)j.m_limbs;
+    d.K = (int)j.K;
+    d.pk = pk->c;
+    if (op == pc2k::OP_DEC) d.sk = j.sk->c;
+    d.in0 = j.in0;
+    d.in1 = j.in1;
+    d.out = j.out;
+    d.count = j.count;
+    if (op == pc2k::OP_SUM) {
+      for (uint32_t k = 0; k < j.K; ++k) hp[pofs + k] = (size_t)j.inputs[k];
+      for (uint32_t k = 0; k < j.K; ++k) hp[pofs + j.K + k] = j.lengths ? j.lengths[k] : j.count;
+      d.inputs = (const uint32_t* const*)(dp + pofs);
+      d.lengths = dp + pofs + j.K;
+      pofs += 2 * (size_t)j.K;
+    }
+    hj[i] = d;
+  }
+  // most expensive class first
+  for (int pass = 0; pass < 2; ++pass) {
+    const int want = pass == 0 ? std::max(pa, pb) : std::min(pa, pb);
+    if (pass == 1 && pa == pb) break;
+    for (size_t i = 0; i < njobs; ++i) {
+      if (hj[i].cls != want) continue;
+      for (size_t g = 0; g < ngroups[i]; ++g) hi[it++] = pc2k::BatchItem{(int)i, 0, first[i] + g};
+    }
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (hipMemcpyAsync(db, hb, njobs * sizeof(pc2k::BatchJob), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(db + r->jobs_b, hb + r->jobs_b, nitems * sizeof(pc2k::BatchItem),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      (pofs && hipMemcpyAsync(dp, hp, pofs * sizeof(size_t), hipMemcpyHostToDevice, st) !=
+                   hipSuccess) ||
+      hipEventRecord(r->copied, st) != hipSuccess)
+    return PC2_E_DEVICE;
+  r->pending = true;
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>(r->grid_cap, nitems));
+  const int w_a = window_for(ctx, pa, op), w_b = window_for(ctx, pb, op);
+  int* queue = (int*)(db + r->jobs_b + r->items_b + r->ptr_b);
+  return status_of(pc2k::launch_batch(op, pair, grid, (const pc2k::BatchJob*)db,
+                                      (const pc2k::BatchItem*)(db + r->jobs_b), (int)nitems,
+                                      queue, r->scratch, r->slot_words, w_a, w_b, ctx->err, st));
+}
+
+int pc2_runner_destroy(pc2_runner* r) {
+  if (!r || !r->ctx) return PC2_E_INVAL;
+  (void)hipSetDevice(r->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (r->dev) (void)hipFree(r->dev);
+  if (r->host) (void)hipHostFree(r->host);
+  if (r->scratch) (void)hipFree(r->scratch);
+  if (r->copied) (void)hipEventDestroy(r->copied);
+  delete r;
+  return PC2_OK;
 }
 
 }  // extern "C"

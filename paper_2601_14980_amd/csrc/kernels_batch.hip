@@ -1,0 +1,179 @@
+// Persistent batch kernels: one launch runs every job of a phase (all
+// encryptions, all aggregations or all decryptions of many edge nodes'
+// vectors of uneven lengths, under keys of up to two size classes).
+//
+// The grid is the device's resident capacity.  Each workgroup (one
+// wavefront) pulls work items -- one element group of one job -- from a
+// device queue with a single global atomic per item, runs the job's
+// per-group body for the job's key class, and exits when the queue is
+// drained, so every wavefront reaches the exit.  The host orders items from
+// the most to the least expensive so that the tail of the launch is made of
+// short items.  The queue counter is reset by a one-lane kernel launched
+// just before, so the pair can be captured in a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "launch.hpp"
+#include "paillier_ops.hpp"
+
+using namespace pc2ops;
+
+namespace {
+
+template <int OP, int C>
+struct OpShape {
+  using Gn = typename pc2k::Geos<C>::Gn;
+  using Gp = typename pc2k::Geos<C>::Gp;
+  static constexpr int EPW = 64 / Gn::T;
+  static constexpr int LDSW = (OP == pc2k::OP_DEC) ? 2 * EPW * Gp::SP : EPW * Gn::SP;
+  static constexpr int TILES = (OP == pc2k::OP_DEC) ? 2 * EPW : (OP == pc2k::OP_SUM ? 0 : EPW);
+};
+
+template <int OP, int C>
+__device__ __forceinline__ void run_item(const pc2k::BatchJob& job, size_t group,
+                                         uint32_t* lds_all, uint32_t* slots, size_t slot_words,
+                                         int w, int* err) {
+  using S = OpShape<OP, C>;
+  if constexpr (OP == pc2k::OP_ENC) {
+    enc_group<typename S::Gn>(job.pk, job.in0, job.m_limbs, job.in1, job.out, job.count, group,
+                              lds_all, slots, slot_words, w, err);
+  } else if constexpr (OP == pc2k::OP_DEC) {
+    dec_group<typename S::Gn, typename S::Gp>(job.sk, job.in0, job.out, job.count, group,
+                                              lds_all, slots, slot_words, w, err);
+  } else {
+    sum_group<typename S::Gn>(job.pk, job.inputs, job.lengths, job.K, job.out, job.count,
+                              group, lds_all, err);
+  }
+}
+
+__global__ void k_queue_reset(int* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+}
+
+template <int OP, int CA, int CB>
+__global__ __launch_bounds__(64, 2) void k_batch(const pc2k::BatchJob* __restrict__ jobs,
+                                                 const pc2k::BatchItem* __restrict__ items,
+                                                 int nitems, int* queue,
+                                                 uint32_t* __restrict__ scratch,
+                                                 size_t slot_words, int w_a, int w_b, int* err) {
+  using A = OpShape<OP, CA>;
+  using B = OpShape<OP, CB>;
+  constexpr int LDSW = A::LDSW > B::LDSW ? A::LDSW : B::LDSW;
+  constexpr int TILES = A::TILES > B::TILES ? A::TILES : B::TILES;
+  __shared__ __align__(16) uint32_t lds_all[LDSW];
+  __shared__ int s_item;
+  uint32_t* slots = scratch + (size_t)blockIdx.x * TILES * slot_words;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= nitems) break;
+    const pc2k::BatchItem item = items[it];
+    const pc2k::BatchJob& job = jobs[item.job];
+    if constexpr (CA == CB) {
+      run_item<OP, CA>(job, item.group, lds_all, slots, slot_words, w_a, err);
+    } else {
+      if (job.cls == CA)
+        run_item<OP, CA>(job, item.group, lds_all, slots, slot_words, w_a, err);
+      else
+        run_item<OP, CB>(job, item.group, lds_all, slots, slot_words, w_b, err);
+    }
+  }
+}
+
+// (CA, CB) pairs with a compiled batch kernel: single classes and the
+// 1024 + 2048-bit mix.
+constexpr int PAIRS[][2] = {{3, 3}, {5, 5}, {6, 6}, {7, 7}, {5, 6}};
+constexpr int NPAIRS = sizeof(PAIRS) / sizeof(PAIRS[0]);
+
+template <int OP, int P>
+const void* batch_ptr() {
+  return (const void*)&k_batch<OP, PAIRS[P][0], PAIRS[P][1]>;
+}
+
+template <int OP>
+const void* batch_kernel_op(int pair) {
+  switch (pair) {
+    case 0: return batch_ptr<OP, 0>();
+    case 1: return batch_ptr<OP, 1>();
+    case 2: return batch_ptr<OP, 2>();
+    case 3: return batch_ptr<OP, 3>();
+    case 4: return batch_ptr<OP, 4>();
+  }
+  return nullptr;
+}
+
+template <int OP, int C>
+void shape_of(int w, int Ls, int* tiles, size_t* words) {
+  using S = OpShape<OP, C>;
+  *tiles = S::TILES;
+  const size_t scal = (size_t)12 * Ls + 16;
+  if constexpr (OP == pc2k::OP_ENC)
+    *words = (size_t)S::Gn::CH << w;
+  else if constexpr (OP == pc2k::OP_DEC)
+    *words = std::max((size_t)S::Gp::CH << w, scal);
+  else
+    *words = 0;
+}
+
+template <int OP>
+void shape_cls(int cls, int w, int Ls, int* tiles, size_t* words) {
+  switch (cls) {
+    case 3: shape_of<OP, 3>(w, Ls, tiles, words); return;
+    case 5: shape_of<OP, 5>(w, Ls, tiles, words); return;
+    case 6: shape_of<OP, 6>(w, Ls, tiles, words); return;
+    case 7: shape_of<OP, 7>(w, Ls, tiles, words); return;
+  }
+  *tiles = 0;
+  *words = 0;
+}
+
+}  // namespace
+
+namespace pc2k {
+
+int batch_pair(int ca, int cb) {
+  if (ca > cb) std::swap(ca, cb);
+  for (int i = 0; i < NPAIRS; ++i)
+    if (PAIRS[i][0] == ca && PAIRS[i][1] == cb) return i;
+  return -1;
+}
+
+int batch_pair_class(int pair, int which) { return PAIRS[pair][which]; }
+
+const void* batch_kernel(int op, int pair) {
+  switch (op) {
+    case OP_ENC: return batch_kernel_op<OP_ENC>(pair);
+    case OP_DEC: return batch_kernel_op<OP_DEC>(pair);
+    case OP_SUM: return batch_kernel_op<OP_SUM>(pair);
+  }
+  return nullptr;
+}
+
+void batch_slot_shape(int op, int cls, int w, int Ls, int* tiles, size_t* words) {
+  switch (op) {
+    case OP_ENC: shape_cls<OP_ENC>(cls, w, Ls, tiles, words); return;
+    case OP_DEC: shape_cls<OP_DEC>(cls, w, Ls, tiles, words); return;
+    case OP_SUM: shape_cls<OP_SUM>(cls, w, Ls, tiles, words); return;
+  }
+  *tiles = 0;
+  *words = 0;
+}
+
+hipError_t launch_batch(int op, int pair, int grid, const BatchJob* jobs, const BatchItem* items,
+                        int nitems, int* queue, uint32_t* scratch, size_t slot_words, int w_a,
+                        int w_b, int* err, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const void* k = batch_kernel(op, pair);
+  if (!k) return hipErrorInvalidValue;
+  void* args[] = {(void*)&jobs, (void*)&items, (void*)&nitems, (void*)&queue,
+                  (void*)&scratch, (void*)&slot_words, (void*)&w_a, (void*)&w_b, (void*)&err};
+  return hipLaunchKernel(k, dim3(grid), dim3(64), args, 0, st);
+}
+
+}  // namespace pc2k

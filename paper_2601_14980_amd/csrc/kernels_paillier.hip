@@ -14,278 +14,50 @@
 // zeroed and the context's error word gets ERR_RANGE.
 #include <hip/hip_runtime.h>
 
-#include "bn_scalar.hpp"
-#include "engine.hpp"
-#include "mont_tile.hpp"
-#include "pc2_types.hpp"
 #include "launch.hpp"
+#include "paillier_ops.hpp"
 
 #include <algorithm>
 
-using namespace pc2d;
-using pc2k::HalfConst;
-using pc2k::ModConst;
-using pc2k::PkConst;
-using pc2k::PtrList;
-using pc2k::SkConst;
-
-namespace {
-
-// Lane 0 of a tile: the tile's LDS digits (value < 2N) -> canonical limbs of
-// the residue mod N, in place in LDS (nl + 1 words are used).
-template <class G>
-__device__ __forceinline__ void lds_canonical(uint32_t* lds, const ModConst& M) {
-  sc_digits_to_limbs<G::D>(lds, G::S, M.nl + 1);
-  if (sc_cmp(lds, M.nl + 1, M.Nl, M.nl) >= 0) sc_sub(lds, M.nl + 1, M.Nl, M.nl);
-}
-
-// Encryption of one element (Sec. III-B, f_en with g = n + 1):
-//   pre0:  MM(m, n R)      = m n  (exact: m n < n^2), + 1 -> g^m, kept in slot entry 0
-//   pre1:  MM(R^2, r)      = r R  (Montgomery form of r)
-//   pow:   (r R)^n         = r^n R
-//   post0: MM(g^m, r^n R)  = g^m r^n mod n^2   (normal form)
-// m and r are first converted to digits in slot entries 0 and 1.
-template <class G>
-__device__ __forceinline__ Program encrypt_program(const PkConst& pk, const uint32_t* me,
-                                                   int m_limbs, const uint32_t* re,
-                                                   uint32_t* slot, int tl) {
-  chunk_from_limbs<G>(slot, me, m_limbs, 0, tl);
-  chunk_from_limbs<G>(slot + G::CH, re, pk.L, 0, tl);
-  Program P = empty_program();
-  P.npre = 2;
-  P.pre0_a = op_chunk(slot);
-  P.pre0_b = op_chunk(pk.nR);
-  P.pre0_to_slot = true;
-  P.pre0_add1 = 1;
-  P.pre1_a = op_chunk(pk.n2.R2);
-  P.pre1_b = op_chunk(slot + G::CH);
-  P.e = pk.n;
-  P.elimbs = pk.L;
-  P.ebits = pk.nbits;
-  P.uniform_e = true;
-  P.one = pk.n2.R1;
-  P.npost = 1;
-  P.post0_a = op_chunk(slot);
-  P.post0_b = op_x();
-  return P;
-}
-
-// One CRT half of a decryption (Sec. III-C f_de through the split of Sec. IV):
-//   redc:  c R^-1 mod s^2      (Montgomery reduction of the 2L-limb ciphertext)
-//   pre1:  MM(R^3, c R^-1)     = c R
-//   pow:   (c R)^(s-1)         = c^(s-1) R
-//   post0: MM(., 1)            = c^(s-1) mod s^2
-template <class G>
-__device__ __forceinline__ Program decrypt_program(const HalfConst& H, int ebits,
-                                                   const uint32_t* ce, int L2, uint32_t* slot,
-                                                   int tl) {
-  chunk_from_limbs<G>(slot, ce, L2, 0, tl);
-  Program P = empty_program();
-  P.npre = 2;
-  P.redc = true;
-  P.redc_lo = slot;
-  P.redc_hi = ce;
-  P.redc_hi_n = L2;
-  P.pre1_a = op_chunk(H.s2.R3);
-  P.pre1_b = op_x();
-  P.e = H.e;
-  P.elimbs = H.Ls;
-  P.ebits = ebits;
-  P.uniform_e = false;
-  P.one = H.s2.R1;
-  P.npost = 1;
-  P.post0_a = op_x();
-  P.post0_b = op_chunk(H.s2.ONE);
-  return P;
-}
-
-// Lane 0 of a half-tile, after decrypt_program: y = c^(s-1) mod s^2 in LDS
-// digits -> m_s = L_s(y) h_s mod s into slot[4Ls+2 ..), flag at slot[5Ls+2].
-// L_s(y) = (y - 1)/s is an exact division: u = (y - 1) s^-1 mod 2^(32 Ls),
-// verified by u s == y - 1 (fails only for c not coprime to s).
-template <class Gp>
-__device__ __forceinline__ void decrypt_half_finish(const HalfConst& H, uint32_t* lds,
-                                                    uint32_t* slot, uint32_t cvalid) {
-  const int Ls = H.Ls, ny = H.s2.nl + 1;
-  uint32_t* y = lds;
-  lds_canonical<Gp>(lds, H.s2);
-  uint32_t one = 1u;
-  uint32_t bor = sc_sub(y, ny, &one, 1);
-  uint32_t* u = slot;                 // Ls
-  uint32_t* us = slot + Ls;           // 2 Ls
-  uint32_t* tmp = slot + 3 * Ls;      // Ls + 2
-  uint32_t* ms = slot + 4 * Ls + 2;   // Ls
-  uint32_t* flag = slot + 5 * Ls + 2;
-  sc_mullo(u, y, H.sinv, Ls);
-  sc_mul(us, u, Ls, H.s, Ls);
-  bool good = (bor == 0) && (sc_cmp(us, 2 * Ls, y, ny) == 0) && cvalid;
-  sc_montmul(ms, u, H.H, H.s, H.s_n0, Ls, tmp);
-  *flag = good ? 1u : 0u;
-}
-
-// Lane 0 of the p half-tile: CRT recombination m = m_q + q ((m_p - m_q) q^-1 mod p)
-// (Lemma 1 for the moduli p, q, in Garner's form) and the store of L limbs.
-__device__ __forceinline__ void garner_store(const SkConst& sk, const uint32_t* slot_p,
-                                             const uint32_t* slot_q, uint32_t* dst, bool live,
-                                             int* err, uint32_t* work) {
-  const int Ls = sk.h[0].Ls, L = sk.pk.L;
-  const uint32_t* mp = slot_p + 4 * Ls + 2;
-  const uint32_t* mq = slot_q + 4 * Ls + 2;
-  const bool good = slot_p[5 * Ls + 2] && slot_q[5 * Ls + 2];
-  uint32_t* d = work;                  // Ls
-  uint32_t* h = work + Ls;             // Ls
-  uint32_t* tmp = work + 2 * Ls;       // Ls + 2
-  uint32_t* prod = work + 3 * Ls + 2;  // 2 Ls
-  for (int i = 0; i < Ls; ++i) d[i] = mp[i];
-  // m_q < q < p, so one conditional addition of p reduces the difference
-  if (sc_sub(d, Ls, mq, Ls)) sc_add(d, Ls, sk.h[0].s, Ls);
-  sc_montmul(h, d, sk.QI, sk.h[0].s, sk.h[0].s_n0, Ls, tmp);
-  sc_mul(prod, sk.h[1].s, Ls, h, Ls);
-  sc_add(prod, 2 * Ls, mq, Ls);
-  if (live) {
-    for (int i = 0; i < L; ++i) dst[i] = (good && i < 2 * Ls) ? prod[i] : 0u;
-    if (!good) atomicOr(err, pc2k::ERR_RANGE);
-  }
-}
-
-// Lane 0 of a tile: canonical limbs of the tile's LDS value to dst (nl limbs),
-// zeros and the error latch if !ok.
-template <class G>
-__device__ __forceinline__ void store_canonical(uint32_t* lds, const ModConst& M, uint32_t* dst,
-                                                bool live, uint32_t ok, int* err) {
-  lds_canonical<G>(lds, M);
-  if (live) {
-    for (int i = 0; i < M.nl; ++i) dst[i] = ok ? lds[i] : 0u;
-    if (!ok) atomicOr(err, pc2k::ERR_RANGE);
-  }
-}
-
-__device__ __forceinline__ uint32_t encrypt_inputs_ok(const PkConst& pk, const uint32_t* me,
-                                                      int m_limbs, const uint32_t* re) {
-  const int L = pk.L;
-  return (sc_cmp(me, m_limbs, pk.n, L) < 0) && !sc_is_zero(re, L) && (sc_cmp(re, L, pk.n, L) < 0);
-}
-
-}  // namespace
+using namespace pc2ops;
 
 // ------------------------------------------------------------------ kernels
 template <class G>
 __global__ __launch_bounds__(64, 2) void k_encrypt(PkConst pk, const uint32_t* __restrict__ m,
-                                                int m_limbs, const uint32_t* __restrict__ r,
-                                                uint32_t* __restrict__ c, size_t count,
-                                                uint32_t* __restrict__ scratch, size_t slot_words,
-                                                int w, int* err) {
+                                                   int m_limbs, const uint32_t* __restrict__ r,
+                                                   uint32_t* __restrict__ c, size_t count,
+                                                   uint32_t* __restrict__ scratch,
+                                                   size_t slot_words, int w, int* err) {
   constexpr int EPW = 64 / G::T;
   __shared__ __align__(16) uint32_t lds_all[EPW * G::SP];
-  const int tl = threadIdx.x & (G::T - 1);
-  const int tile = threadIdx.x / G::T;
-  uint32_t* lds = lds_all + tile * G::SP;
-  uint32_t* slot = scratch + ((size_t)blockIdx.x * EPW + tile) * slot_words;
-  uint32_t N[G::K];
-  load_chunk<G>(N, pk.n2.N, tl);
-  const uint32_t np = pk.n2.nprime;
-  const int L = pk.L, L2 = 2 * pk.L;
+  uint32_t* slots = scratch + (size_t)blockIdx.x * EPW * slot_words;
   const size_t ngroups = (count + EPW - 1) / EPW;
-  for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
-    size_t e = gi * EPW + tile;
-    const bool live = e < count;
-    if (!live) e = count - 1;
-    const uint32_t* me = m + e * m_limbs;
-    const uint32_t* re = r + e * L;
-    uint32_t ok = 1;
-    if (tl == 0) ok = encrypt_inputs_ok(pk, me, m_limbs, re);
-    Program P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl);
-    uint32_t x[G::K];
-    run_program<G>(P, x, lds, slot, w, N, np, tl);
-    lds_sync();
-    to_lds<G>(lds, x, tl);
-    lds_sync();
-    if (tl == 0) store_canonical<G>(lds, pk.n2, c + e * L2, live, ok, err);
-  }
+  for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x)
+    enc_group<G>(pk, m, m_limbs, r, c, count, gi, lds_all, slots, slot_words, w, err);
 }
 
 template <class Gn, class Gp>
 __global__ __launch_bounds__(64, 2) void k_decrypt(SkConst sk, const uint32_t* __restrict__ c,
-                                                uint32_t* __restrict__ m, size_t count,
-                                                uint32_t* __restrict__ scratch, size_t slot_words,
-                                                int w, int* err) {
-  constexpr int TP = Gp::T, EPW = 64 / (2 * TP);
+                                                   uint32_t* __restrict__ m, size_t count,
+                                                   uint32_t* __restrict__ scratch,
+                                                   size_t slot_words, int w, int* err) {
+  constexpr int EPW = 64 / (2 * Gp::T);
   __shared__ __align__(16) uint32_t lds_all[2 * EPW * Gp::SP];
-  const int tl = threadIdx.x & (TP - 1);
-  const int ht = threadIdx.x / TP;  // half-tile index
-  const int half = ht & 1;
-  const int elem = ht >> 1;
-  uint32_t* lds = lds_all + ht * Gp::SP;
-  uint32_t* slot = scratch + ((size_t)blockIdx.x * 2 * EPW + ht) * slot_words;
-  const HalfConst H = half ? sk.h[1] : sk.h[0];
-  uint32_t N[Gp::K];
-  load_chunk<Gp>(N, H.s2.N, tl);
-  const uint32_t np = H.s2.nprime;
-  const int L = sk.pk.L, L2 = 2 * L;
+  uint32_t* slots = scratch + (size_t)blockIdx.x * 2 * EPW * slot_words;
   const size_t ngroups = (count + EPW - 1) / EPW;
-  for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
-    size_t e = gi * EPW + elem;
-    const bool live = e < count;
-    if (!live) e = count - 1;
-    const uint32_t* ce = c + e * L2;
-    uint32_t cv = 1;
-    if (tl == 0) cv = sc_cmp(ce, L2, sk.pk.n2.Nl, L2) < 0;
-    Program P = decrypt_program<Gp>(H, sk.ebits, ce, L2, slot, tl);
-    uint32_t x[Gp::K];
-    run_program<Gp>(P, x, lds, slot, w, N, np, tl);
-    lds_sync();
-    to_lds<Gp>(lds, x, tl);
-    lds_sync();
-    if (tl == 0) decrypt_half_finish<Gp>(H, lds, slot, cv);
-    lds_sync();
-    if (tl == 0 && half == 0)
-      garner_store(sk, slot, slot + slot_words, m + e * L, live, err, slot + 6 * H.Ls + 4);
-  }
+  for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x)
+    dec_group<Gn, Gp>(sk, c, m, count, gi, lds_all, slots, slot_words, w, err);
 }
 
-// out = prod_k c_k mod n^2.  acc_k = MM(c_k, acc_{k-1}) keeps a factor R^-(K-1),
-// removed by one product with R^K mod n^2.
 template <class G>
 __global__ __launch_bounds__(64, 2) void k_hom_sum(PkConst pk, PtrList cs, int K,
-                                                uint32_t* __restrict__ out, size_t count,
-                                                int* err) {
+                                                   uint32_t* __restrict__ out, size_t count,
+                                                   int* err) {
   constexpr int EPW = 64 / G::T;
   __shared__ __align__(16) uint32_t lds_all[EPW * G::SP];
-  const int tl = threadIdx.x & (G::T - 1);
-  const int tile = threadIdx.x / G::T;
-  uint32_t* lds = lds_all + tile * G::SP;
-  uint32_t N[G::K];
-  load_chunk<G>(N, pk.n2.N, tl);
-  const uint32_t np = pk.n2.nprime;
-  const int L2 = 2 * pk.L;
   const size_t ngroups = (count + EPW - 1) / EPW;
-  for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
-    size_t e = gi * EPW + tile;
-    const bool live = e < count;
-    if (!live) e = count - 1;
-    uint32_t ok = 1;
-    if (tl == 0)
-      for (int k = 0; k < K; ++k) ok &= sc_cmp(cs.p[k] + e * L2, L2, pk.n2.Nl, L2) < 0;
-    uint32_t acc[G::K];
-    lds_sync();
-    lds_digits_from_limbs<G>(lds, cs.p[0] + e * L2, L2, 0, tl);
-    lds_sync();
-    from_lds<G>(acc, lds, tl);
-    for (int k = 1; k <= K; ++k) {
-      lds_sync();
-      if (k < K)
-        lds_digits_from_limbs<G>(lds, cs.p[k] + e * L2, L2, 0, tl);
-      else
-        lds_from_chunk<G>(lds, pk.Rk + (size_t)K * G::CH, tl);
-      lds_sync();
-      // b = the incoming factor (in LDS), a = the running product (registers)
-      mont_mul<G>(acc, acc, lds, N, np, tl);
-    }
-    lds_sync();
-    to_lds<G>(lds, acc, tl);
-    lds_sync();
-    if (tl == 0) store_canonical<G>(lds, pk.n2, out + e * L2, live, ok, err);
-  }
+  for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x)
+    sum_group<G>(pk, cs.p, nullptr, K, out, count, gi, lds_all, err);
 }
 
 // out = c^k mod n^2 with a per-element 64-bit k (Definition 2):
@@ -424,23 +196,6 @@ __global__ __launch_bounds__(64, 2) void k_enc_sum_dec(SkConst sk, PtrList ms, P
 // ------------------------------------------------------------ host launchers
 namespace pc2k {
 
-template <int CLS>
-struct Geos;
-#define PC2_CLASS(I, nD, nK, nT, pD, pK, pT)   \
-  template <>                                   \
-  struct Geos<I> {                              \
-    using Gn = pc2d::Geo<nD, nK, nT>;           \
-    using Gp = pc2d::Geo<pD, pK, pT>;           \
-  };
-PC2_CLASS(0, 28, 2, 2, 28, 2, 1)
-PC2_CLASS(1, 28, 3, 2, 28, 3, 1)
-PC2_CLASS(2, 28, 5, 2, 28, 5, 1)
-PC2_CLASS(3, 28, 10, 2, 28, 10, 1)
-PC2_CLASS(4, 28, 19, 2, 28, 19, 1)
-PC2_CLASS(5, 28, 37, 2, 28, 37, 1)
-PC2_CLASS(6, 27, 38, 4, 28, 37, 2)
-PC2_CLASS(7, 27, 29, 8, 27, 29, 4)
-#undef PC2_CLASS
 
 #define PC2_DISPATCH(cls, EXPR)            \
   switch (cls) {                           \

@@ -23,6 +23,15 @@ hipError_t launch_scalar_mul(int cls, const Launch& l, const PkConst& pk, const 
 hipError_t launch_fused(int cls, const Launch& l, const SkConst& sk, const PtrList& ms,
                         const PtrList& rs, int K, int m_limbs, uint32_t* mout, size_t count);
 
+// persistent batch kernels (kernels_batch.hip)
+int batch_pair(int ca, int cb);
+int batch_pair_class(int pair, int which);
+const void* batch_kernel(int op, int pair);
+void batch_slot_shape(int op, int cls, int w, int Ls, int* tiles, size_t* words);
+hipError_t launch_batch(int op, int pair, int grid, const BatchJob* jobs, const BatchItem* items,
+                        int nitems, int* queue, uint32_t* scratch, size_t slot_words, int w_a,
+                        int w_b, int* err, void* stream);
+
 hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, const double* x,
                            uint64_t* m, size_t count);
 hipError_t launch_dequantize(const Launch& l, int log2_scale, uint64_t offset, const uint32_t* m,

@@ -57,6 +57,26 @@ struct PtrList {
   const uint32_t* p[RK_MAX];
 };
 
+// One job of a persistent batch launch (device copy).  All jobs of a launch
+// run the same operation; their key classes may differ.
+struct BatchJob {
+  int cls, op, m_limbs, K;
+  PkConst pk;                     // encrypt, hom_sum
+  SkConst sk;                     // decrypt
+  const uint32_t* in0;            // encrypt: m; decrypt: c
+  const uint32_t* in1;            // encrypt: r
+  uint32_t* out;
+  size_t count;                   // output elements
+  const uint32_t* const* inputs;  // hom_sum: K device pointers
+  const size_t* lengths;          // hom_sum: K input lengths (may be null)
+};
+// A work item: one wavefront's group of elements of one job.
+struct BatchItem {
+  int job;
+  int pad;
+  size_t group;
+};
+
 // Key size classes: index by ceil(log2) of the key.  n^2 and s^2 use
 // separate digit geometries (see mont_tile.hpp).
 constexpr int NUM_CLASSES = 8;

@@ -33,6 +33,9 @@ PC2_OPT_WINDOW = 1
 PC2_OPT_MODMUL = 2
 PC2_MODMUL_VALU = 0
 PC2_MODMUL_MFMA = 1
+PC2_OP_ENCRYPT = 1
+PC2_OP_HOM_SUM = 2
+PC2_OP_DECRYPT = 3
 
 EXPORTS = [
     "pc2_ctx_create", "pc2_ctx_destroy", "pc2_ctx_sync", "pc2_ctx_take_error",
@@ -40,6 +43,8 @@ EXPORTS = [
     "pc2_pk_create", "pc2_sk_create", "pc2_sk_public", "pc2_pk_destroy", "pc2_sk_destroy",
     "pc2_pk_info", "pc2_quantize", "pc2_dequantize", "pc2_encrypt", "pc2_decrypt",
     "pc2_hom_add", "pc2_hom_scalar_mul", "pc2_hom_sum", "pc2_enc_sum_dec",
+    "pc2_batch_create", "pc2_batch_run", "pc2_batch_destroy", "pc2_autotune",
+    "pc2_runner_create", "pc2_runner_group_size", "pc2_runner_launch", "pc2_runner_destroy",
 ]
 
 
@@ -51,6 +56,13 @@ class PC2Error(RuntimeError):
 
 class pc2_qparams(ctypes.Structure):
     _fields_ = [("log2_scale", c_int32), ("offset", c_uint64)]
+
+
+class pc2_job(ctypes.Structure):
+    _fields_ = [("op", c_int), ("pk", c_void_p), ("sk", c_void_p), ("in0", c_void_p),
+                ("in1", c_void_p), ("m_limbs", c_uint32), ("out", c_void_p),
+                ("count", c_size_t), ("K", c_uint32), ("inputs", c_void_p),
+                ("lengths", c_void_p)]
 
 
 def _load() -> ctypes.CDLL:
@@ -84,6 +96,15 @@ def _load() -> ctypes.CDLL:
         "pc2_hom_sum": (c_int, [P, POINTER(P), c_uint32, P, c_size_t, P]),
         "pc2_enc_sum_dec": (c_int, [P, POINTER(P), POINTER(P), c_uint32, c_uint32, P,
                                     c_size_t, P]),
+        "pc2_batch_create": (c_int, [P, POINTER(pc2_job), c_size_t, POINTER(P)]),
+        "pc2_batch_run": (c_int, [P, P]),
+        "pc2_batch_destroy": (c_int, [P]),
+        "pc2_autotune": (c_int, [P, P, POINTER(c_int), POINTER(c_int)]),
+        "pc2_runner_create": (c_int, [P, c_int, c_uint32, c_size_t, c_size_t, POINTER(P)]),
+        "pc2_runner_group_size": (c_int, [P, c_int, POINTER(c_uint32)]),
+        "pc2_runner_launch": (c_int, [P, POINTER(pc2_job), POINTER(c_size_t), POINTER(c_size_t),
+                                      c_size_t, P]),
+        "pc2_runner_destroy": (c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -316,6 +337,121 @@ def pc2_enc_sum_dec(sk: SecretKey, ms: Sequence[torch.Tensor], rs: Sequence[torc
     _check(lib.pc2_enc_sum_dec(sk.handle, mp, rp, len(ms), m_limbs,
                                _dev_ptr(m_out, torch.int32, "m_out"), count, _stream(stream)),
            "pc2_enc_sum_dec")
+
+
+# ------------------------------------------------------------------- batches
+def _make_jobs(jobs: Sequence[dict], keep: list):
+    """dicts (op, pk / sk, m, r, c, inputs, lengths, out) -> pc2_job array."""
+    arr = (pc2_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        op = j["op"]
+        d = arr[i]
+        d.op = op
+        out = j["out"]
+        d.out = _dev_ptr(out, torch.int32, "out")
+        d.count = out.shape[0]
+        if op == PC2_OP_ENCRYPT:
+            d.pk = j["pk"].handle
+            d.in0 = _dev_ptr(j["m"], torch.int32, "m")
+            d.in1 = _dev_ptr(j["r"], torch.int32, "r")
+            d.m_limbs = j["m"].shape[1]
+        elif op == PC2_OP_DECRYPT:
+            d.sk = j["sk"].handle
+            d.in0 = _dev_ptr(j["c"], torch.int32, "c")
+        elif op == PC2_OP_HOM_SUM:
+            d.pk = j["pk"].handle
+            ins = j["inputs"]
+            ptrs = (c_void_p * len(ins))(*[_dev_ptr(t, torch.int32, "input") for t in ins])
+            d.K = len(ins)
+            d.inputs = ctypes.cast(ptrs, c_void_p)
+            keep.append(ptrs)
+            if j.get("lengths") is not None:
+                lens = (c_size_t * len(ins))(*[int(v) for v in j["lengths"]])
+                d.lengths = ctypes.cast(lens, c_void_p)
+                keep.append(lens)
+        else:
+            raise ValueError(f"unknown op {op}")
+    return arr
+
+
+class Batch:
+    """A planned persistent launch over many jobs of one operation.
+
+    jobs: list of dicts with the fields of pc2_job -- op, pk / sk, m, r (encrypt),
+    c (decrypt), inputs and optional lengths (hom_sum), out -- with tensors for
+    the data arrays.  The tensors must outlive the batch.
+    """
+
+    def __init__(self, ctx: Context, jobs: Sequence[dict]):
+        self.ctx = ctx
+        self._keep: list = []
+        arr = _make_jobs(jobs, self._keep)
+        h = c_void_p()
+        _check(lib.pc2_batch_create(ctx.handle, arr, len(jobs), byref(h)), "pc2_batch_create")
+        self.handle = h
+
+    def run(self, stream=None) -> None:
+        """Run on a stream (torch's current one by default): the first run on a
+        non-null stream is captured in a HIP graph, later runs replay it.
+        stream=0 launches on the null stream without a graph."""
+        st = _stream(stream) if stream != 0 else None
+        _check(lib.pc2_batch_run(self.handle, st), "pc2_batch_run")
+
+    def close(self) -> None:
+        if self.handle:
+            lib.pc2_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Runner:
+    """Reusable persistent launcher (pc2_runner): one launch per call over
+    element-group ranges of several jobs."""
+
+    def __init__(self, ctx: Context, op: int, max_nbits: int, max_jobs: int, max_groups: int):
+        h = c_void_p()
+        _check(lib.pc2_runner_create(ctx.handle, op, max_nbits, max_jobs, max_groups, byref(h)),
+               "pc2_runner_create")
+        self.handle = h
+        self.ctx = ctx
+
+    def launch(self, jobs: Sequence[dict], first: Sequence[int], ngroups: Sequence[int],
+               stream=None) -> None:
+        keep: list = []
+        arr = _make_jobs(jobs, keep)
+        f = (c_size_t * len(jobs))(*first)
+        g = (c_size_t * len(jobs))(*ngroups)
+        _check(lib.pc2_runner_launch(self.handle, arr, f, g, len(jobs), _stream(stream)),
+               "pc2_runner_launch")
+
+    def close(self) -> None:
+        if self.handle:
+            lib.pc2_runner_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def runner_group_size(pk: PublicKey, op: int) -> int:
+    v = c_uint32()
+    _check(lib.pc2_runner_group_size(pk.handle, op, byref(v)), "pc2_runner_group_size")
+    return v.value
+
+
+def pc2_autotune(sk: SecretKey, stream=None) -> tuple[int, int]:
+    """Tune the exponentiation windows of this key's class; returns (w_enc, w_dec)."""
+    we, wd = c_int(), c_int()
+    _check(lib.pc2_autotune(sk.handle, _stream(stream), byref(we), byref(wd)), "pc2_autotune")
+    return we.value, wd.value
 
 
 # ---------------------------------------------------------------- marshalling

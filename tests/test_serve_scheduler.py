@@ -1,0 +1,135 @@
+"""The continuous-batching scheduler against a simulated executor on a virtual
+clock (CPU): every element group runs exactly once, the HBM budget is never
+exceeded, admission is first come first served, late short requests join
+running batches, and latency is accounted from arrival."""
+from __future__ import annotations
+
+import random
+
+import pytest
+
+from paper_2601_14980_amd.serve import OPS, Request, Scheduler, percentile
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor:
+    """Each op is one in-order stream; a tick of g groups takes g * cost[op]."""
+
+    GROUP = 16
+    COST = {"encrypt": 1.0e-3, "aggregate": 0.2e-3, "decrypt": 0.3e-3}
+
+    def __init__(self, clock, budget):
+        self.clock = clock
+        self.budget = budget
+        self.live: dict[int, int] = {}
+        self.coverage: dict[int, list[int]] = {}
+        self.ticks: list[tuple[str, list]] = []
+
+    def group_size(self, req):
+        return self.GROUP
+
+    def bytes_for(self, req):
+        return req.length * 100
+
+    def admit(self, req):
+        self.live[req.rid] = req.nbytes
+        assert sum(self.live.values()) <= self.budget
+        self.coverage[req.rid] = []
+
+    def launch(self, op, pieces):
+        groups = 0
+        for req, first, n in pieces:
+            self.coverage[req.rid].extend(range(first, first + n))
+            groups += n
+        self.ticks.append((op, [(r.rid, f, n) for r, f, n in pieces]))
+        return self.clock() + groups * self.COST[op]
+
+    def poll(self, handle):
+        return self.clock() >= handle - 1e-12
+
+    def release(self, req):
+        del self.live[req.rid]
+
+
+def run(requests, budget=10**9, tick=64, dt=1e-4):
+    clock = Clock()
+    ex = FakeExecutor(clock, budget)
+    sch = Scheduler(ex, budget, tick, clock=clock)
+
+    def idle():
+        clock.t += dt
+
+    makespan = sch.run_trace(requests, idle=idle, t0=0.0)
+    return sch, ex, makespan
+
+
+def trace(n, seed=0, rate=2000.0):
+    rng = random.Random(seed)
+    t, out = 0.0, []
+    for i in range(n):
+        t += rng.expovariate(rate)
+        op = rng.choice(OPS)
+        L = int(round(2 ** rng.uniform(8, 14)))
+        out.append(Request(rid=i, op=op, length=L, arrival=t,
+                           K=rng.randint(2, 8) if op == "aggregate" else 0))
+    return out
+
+
+def test_every_group_exactly_once_and_all_complete():
+    reqs = trace(120, seed=1)
+    sch, ex, _ = run(reqs)
+    assert len(sch.finished) == len(reqs)
+    for r in reqs:
+        groups = -(-r.length // FakeExecutor.GROUP)
+        assert sorted(ex.coverage[r.rid]) == list(range(groups))
+        assert r.completed >= r.arrival and r.latency >= 0
+
+
+def test_budget_and_fifo_admission():
+    reqs = trace(80, seed=2)
+    budget = 400_000
+    big = [r for r in reqs if r.length * 100 > budget]
+    sch, ex, _ = run(reqs, budget=budget)
+    assert sch.max_used <= budget
+    assert {r.rid for r in sch.rejected} == {r.rid for r in big}
+    admitted = sorted((r for r in reqs if r.admitted is not None), key=lambda r: r.admitted)
+    # first come, first served: admission order follows arrival order
+    order = [r.rid for r in sorted(admitted, key=lambda r: (r.admitted, r.arrival))]
+    assert order == sorted(order, key=lambda rid: reqs[rid].arrival)
+
+
+def test_late_short_request_joins_running_batches():
+    long = Request(rid=0, op="encrypt", length=16 * 1000, arrival=0.0)
+    short = Request(rid=1, op="encrypt", length=16 * 2, arrival=0.005)
+    sch, ex, _ = run([long, short], tick=64)
+    # the short request completes long before the long one
+    assert short.completed < long.completed
+    # some launch carries groups of both requests
+    assert any(len({rid for rid, _, _ in p}) == 2 for _, p in ex.ticks)
+
+
+def test_ops_overlap_on_separate_streams():
+    reqs = [Request(rid=i, op=op, length=16 * 50, arrival=0.0) for i, op in enumerate(OPS)]
+    sch, ex, makespan = run(reqs)
+    serial = sum(50 * FakeExecutor.COST[op] for op in OPS)
+    assert makespan < serial  # the three operations ran concurrently
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert percentile(v, 50) == 50
+    assert percentile(v, 99) == 99
+    assert percentile(v, 100) == 100
+    assert percentile([3.0], 99) == 3.0
+
+
+def test_bad_arguments():
+    with pytest.raises(ValueError):
+        Scheduler(FakeExecutor(Clock(), 1), 0, 4)

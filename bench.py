@@ -56,7 +56,8 @@ def montgomery_products_per_encrypt(nbits_n: int, n: int, window: int) -> tuple[
 
 
 def montgomery_products_per_decrypt(p: int, q: int, window: int) -> tuple[int, int]:
-    """Both CRT halves: REDC + R^3 product + table + powering + conversion."""
+    """Both CRT halves: REDC + R^3 product + table + powering (zero windows
+    skipped) + conversion."""
     w = window
     total_mm, total_prod = 0, 0
     for s in (p, q):
@@ -64,7 +65,7 @@ def montgomery_products_per_decrypt(p: int, q: int, window: int) -> tuple[int, i
         eb = max((p - 1).bit_length(), (q - 1).bit_length())
         nw = (eb + w - 1) // w
         digits = [(e >> (i * w)) & ((1 << w) - 1) for i in range(nw)]
-        mults = nw - 1  # exponents differ per half: every window multiplies
+        mults = sum(1 for d in digits[:-1] if d != 0)  # zero windows are skipped
         mm = 1 + 1 + ((1 << w) - 2) + w * (nw - 1) + mults + 1
         S = (s * s).bit_length() + 31 >> 5
         total_mm += mm
@@ -99,6 +100,270 @@ def cpu_baseline(p: int, q: int, ms, rs, cts, budget_s: float = 20.0) -> dict:
                       f"workload ({dt:.1f} s wall, multiprocessing pool of {cores})"}
 
 
+# ------------------------------------------------------- batching (config 3)
+BATCH_NODES = 16
+BATCH_SEED = 3
+
+
+def run_batching(pc2, gen, ctx, torch, np, args, reps: int = 3) -> dict:
+    """16 nodes, lengths log-uniform in [1024, 65536], even nodes under a
+    1024-bit key and odd nodes under a 2048-bit key.  Phases: encrypt every
+    node vector; per key group, multiply element j over the nodes whose
+    vector reaches j; decrypt both aggregates.  Batched: one persistent
+    graph-captured launch per phase.  Plain: one launch per call."""
+    lengths = gen.log_uniform_lengths(BATCH_SEED, BATCH_NODES, 1024, 65536)
+    keys = []
+    for bits in (1024, 2048):
+        p, q = gen.primes_for(BATCH_SEED, bits)
+        keys.append(pc2.SecretKey(ctx, bits, p, q))
+    xs = gen.normal_vectors(BATCH_SEED, lengths)
+    qp = gen.Q_PLAIN
+    nodes = []
+    for i, L in enumerate(lengths):
+        sk = keys[i % 2]
+        x = torch.from_numpy(xs[i]).cuda()
+        m = torch.empty(L, dtype=torch.int64, device="cuda")
+        pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, x, m)
+        r = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, L, sk.L, BATCH_SEED, extra=i))
+        c = torch.empty((L, 2 * sk.L), dtype=torch.int32, device="cuda")
+        nodes.append(dict(sk=sk, L=L, m=m.view(torch.int32).reshape(L, 2), r=r, c=c))
+    groups = []
+    for g, sk in enumerate(keys):
+        mem = [nd for i, nd in enumerate(nodes) if i % 2 == g]
+        maxlen = max(nd["L"] for nd in mem)
+        groups.append(dict(sk=sk, mem=mem, maxlen=maxlen,
+                           agg=torch.empty((maxlen, 2 * sk.L), dtype=torch.int32, device="cuda"),
+                           dec=torch.empty((maxlen, sk.L), dtype=torch.int32, device="cuda")))
+    if ctx.sync() != 0:
+        raise RuntimeError("quantize reported a range error")
+    enc_jobs = [dict(op=pc2.PC2_OP_ENCRYPT, pk=nd["sk"].public, m=nd["m"], r=nd["r"],
+                     out=nd["c"]) for nd in nodes]
+    sum_jobs = [dict(op=pc2.PC2_OP_HOM_SUM, pk=g["sk"].public, inputs=[nd["c"] for nd in g["mem"]],
+                     lengths=[nd["L"] for nd in g["mem"]], out=g["agg"]) for g in groups]
+    dec_jobs = [dict(op=pc2.PC2_OP_DECRYPT, sk=g["sk"], c=g["agg"], out=g["dec"]) for g in groups]
+    batches = [pc2.Batch(ctx, j) for j in (enc_jobs, sum_jobs, dec_jobs)]
+    side = torch.cuda.Stream()
+
+    def batched():
+        with torch.cuda.stream(side):
+            for b in batches:
+                b.run()
+        side.synchronize()
+
+    def plain():
+        for nd in nodes:
+            pc2.pc2_encrypt(nd["sk"].public, nd["m"], nd["r"], nd["c"])
+            ctx.sync()
+        for g in groups:
+            # ragged product as one call per run of equal membership
+            cuts = sorted({0} | {nd["L"] for nd in g["mem"]})
+            for a, b in zip(cuts[:-1], cuts[1:]):
+                ins = [nd["c"][a:b] for nd in g["mem"] if nd["L"] >= b]
+                pc2.pc2_hom_sum(g["sk"].public, ins, g["agg"][a:b])
+                ctx.sync()
+        for g in groups:
+            pc2.pc2_decrypt(g["sk"], g["agg"], g["dec"])
+            ctx.sync()
+
+    ops = sum(lengths) + sum(g["maxlen"] for g in groups)
+    batched()
+    plain()
+    tb, tp = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        batched()
+        tb.append(time.perf_counter() - t1)
+        dec_b = [g["dec"].clone() for g in groups]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain()
+        tp.append(time.perf_counter() - t1)
+        for g, d in zip(groups, dec_b):
+            if not torch.equal(g["dec"], d):
+                raise RuntimeError("batched and plain results differ")
+    if ctx.sync() != 0:
+        raise RuntimeError("device reported a data error")
+    # exact end-to-end check: decrypted aggregate = sum of quantized plaintexts reaching j
+    exact = True
+    for g in groups:
+        dec = pc2.from_device_limbs(g["dec"])
+        want = np.zeros(g["maxlen"], dtype=object)
+        for nd in g["mem"]:
+            mv = nd["m"].cpu().numpy().view(np.uint64).reshape(-1)
+            want[:nd["L"]] += mv.astype(object)
+        got = dec[:, 0].astype(object) + (dec[:, 1].astype(object) << 32)
+        exact &= bool(np.all(dec[:, 2:] == 0)) and bool(np.all(got == want))
+    for b in batches:
+        b.close()
+    mb, mp = float(np.median(tb)), float(np.median(tp))
+    log(f"batching: batched {mb * 1e3:.1f} ms, plain {mp * 1e3:.1f} ms per phase set")
+    return {"workload": "16 nodes, lengths log-uniform [1024, 65536] (sum %d), keys 1024/2048-bit "
+                        "alternating; encrypt all, ragged per-key aggregation, decrypt both"
+                        % sum(lengths),
+            "ops": ops, "batched_ops_per_s": round(ops / mb, 1),
+            "plain_ops_per_s": round(ops / mp, 1), "batched_over_plain": round(mp / mb, 3),
+            "batched_ms": round(mb * 1e3, 2), "plain_ms": round(mp * 1e3, 2),
+            "end_to_end_exact": exact}
+
+
+# -------------------------------------------------------- serving (config 5)
+SERVE_SEED = 5
+
+
+def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
+    """Poisson arrivals of encrypt / aggregate / decrypt requests (1/3 each),
+    lengths log-uniform in [256, 65536], the 2048-bit key resident, K ~ U{2..8}
+    resident ciphertext vectors per aggregate, admission by a 4 GiB budget.
+    Run at the configured 2000 req/s (overload: latency is queueing) and at
+    0.7x the capacity that run measured."""
+    from paper_2601_14980_amd.serve import GpuExecutor, Request, Scheduler, percentile
+    import random
+    L = sk.L
+    PL = 65536
+    rng = np.random.default_rng(gen.seed_seq(SERVE_SEED, gen.DATA))
+    xq = torch.from_numpy(rng.standard_normal(PL)).cuda()
+    qp = gen.Q_PLAIN
+    mpool = torch.empty(PL, dtype=torch.int64, device="cuda")
+    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, xq, mpool)
+    mpool2 = mpool.view(torch.int32).reshape(PL, 2)
+    rpool = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, PL, L, SERVE_SEED))
+    cpool = []
+    for k in range(8):
+        c = torch.empty((PL, 2 * L), dtype=torch.int32, device="cuda")
+        cpool.append(c)
+    pc2.pc2_encrypt(sk.public, mpool2, rpool, cpool[0])
+    for k in range(1, 8):  # distinct resident ciphertexts: powers of the first
+        kk = torch.full((PL,), k + 1, dtype=torch.int64, device="cuda")
+        pc2.pc2_hom_scalar_mul(sk.public, cpool[0], kk, cpool[k])
+    if ctx.sync() != 0:
+        raise RuntimeError("device reported a data error while warming the pool")
+
+    def make_trace(n, rate, seed):
+        r = random.Random(seed)
+        t, out = 0.0, []
+        for i in range(n):
+            t += r.expovariate(rate)
+            op = ("encrypt", "aggregate", "decrypt")[r.randrange(3)]
+            length = int(round(np.exp(r.uniform(np.log(256), np.log(65536)))))
+            req = Request(rid=i, op=op, length=length, arrival=t)
+            if op == "encrypt":
+                req.payload = dict(m=mpool2[:length], r=rpool[:length])
+            elif op == "aggregate":
+                req.K = r.randint(2, 8)
+                req.payload = dict(inputs=[cpool[j] for j in r.sample(range(8), req.K)])
+            else:
+                req.payload = dict(c=cpool[r.randrange(8)][:length])
+            out.append(req)
+        return out
+
+    ex = GpuExecutor(ctx, sk, max_groups=1 << 16, max_jobs=1024)
+    budget = 4 << 30
+
+    def serve(reqs):
+        sch = Scheduler(ex, hbm_budget=budget, tick_groups=4096)
+        span = sch.run_trace(reqs)
+        torch.cuda.synchronize()
+        lat = [r.latency for r in sch.finished]
+        ed = sum(r.length for r in sch.finished if r.op in ("encrypt", "decrypt"))
+        return dict(requests=len(sch.finished), rejected=len(sch.rejected),
+                    rate_req_per_s=round(len(reqs) / max(reqs[-1].arrival - reqs[0].arrival
+                                                         + 1e-9, 1e-9), 1),
+                    p50_ms=round(1e3 * percentile(lat, 50), 2),
+                    p99_ms=round(1e3 * percentile(lat, 99), 2),
+                    makespan_s=round(span, 3), launches=sch.ticks,
+                    enc_dec_ops_per_s=round(ed / span, 1),
+                    max_hbm_bytes=sch.max_used)
+
+    n = args.serve_requests
+    hot = serve(make_trace(n, 2000.0, SERVE_SEED))
+    cap = hot["requests"] / hot["makespan_s"]
+    sub = serve(make_trace(n, 0.7 * cap, SERVE_SEED + 1))
+    if ctx.sync() != 0:
+        raise RuntimeError("device reported a data error while serving")
+    ex.close()
+    log(f"serving: offered 2000 req/s -> p50 {hot['p50_ms']} ms p99 {hot['p99_ms']} ms; "
+        f"at 0.7x capacity ({0.7 * cap:.0f} req/s) p50 {sub['p50_ms']} ms p99 {sub['p99_ms']} ms")
+    return {"workload": f"{n} requests per run, Poisson arrivals, encrypt/aggregate/decrypt 1/3 each, "
+                        "lengths log-uniform [256, 65536], 2048-bit key, HBM budget 4 GiB",
+            "configured_2000_req_s": hot, "sub_saturation_0p7_capacity": sub}
+
+
+# ------------------------------------------------------------- ADMM (config 4)
+ADMM_SEED = 4
+ADMM_BITS = 3072
+ADMM_M, ADMM_N, ADMM_K = 4096, 16384, 32
+
+
+def run_admm(pc2, gen, ctx, torch, np, args) -> dict:
+    """Distributed lasso, A 4096 x 16384 ~ N(0, 1/4096) split row-wise over 32
+    nodes, x* 1 %-sparse with N(0,1) nonzeros, noise 1e-3; rho = 1,
+    lambda = 0.1 ||A^T y||_inf.  Every iteration quantizes the 32 local
+    16384-dim updates, encrypts them under a 3072-bit key, aggregates them
+    homomorphically, decrypts and dequantizes the sum and applies the
+    consensus update, all on the device."""
+    from paper_2601_14980_amd.admm import EncryptedConsensusLasso
+    M, N, K = ADMM_M, ADMM_N, ADMM_K
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(gen.seed_seq(ADMM_SEED, gen.DATA))
+    A = rng.standard_normal((M, N)) / 64.0          # N(0, 1/4096)
+    support = rng.choice(N, size=N // 100, replace=False)
+    xstar = np.zeros(N)
+    xstar[support] = rng.standard_normal(support.size)
+    y = A @ xstar + 1e-3 * rng.standard_normal(M)
+    lam = 0.1 * float(np.max(np.abs(A.T @ y)))
+    p, q = gen.primes_for(ADMM_SEED, ADMM_BITS)
+    sk = pc2.SecretKey(ctx, ADMM_BITS, p, q)
+    r_pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, K * N, sk.L, ADMM_SEED))
+    log(f"admm: inputs generated in {time.perf_counter() - t0:.1f}s")
+    qa = gen.Q_ADMM
+    Ad = torch.from_numpy(A).cuda()
+    yd = torch.from_numpy(y).cuda()
+    del A
+    drv = EncryptedConsensusLasso(ctx, sk, Ad, yd, K, 1.0, lam, qa.log2_scale, qa.offset, r_pool)
+    z = torch.zeros(N, dtype=torch.float64, device="cuda")
+    u = torch.zeros((K, N), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    times, enc_ms, dec_ms = [], [], []
+    for it in range(args.admm_warmup + args.admm_iters):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        drv.local(z, u)
+        pc2.pc2_quantize(ctx, qa.log2_scale, qa.offset, drv.xu.reshape(-1), drv.m)
+        ev[0].record(stream)
+        pc2.pc2_encrypt(sk.public, drv.m.view(torch.int32).reshape(K * N, 2), drv.r, drv.c)
+        ev[1].record(stream)
+        pc2.pc2_hom_sum(sk.public, drv.parts, drv.agg)
+        ev[2].record(stream)
+        pc2.pc2_decrypt(sk, drv.agg, drv.msum)
+        ev[3].record(stream)
+        pc2.pc2_dequantize(ctx, qa.log2_scale, qa.offset, drv.msum, K, drv.total)
+        drv.consensus(z, u)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        if it >= args.admm_warmup:
+            times.append(dt)
+            enc_ms.append(ev[0].elapsed_time(ev[1]))
+            dec_ms.append(ev[2].elapsed_time(ev[3]))
+        log(f"admm iteration {it + 1}: {dt * 1e3:.0f} ms")
+    if ctx.sync() != 0:
+        raise RuntimeError("device reported a data error in the ADMM loop")
+    zh = z.cpu().numpy()
+    drv.close()
+    mt = float(np.median(times))
+    return {"workload": "lasso A 4096x16384 ~ N(0,1/4096), 32 nodes x 128 rows, x* 1% sparse, "
+                        "noise 1e-3, rho 1, lambda 0.1 ||A^T y||_inf; 3072-bit key, scale 2^44, "
+                        "offset 2^51",
+            "modmul": "valu", "iterations_timed": len(times), "ms_per_iteration": round(mt * 1e3, 1),
+            "encrypt_ms": round(float(np.median(enc_ms)), 1),
+            "decrypt_ms": round(float(np.median(dec_ms)), 1),
+            "enc_dec_ops_per_s": round((K * N + N) / mt, 1),
+            "lambda": lam,
+            "mse_z_vs_xstar": float(np.mean((zh - xstar) ** 2)),
+            "nnz_z": int(np.count_nonzero(zh))}
+
+
 # --------------------------------------------------------------------- main
 def main() -> int:
     ap = argparse.ArgumentParser()
@@ -108,6 +373,12 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--window", type=int, default=0)
+    ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--no-admm", action="store_true")
+    ap.add_argument("--admm-iters", type=int, default=2)
+    ap.add_argument("--admm-warmup", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
@@ -238,6 +509,10 @@ def main() -> int:
         log("timing the oracle on the host cores")
         cpu = cpu_baseline(p, q, ms_s, rs_s, cts)
 
+    batching = None if args.no_batching else run_batching(pc2, gen, ctx, torch, np, args)
+    serving = None if args.no_serving else run_serving(pc2, gen, ctx, sk, torch, np, args)
+    admm = None if args.no_admm else run_admm(pc2, gen, ctx, torch, np, args)
+
     out = {
         "metric": "2048-bit Paillier enc+dec ops/sec, batched vs plain; serving p50/p99 latency",
         "value": round(value, 1),
@@ -272,6 +547,9 @@ def main() -> int:
                      "mm_per_encrypt": mm_enc,
                      "avg_launch_ms": round(enc_avg_s * 1e3, 3)},
         "cpu_baseline": cpu,
+        "batching": batching,
+        "serving": serving,
+        "admm": admm,
         "host": platform.node(),
     }
     print(json.dumps(out), flush=True)

@@ -229,6 +229,29 @@ int pc2_runner_launch(pc2_runner *runner, const pc2_job *jobs, const size_t *fir
                       const size_t *ngroups, size_t njobs, void *hip_stream);
 int pc2_runner_destroy(pc2_runner *runner);
 
+/* ------------------------------------------------ ADMM update (FP64 kernels)
+ *
+ * The consensus-lasso iteration around the encrypted aggregation: A (M x N,
+ * row-major doubles) is split by rows over K nodes of B = M/K rows; node k
+ * holds A_k, y_k and u_k (Sec. II's x/z/v updates with v = u/rho, in the
+ * global-consensus form of this row split).
+ *   pc2_admm_local:     w_k = A_k^T y_k + rho (z - u_k),
+ *                       x_k = (w_k - A_k^T W_k^-1 A_k w_k) / rho,  W_k = rho I + A_k A_k^T,
+ *                       xu_k = x_k + u_k (the vector each node quantizes and encrypts)
+ *   pc2_admm_consensus: z = S_{lambda/(rho K)}(sum / K) with S the soft threshold and
+ *                       sum = sum_k xu_k (the decrypted, dequantized aggregate);
+ *                       u_k += x_k - z
+ * A and y are device pointers owned by the caller (valid for the handle's
+ * life); z [N], u, x, xu [K][N] and sum [N] are device doubles. */
+typedef struct pc2_admm pc2_admm;
+int pc2_admm_create(pc2_ctx *ctx, const double *A, const double *y, uint32_t M, uint32_t N,
+                    uint32_t K, double rho, void *hip_stream, pc2_admm **out);
+int pc2_admm_local(pc2_admm *admm, const double *z, const double *u, double *x, double *xu,
+                   void *hip_stream);
+int pc2_admm_consensus(pc2_admm *admm, const double *sum, const double *x, double lambda,
+                       double *z, double *u, void *hip_stream);
+int pc2_admm_destroy(pc2_admm *admm);
+
 /* Autotuner: times the exponentiation window w in {4, 5, 6} for encryption
  * and decryption under this key's size class on a device-filling synthetic
  * sample, keeps the fastest in the context (used by later calls and

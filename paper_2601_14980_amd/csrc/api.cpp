@@ -33,12 +33,22 @@ struct pc2_runner {
   size_t max_jobs = 0, max_groups = 0, max_ptrs = 0;
   size_t slot_words = 0;
   int grid_cap = 0;
+  int ls = 0;            // largest prime (limbs) the decryption staging holds
   void* dev = nullptr;   // jobs | items | pointers | queue
   void* host = nullptr;  // pinned staging, same layout
   size_t jobs_b = 0, items_b = 0, ptr_b = 0;
   uint32_t* scratch = nullptr;
   hipEvent_t copied = nullptr;
   bool pending = false;
+};
+
+struct pc2_admm {
+  pc2_ctx* ctx = nullptr;
+  const double* A = nullptr;
+  int N = 0, B = 0, K = 0;
+  double rho = 1.0;
+  double* buf = nullptr;  // W (K B B) | aty (K N) | w (K N) | t (K B) | s (K B)
+  double *W = nullptr, *aty = nullptr, *w = nullptr, *t = nullptr, *s = nullptr;
 };
 
 struct pc2_batch {
@@ -269,9 +279,11 @@ int occupancy(pc2_ctx* ctx, int cls, int op) {
   return o;
 }
 
-// grid + scratch for a Paillier launch over `count` elements
+// grid + scratch for a Paillier launch over `count` elements.  The scratch
+// holds aux_words of per-call staging first (Launch::aux, at the same place
+// for every launch that asks for the same amount), then the tables.
 int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::Launch* l,
-            void* stream) {
+            void* stream, size_t aux_words = 0) {
   const int w = window_for(ctx, cls, op);
   const size_t epb = (size_t)pc2k::elems_per_block(cls);
   const size_t groups = (count + epb - 1) / epb;
@@ -285,7 +297,8 @@ int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::La
   pc2k::slot_shape(cls, op, w, Ls, L, &tiles, &words);
   words = (words + 3) & ~(size_t)3;
   l->slot_words = words;
-  const size_t need = (size_t)l->grid * tiles * words * 4;
+  const size_t aux = (aux_words + 63) & ~(size_t)63;
+  const size_t need = (aux + (size_t)l->grid * tiles * words) * 4;
   if (need > ctx->scratch_bytes) {
     // growing the scratch: wait for in-flight work that may use the old one
     if (hipDeviceSynchronize() != hipSuccess) return PC2_E_DEVICE;
@@ -295,11 +308,13 @@ int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::La
     if (hipMalloc(&ctx->scratch, need) != hipSuccess) return PC2_E_NOMEM;
     ctx->scratch_bytes = need;
   }
-  l->scratch = ctx->scratch;
+  l->aux = aux_words ? ctx->scratch : nullptr;
+  l->scratch = ctx->scratch + aux;
   return PC2_OK;
 }
 
 int status_of(hipError_t e) { return e == hipSuccess ? PC2_OK : PC2_E_DEVICE; }
+
 
 }  // namespace
 
@@ -461,6 +476,7 @@ int pc2_sk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* p_limbs, const u
   // the s^2 moduli must satisfy 4 s^2 < R for their digit geometry
   if (pc2h::bitlen(p2) + 2 > g.pD * g.pK * g.pT) return PC2_E_UNSUPPORTED;
   const int Ls = (int)pc2h::resized(p, p.size()).size();
+  if (Ls > pc2k::LS_MAX) return PC2_E_UNSUPPORTED;
   const int nl2 = (pc2h::bitlen(p2) + 31) / 32;
   DevBuf buf;
   PkOffsets po = add_public(buf, n, cls, L);
@@ -565,10 +581,22 @@ int pc2_decrypt(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count, 
   if (!sk || !sk->ctx) return PC2_E_INVAL;
   if (count == 0) return PC2_OK;
   if (!c || !m) return PC2_E_INVAL;
+  // the two CRT halves of up to DEC_CHUNK elements are staged between the
+  // per-prime phase and the recombination
+  const int Ls = sk->c.h[0].Ls;
+  const size_t chunk = std::min(count, pc2k::DEC_CHUNK);
   pc2k::Launch l{};
-  int rc = prepare(sk->ctx, sk->pk.cls, pc2k::OP_DEC, count, sk->c.h[0].Ls, sk->pk.L, &l, stream);
+  int rc = prepare(sk->ctx, sk->pk.cls, pc2k::OP_DEC, chunk, Ls, sk->pk.L, &l, stream,
+                   chunk * 2 * (size_t)(Ls + 1));
   if (rc) return rc;
-  return status_of(pc2k::launch_decrypt(sk->pk.cls, l, sk->c, c, m, count));
+  const size_t L2 = 2 * (size_t)sk->pk.L;
+  for (size_t b = 0; b < count; b += chunk) {
+    const size_t n = std::min(chunk, count - b);
+    rc = status_of(pc2k::launch_decrypt(sk->pk.cls, l, sk->c, c + b * L2, m + b * sk->pk.L, n,
+                                        l.aux));
+    if (rc) return rc;
+  }
+  return PC2_OK;
 }
 
 int pc2_hom_sum(const pc2_pk* pk, const uint32_t* const* c_k, uint32_t K, uint32_t* out,
@@ -626,12 +654,34 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
     ms.p[k] = m_k[k];
     rs.p[k] = r_k[k];
   }
-  pc2k::Launch l{};
-  int rc = prepare(sk->ctx, sk->pk.cls, pc2k::OP_FUSED, count, sk->c.h[0].Ls, sk->pk.L, &l,
-                   stream);
+  // per chunk: the products (2L limbs per element) then the CRT halves
+  pc2_ctx* ctx = sk->ctx;
+  const int Ls = sk->c.h[0].Ls, L = sk->pk.L, cls = sk->pk.cls;
+  const size_t chunk = std::min(count, pc2k::DEC_CHUNK);
+  const size_t prod_words = chunk * 2 * (size_t)L;
+  const size_t aux = prod_words + chunk * 2 * (size_t)(Ls + 1);
+  pc2k::Launch le{}, ld{};
+  int rc = prepare(ctx, cls, pc2k::OP_DEC, chunk, Ls, L, &ld, stream, aux);
+  if (!rc) rc = prepare(ctx, cls, pc2k::OP_FUSED, chunk, Ls, L, &le, stream, aux);
+  if (!rc && ld.aux != le.aux)  // the second call grew the scratch
+    rc = prepare(ctx, cls, pc2k::OP_DEC, chunk, Ls, L, &ld, stream, aux);
   if (rc) return rc;
-  return status_of(
-      pc2k::launch_fused(sk->pk.cls, l, sk->c, ms, rs, (int)K, (int)m_limbs, m_out, count));
+  uint32_t* prod = le.aux;
+  uint32_t* halves = le.aux + prod_words;
+  for (size_t b = 0; b < count; b += chunk) {
+    const size_t n = std::min(chunk, count - b);
+    pc2k::PtrList mb{}, rb{};
+    for (uint32_t k = 0; k < K; ++k) {
+      mb.p[k] = ms.p[k] + b * m_limbs;
+      rb.p[k] = rs.p[k] + b * (size_t)L;
+    }
+    rc = status_of(
+        pc2k::launch_enc_prod(cls, le, sk->pk.c, mb, rb, (int)K, (int)m_limbs, prod, n));
+    if (!rc)
+      rc = status_of(pc2k::launch_decrypt(cls, ld, sk->c, prod, m_out + b * L, n, halves));
+    if (rc) return rc;
+  }
+  return PC2_OK;
 }
 
 // ---------------------------------------------------------------- batches
@@ -923,7 +973,8 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
     size_t words = 0;
     int occ_max = 1;
     const int L = (int)((max_nbits + 31) / 32);
-    const int Ls = L / 2 + 2;
+    const int Ls = std::min(L / 2 + 2, pc2k::LS_MAX);
+    r->ls = Ls;
     for (int c = 0; c <= cls; ++c) {
       const int pair = pc2k::batch_pair(c, c);
       if (pair < 0) continue;
@@ -981,7 +1032,7 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     if (first[i] + ngroups[i] > (j.count + epw - 1) / epw) return PC2_E_INVAL;
     if (op == pc2k::OP_ENC && (!j.in0 || !j.in1 || j.m_limbs < 1 || (int)j.m_limbs > pk->L))
       return PC2_E_INVAL;
-    if (op == pc2k::OP_DEC && !j.in0) return PC2_E_INVAL;
+    if (op == pc2k::OP_DEC && (!j.in0 || j.sk->c.h[0].Ls > r->ls)) return PC2_E_INVAL;
     if (op == pc2k::OP_SUM) {
       if (!j.inputs || j.K < 1 || j.K > (uint32_t)pc2k::RK_MAX) return PC2_E_INVAL;
       for (uint32_t k = 0; k < j.K; ++k)
@@ -1045,19 +1096,19 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
   hipStream_t st = (hipStream_t)hip_stream;
   if (hipMemcpyAsync(db, hb, njobs * sizeof(pc2k::BatchJob), hipMemcpyHostToDevice, st) !=
           hipSuccess ||
-      hipMemcpyAsync(db + r->jobs_b, hb + r->jobs_b, nitems * sizeof(pc2k::BatchItem),
+      hipMemcpyAsync(db + r->jobs_b, hb + r->jobs_b, it * sizeof(pc2k::BatchItem),
                      hipMemcpyHostToDevice, st) != hipSuccess ||
       (pofs && hipMemcpyAsync(dp, hp, pofs * sizeof(size_t), hipMemcpyHostToDevice, st) !=
                    hipSuccess) ||
       hipEventRecord(r->copied, st) != hipSuccess)
     return PC2_E_DEVICE;
   r->pending = true;
-  const int grid = (int)std::max<size_t>(1, std::min<size_t>(r->grid_cap, nitems));
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>(r->grid_cap, it));
   const int w_a = window_for(ctx, pa, op), w_b = window_for(ctx, pb, op);
   int* queue = (int*)(db + r->jobs_b + r->items_b + r->ptr_b);
   return status_of(pc2k::launch_batch(op, pair, grid, (const pc2k::BatchJob*)db,
-                                      (const pc2k::BatchItem*)(db + r->jobs_b), (int)nitems,
-                                      queue, r->scratch, r->slot_words, w_a, w_b, ctx->err, st));
+                                      (const pc2k::BatchItem*)(db + r->jobs_b), (int)it, queue,
+                                      r->scratch, r->slot_words, w_a, w_b, ctx->err, st));
 }
 
 int pc2_runner_destroy(pc2_runner* r) {
@@ -1069,6 +1120,68 @@ int pc2_runner_destroy(pc2_runner* r) {
   if (r->scratch) (void)hipFree(r->scratch);
   if (r->copied) (void)hipEventDestroy(r->copied);
   delete r;
+  return PC2_OK;
+}
+
+// ------------------------------------------------------------------ ADMM
+int pc2_admm_create(pc2_ctx* ctx, const double* A, const double* y, uint32_t M, uint32_t N,
+                    uint32_t K, double rho, void* hip_stream, pc2_admm** out) {
+  if (!ctx || !A || !y || !out || M == 0 || N == 0 || K == 0 || M % K != 0 || !(rho > 0.0))
+    return PC2_E_INVAL;
+  *out = nullptr;
+  const size_t B = M / K;
+  if (B > 4096) return PC2_E_UNSUPPORTED;  // the per-node solve keeps B doubles in LDS
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  pc2_admm* a = new (std::nothrow) pc2_admm();
+  if (!a) return PC2_E_NOMEM;
+  const size_t words = K * B * B + 2 * (size_t)K * N + 2 * (size_t)K * B;
+  if (hipMalloc(&a->buf, words * sizeof(double)) != hipSuccess) {
+    delete a;
+    return PC2_E_NOMEM;
+  }
+  a->ctx = ctx;
+  a->A = A;
+  a->N = (int)N;
+  a->B = (int)B;
+  a->K = (int)K;
+  a->rho = rho;
+  a->W = a->buf;
+  a->aty = a->W + K * B * B;
+  a->w = a->aty + (size_t)K * N;
+  a->t = a->w + (size_t)K * N;
+  a->s = a->t + (size_t)K * B;
+  if (pc2k::admm_setup(A, y, (int)N, (int)B, (int)K, rho, a->W, a->aty, hip_stream) !=
+      hipSuccess) {
+    (void)hipFree(a->buf);
+    delete a;
+    return PC2_E_DEVICE;
+  }
+  *out = a;
+  return PC2_OK;
+}
+
+int pc2_admm_local(pc2_admm* a, const double* z, const double* u, double* x, double* xu,
+                   void* hip_stream) {
+  if (!a || !z || !u || !x || !xu) return PC2_E_INVAL;
+  if (hipSetDevice(a->ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  return status_of(pc2k::admm_local(a->A, a->W, a->aty, z, u, a->N, a->B, a->K, a->rho, a->w,
+                                    a->t, a->s, x, xu, hip_stream));
+}
+
+int pc2_admm_consensus(pc2_admm* a, const double* sum, const double* x, double lambda, double* z,
+                       double* u, void* hip_stream) {
+  if (!a || !sum || !x || !z || !u || !(lambda >= 0.0)) return PC2_E_INVAL;
+  if (hipSetDevice(a->ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  const double kappa = lambda / (a->rho * a->K);
+  return status_of(pc2k::admm_consensus(sum, x, a->N, a->K, kappa, z, u, hip_stream));
+}
+
+int pc2_admm_destroy(pc2_admm* a) {
+  if (!a || !a->ctx) return PC2_E_INVAL;
+  (void)hipSetDevice(a->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (a->buf) (void)hipFree(a->buf);
+  delete a;
   return PC2_OK;
 }
 

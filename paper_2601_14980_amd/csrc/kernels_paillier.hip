@@ -36,17 +36,33 @@ __global__ __launch_bounds__(64, 2) void k_encrypt(PkConst pk, const uint32_t* _
     enc_group<G>(pk, m, m_limbs, r, c, count, gi, lds_all, slots, slot_words, w, err);
 }
 
-template <class Gn, class Gp>
-__global__ __launch_bounds__(64, 2) void k_decrypt(SkConst sk, const uint32_t* __restrict__ c,
-                                                   uint32_t* __restrict__ m, size_t count,
-                                                   uint32_t* __restrict__ scratch,
-                                                   size_t slot_words, int w, int* err) {
-  constexpr int EPW = 64 / (2 * Gp::T);
-  __shared__ __align__(16) uint32_t lds_all[2 * EPW * Gp::SP];
-  uint32_t* slots = scratch + (size_t)blockIdx.x * 2 * EPW * slot_words;
-  const size_t ngroups = (count + EPW - 1) / EPW;
-  for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x)
-    dec_group<Gn, Gp>(sk, c, m, count, gi, lds_all, slots, slot_words, w, err);
+// Decryption, phase 1: work item w covers element group w / 2 for prime
+// w % 2, so every wavefront works on one prime.
+template <class Gp>
+__global__ __launch_bounds__(64, 2) void k_decrypt_half(SkConst sk, const uint32_t* __restrict__ c,
+                                                        size_t count,
+                                                        uint32_t* __restrict__ scratch,
+                                                        size_t slot_words, int w,
+                                                        uint32_t* __restrict__ halves) {
+  constexpr int EPW = 64 / Gp::T;
+  __shared__ __align__(16) uint32_t lds_all[EPW * Gp::SP];
+  uint32_t* slots = scratch + (size_t)blockIdx.x * EPW * slot_words;
+  const size_t nitems = 2 * ((count + EPW - 1) / EPW);
+  const size_t stride = (size_t)EPW * 2 * (sk.h[0].Ls + 1);
+  for (size_t it = blockIdx.x; it < nitems; it += gridDim.x)
+    dec_half_group<Gp>(sk, (int)(it & 1), c, count, it >> 1, lds_all, slots, slot_words, w,
+                       halves + (it >> 1) * stride);
+}
+
+// Decryption, phase 2: CRT recombination, one lane per element.
+__global__ __launch_bounds__(64) void k_garner(SkConst sk, const uint32_t* __restrict__ halves,
+                                               uint32_t* __restrict__ m, size_t count, int* err) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int Ls = sk.h[0].Ls;
+  uint32_t work[5 * pc2k::LS_MAX + 2];
+  const uint32_t* hp = halves + e * 2 * (size_t)(Ls + 1);
+  garner_elem(sk, hp, hp + Ls + 1, m + e * sk.pk.L, err, work);
 }
 
 template <class G>
@@ -108,88 +124,60 @@ __global__ __launch_bounds__(64, 2) void k_scalar_mul(PkConst pk, const uint32_t
   }
 }
 
-// m_out[j] = Dec(prod_k Enc(m_k[j], r_k[j])): the K ciphertexts and their
-// product never reach the output; the running product lives in the element's
-// scratch slot.
-template <class Gn, class Gp>
-__global__ __launch_bounds__(64, 2) void k_enc_sum_dec(SkConst sk, PtrList ms, PtrList rs, int K,
-                                                    int m_limbs, uint32_t* __restrict__ mout,
+// prod[j] = prod_k Enc(m_k[j], r_k[j]) mod n^2, the first phase of the fused
+// encrypt -> aggregate -> decrypt path: the K ciphertexts never leave the
+// element's scratch slot, and the product goes to the caller's staging area,
+// from which the two decryption phases produce m_out.
+template <class G>
+__global__ __launch_bounds__(64, 2) void k_enc_prod(PkConst pk, PtrList ms, PtrList rs, int K,
+                                                    int m_limbs, uint32_t* __restrict__ prod,
                                                     size_t count, uint32_t* __restrict__ scratch,
                                                     size_t slot_words, int w, int* err) {
-  static_assert(Gn::T == 2 * Gp::T, "element tile = two half tiles");
-  constexpr int EPW = 64 / Gn::T;
-  constexpr int LDSW = (Gn::SP > 2 * Gp::SP) ? Gn::SP : 2 * Gp::SP;
-  __shared__ __align__(16) uint32_t lds_all[EPW * LDSW];
-  const int tn = threadIdx.x & (Gn::T - 1);
-  const int tile = threadIdx.x / Gn::T;
-  const int tp = threadIdx.x & (Gp::T - 1);
-  const int half = (threadIdx.x / Gp::T) & 1;
-  uint32_t* lds_n = lds_all + tile * LDSW;
-  uint32_t* lds_h = lds_n + half * Gp::SP;
-  // per element: the n^2 slot (table, then ciphertext limbs), the running
-  // product, then the two half-tile slots
-  uint32_t* slot_n = scratch + ((size_t)blockIdx.x * EPW + tile) * 4 * slot_words;
-  uint32_t* slot_acc = slot_n + slot_words;
-  uint32_t* slot_h = slot_n + (2 + half) * slot_words;
-  const PkConst& pk = sk.pk;
+  constexpr int EPW = 64 / G::T;
+  __shared__ __align__(16) uint32_t lds_all[EPW * G::SP];
+  const int tl = threadIdx.x & (G::T - 1);
+  const int tile = threadIdx.x / G::T;
+  uint32_t* lds = lds_all + tile * G::SP;
+  // per element: the table slot, then the running product
+  uint32_t* slot = scratch + ((size_t)blockIdx.x * EPW + tile) * 2 * slot_words;
+  uint32_t* slot_acc = slot + slot_words;
   const int L = pk.L, L2 = 2 * L;
-  const HalfConst H = half ? sk.h[1] : sk.h[0];
+  uint32_t N[G::K];
+  load_chunk<G>(N, pk.n2.N, tl);
+  const uint32_t np = pk.n2.nprime;
   const size_t ngroups = (count + EPW - 1) / EPW;
   for (size_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
     size_t e = gi * EPW + tile;
     const bool live = e < count;
     if (!live) e = count - 1;
     uint32_t okall = 1;
-    {
-      uint32_t N[Gn::K];
-      load_chunk<Gn>(N, pk.n2.N, tn);
-      const uint32_t np = pk.n2.nprime;
-      uint32_t x[Gn::K];
-      // k = 0..K-1: encrypt and fold into the running product; k = K: remove R^-(K-1)
-      for (int k = 0; k <= K; ++k) {
-        Program P;
-        if (k < K) {
-          const uint32_t* me = ms.p[k] + e * m_limbs;
-          const uint32_t* re = rs.p[k] + e * L;
-          if (tn == 0) okall &= encrypt_inputs_ok(pk, me, m_limbs, re);
-          P = encrypt_program<Gn>(pk, me, m_limbs, re, slot_n, tn);
-          if (k > 0) {
-            P.npost = 2;
-            P.post1_a = op_x();
-            P.post1_b = op_chunk(slot_acc);
-          }
-        } else {
-          P = empty_program();
-          P.npre = 1;
-          P.pre0_a = op_chunk(pk.Rk + (size_t)K * Gn::CH);
-          P.pre0_b = op_chunk(slot_acc);
+    uint32_t x[G::K];
+    // k = 0..K-1: encrypt and fold into the running product; k = K: remove R^-(K-1)
+    for (int k = 0; k <= K; ++k) {
+      Program P;
+      if (k < K) {
+        const uint32_t* me = ms.p[k] + e * m_limbs;
+        const uint32_t* re = rs.p[k] + e * L;
+        if (tl == 0) okall &= encrypt_inputs_ok(pk, me, m_limbs, re);
+        P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl);
+        if (k > 0) {
+          P.npost = 2;
+          P.post1_a = op_x();
+          P.post1_b = op_chunk(slot_acc);
         }
-        run_program<Gn>(P, x, lds_n, slot_n, w, N, np, tn);
-        if (k < K) store_chunk<Gn>(slot_acc, x, tn);
+      } else {
+        P = empty_program();
+        P.npre = 1;
+        P.pre0_a = op_chunk(pk.Rk + (size_t)K * G::CH);
+        P.pre0_b = op_chunk(slot_acc);
       }
-      lds_sync();
-      to_lds<Gn>(lds_n, x, tn);
-      lds_sync();
-      if (tn == 0) {
-        lds_canonical<Gn>(lds_n, pk.n2);
-        for (int i = 0; i < L2; ++i) slot_acc[i] = lds_n[i];
-      }
+      run_program<G>(P, x, lds, slot, w, N, np, tl);
+      if (k < K) store_chunk<G>(slot_acc, x, tl);
     }
-    okall = tile_bcast0<Gn::T>(okall);
     lds_sync();
-    uint32_t N[Gp::K];
-    load_chunk<Gp>(N, H.s2.N, tp);
-    const uint32_t np = H.s2.nprime;
-    Program P = decrypt_program<Gp>(H, sk.ebits, slot_acc, L2, slot_h, tp);
-    uint32_t x[Gp::K];
-    run_program<Gp>(P, x, lds_h, slot_h, w, N, np, tp);
+    to_lds<G>(lds, x, tl);
     lds_sync();
-    to_lds<Gp>(lds_h, x, tp);
-    lds_sync();
-    if (tp == 0) decrypt_half_finish<Gp>(H, lds_h, slot_h, okall);
-    lds_sync();
-    if (tp == 0 && half == 0)
-      garner_store(sk, slot_h, slot_h + slot_words, mout + e * L, live, err, slot_n);
+    if (tl == 0) store_canonical<G>(lds, pk.n2, prod + e * L2, live, okall, err);
   }
 }
 
@@ -215,10 +203,10 @@ static const void* kernel_ptr(int op) {
   using Gp = typename Geos<C>::Gp;
   switch (op) {
     case OP_ENC: return (const void*)&k_encrypt<Gn>;
-    case OP_DEC: return (const void*)&k_decrypt<Gn, Gp>;
+    case OP_DEC: return (const void*)&k_decrypt_half<Gp>;
     case OP_SUM: return (const void*)&k_hom_sum<Gn>;
     case OP_SMUL: return (const void*)&k_scalar_mul<Gn>;
-    case OP_FUSED: return (const void*)&k_enc_sum_dec<Gn, Gp>;
+    case OP_FUSED: return (const void*)&k_enc_prod<Gn>;
   }
   return nullptr;
 }
@@ -242,13 +230,12 @@ static void slot_shape_t(int op, int w, int Ls, int L, int* tiles, size_t* words
       *words = (size_t)Gn::CH << w;
       break;
     case OP_DEC:
-      *tiles = 2 * epw;
+      *tiles = 64 / Gp::T;
       *words = std::max((size_t)Gp::CH << w, scal);
       break;
     case OP_FUSED:
-      *tiles = 4 * epw;
-      *words = std::max(std::max((size_t)Gn::CH << w, (size_t)Gp::CH << w),
-                        std::max(scal, (size_t)2 * L + 4 + 5 * Ls + 8));
+      *tiles = 2 * epw;
+      *words = (size_t)Gn::CH << w;
       break;
     default:
       *tiles = 0;
@@ -283,15 +270,20 @@ hipError_t launch_encrypt(int cls, const Launch& l, const PkConst& pk, const uin
 
 template <int C>
 static hipError_t dec_t(const Launch& l, const SkConst& sk, const uint32_t* c, uint32_t* m,
-                        size_t count) {
-  hipLaunchKernelGGL((k_decrypt<typename Geos<C>::Gn, typename Geos<C>::Gp>), dim3(l.grid),
-                     dim3(64), 0, (hipStream_t)l.stream, sk, c, m, count, l.scratch,
-                     l.slot_words, l.window, l.err);
+                        size_t count, uint32_t* halves) {
+  if (sk.h[0].Ls > LS_MAX || halves == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_decrypt_half<typename Geos<C>::Gp>), dim3(l.grid), dim3(64), 0,
+                     (hipStream_t)l.stream, sk, c, count, l.scratch, l.slot_words, l.window,
+                     halves);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_garner, dim3((unsigned)((count + 63) / 64)), dim3(64), 0,
+                     (hipStream_t)l.stream, sk, halves, m, count, l.err);
   return hipGetLastError();
 }
 hipError_t launch_decrypt(int cls, const Launch& l, const SkConst& sk, const uint32_t* c,
-                          uint32_t* m, size_t count) {
-  PC2_DISPATCH(cls, return dec_t<C>(l, sk, c, m, count));
+                          uint32_t* m, size_t count, uint32_t* halves) {
+  PC2_DISPATCH(cls, return dec_t<C>(l, sk, c, m, count, halves));
   return hipErrorInvalidValue;
 }
 
@@ -323,16 +315,16 @@ hipError_t launch_scalar_mul(int cls, const Launch& l, const PkConst& pk, const 
 }
 
 template <int C>
-static hipError_t fused_t(const Launch& l, const SkConst& sk, const PtrList& ms,
-                          const PtrList& rs, int K, int m_limbs, uint32_t* mout, size_t count) {
-  hipLaunchKernelGGL((k_enc_sum_dec<typename Geos<C>::Gn, typename Geos<C>::Gp>), dim3(l.grid),
-                     dim3(64), 0, (hipStream_t)l.stream, sk, ms, rs, K, m_limbs, mout, count,
-                     l.scratch, l.slot_words, l.window, l.err);
+static hipError_t fused_t(const Launch& l, const PkConst& pk, const PtrList& ms,
+                          const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count) {
+  hipLaunchKernelGGL((k_enc_prod<typename Geos<C>::Gn>), dim3(l.grid), dim3(64), 0,
+                     (hipStream_t)l.stream, pk, ms, rs, K, m_limbs, prod, count, l.scratch,
+                     l.slot_words, l.window, l.err);
   return hipGetLastError();
 }
-hipError_t launch_fused(int cls, const Launch& l, const SkConst& sk, const PtrList& ms,
-                        const PtrList& rs, int K, int m_limbs, uint32_t* mout, size_t count) {
-  PC2_DISPATCH(cls, return fused_t<C>(l, sk, ms, rs, K, m_limbs, mout, count));
+hipError_t launch_enc_prod(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
+                           const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count) {
+  PC2_DISPATCH(cls, return fused_t<C>(l, pk, ms, rs, K, m_limbs, prod, count));
   return hipErrorInvalidValue;
 }
 

@@ -10,18 +10,22 @@ enum Op { OP_ENC = 0, OP_DEC = 1, OP_SUM = 2, OP_SMUL = 3, OP_FUSED = 4, OP_COUN
 
 const void* kernel_for(int cls, int op);
 void slot_shape(int cls, int op, int w, int Ls, int L, int* tiles, size_t* words);
-int elems_per_block(int cls);
+int elems_per_block(int cls);          // elements per workgroup pass (modulus n^2)
 
 hipError_t launch_encrypt(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
                           int m_limbs, const uint32_t* r, uint32_t* c, size_t count);
+// halves: 2 (Ls + 1) words per element of staging between the two phases;
+// count <= DEC_CHUNK per launch pair
+constexpr size_t DEC_CHUNK = (size_t)1 << 18;
 hipError_t launch_decrypt(int cls, const Launch& l, const SkConst& sk, const uint32_t* c,
-                          uint32_t* m, size_t count);
+                          uint32_t* m, size_t count, uint32_t* halves);
 hipError_t launch_hom_sum(int cls, const Launch& l, const PkConst& pk, const PtrList& cs, int K,
                           uint32_t* out, size_t count);
 hipError_t launch_scalar_mul(int cls, const Launch& l, const PkConst& pk, const uint32_t* c,
                              const uint32_t* k, uint32_t* out, size_t count);
-hipError_t launch_fused(int cls, const Launch& l, const SkConst& sk, const PtrList& ms,
-                        const PtrList& rs, int K, int m_limbs, uint32_t* mout, size_t count);
+// first phase of the fused path: prod = prod_k Enc(m_k, r_k), 2L limbs per element
+hipError_t launch_enc_prod(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
+                           const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count);
 
 // persistent batch kernels (kernels_batch.hip)
 int batch_pair(int ca, int cb);
@@ -31,6 +35,15 @@ void batch_slot_shape(int op, int cls, int w, int Ls, int* tiles, size_t* words)
 hipError_t launch_batch(int op, int pair, int grid, const BatchJob* jobs, const BatchItem* items,
                         int nitems, int* queue, uint32_t* scratch, size_t slot_words, int w_a,
                         int w_b, int* err, void* stream);
+
+// FP64 ADMM kernels (kernels_admm.hip)
+hipError_t admm_setup(const double* A, const double* y, int N, int B, int K, double rho,
+                      double* W, double* aty, void* stream);
+hipError_t admm_local(const double* A, const double* Lchol, const double* aty, const double* z,
+                      const double* u, int N, int B, int K, double rho, double* w, double* t,
+                      double* s, double* x, double* xu, void* stream);
+hipError_t admm_consensus(const double* sum, const double* x, int N, int K, double kappa,
+                          double* z, double* u, void* stream);
 
 hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, const double* x,
                            uint64_t* m, size_t count);

@@ -225,6 +225,71 @@ __device__ __forceinline__ void dec_group(const SkConst& sk, const uint32_t* __r
     garner_store(sk, slot, slot + slot_words, m + e * L, live, err, slot + 6 * H.Ls + 4);
 }
 
+// One CRT half (prime s = p for half 0, q for half 1) of the decryption of
+// the group gi of 64/Tp elements, one element per Tp-lane tile.  The half is
+// uniform over the wavefront, so the prime's constants and exponent are
+// wave-uniform and zero windows of s-1 are skipped.  Lane 0 of tile t writes
+// m_s (Ls limbs) and a validity word to stage[(2 t + half) (Ls + 1) ..].
+template <class Gp>
+__device__ __forceinline__ void dec_half_group(const SkConst& sk, int half,
+                                               const uint32_t* __restrict__ c, size_t count,
+                                               size_t gi, uint32_t* lds_all, uint32_t* slots,
+                                               size_t slot_words, int w,
+                                               uint32_t* __restrict__ stage) {
+  constexpr int EPW = 64 / Gp::T;
+  const int tl = threadIdx.x & (Gp::T - 1);
+  const int tile = threadIdx.x / Gp::T;
+  uint32_t* lds = lds_all + tile * Gp::SP;
+  uint32_t* slot = slots + tile * slot_words;
+  const HalfConst& H = sk.h[half];
+  uint32_t N[Gp::K];
+  load_chunk<Gp>(N, H.s2.N, tl);
+  const uint32_t np = H.s2.nprime;
+  const int L2 = 2 * sk.pk.L, Ls = H.Ls;
+  size_t e = gi * EPW + tile;
+  const bool live = e < count;
+  if (!live) e = count - 1;
+  const uint32_t* ce = c + e * L2;
+  uint32_t cv = 1;
+  if (tl == 0) cv = sc_cmp(ce, L2, sk.pk.n2.Nl, L2) < 0;
+  Program P = decrypt_program<Gp>(H, sk.ebits, ce, L2, slot, tl);
+  P.uniform_e = true;
+  uint32_t x[Gp::K];
+  run_program<Gp>(P, x, lds, slot, w, N, np, tl);
+  lds_sync();
+  to_lds<Gp>(lds, x, tl);
+  lds_sync();
+  if (tl == 0) {
+    decrypt_half_finish<Gp>(H, lds, slot, cv);
+    if (live) {
+      uint32_t* dst = stage + (size_t)(2 * tile + half) * (Ls + 1);
+      for (int i = 0; i < Ls; ++i) dst[i] = slot[4 * Ls + 2 + i];
+      dst[Ls] = slot[5 * Ls + 2];
+    }
+  }
+}
+
+// CRT recombination of one element from its two halves (one lane per element):
+// m = m_q + q ((m_p - m_q) q^-1 mod p), Lemma 1 for the moduli p, q in
+// Garner's form.  work: 5 Ls + 2 words.
+__device__ __forceinline__ void garner_elem(const SkConst& sk, const uint32_t* __restrict__ hp,
+                                            const uint32_t* __restrict__ hq, uint32_t* dst,
+                                            int* err, uint32_t* work) {
+  const int Ls = sk.h[0].Ls, L = sk.pk.L;
+  const bool good = hp[Ls] && hq[Ls];
+  uint32_t* d = work;                  // Ls
+  uint32_t* h = work + Ls;             // Ls
+  uint32_t* tmp = work + 2 * Ls;       // Ls + 2
+  uint32_t* prod = work + 3 * Ls + 2;  // 2 Ls
+  for (int i = 0; i < Ls; ++i) d[i] = hp[i];
+  if (sc_sub(d, Ls, hq, Ls)) sc_add(d, Ls, sk.h[0].s, Ls);
+  sc_montmul(h, d, sk.QI, sk.h[0].s, sk.h[0].s_n0, Ls, tmp);
+  sc_mul(prod, sk.h[1].s, Ls, h, Ls);
+  sc_add(prod, 2 * Ls, hq, Ls);
+  for (int i = 0; i < L; ++i) dst[i] = (good && i < 2 * Ls) ? prod[i] : 0u;
+  if (!good) atomicOr(err, pc2k::ERR_RANGE);
+}
+
 // out[j] = prod_k c_k[j] mod n^2 over the inputs with j < len_k (all inputs
 // when lens is null).  acc = MM(c_k, acc) keeps a factor R^-(K-1), removed by
 // one product with R^K; an input that does not reach element j contributes

@@ -70,6 +70,10 @@ struct BatchJob {
   const uint32_t* const* inputs;  // hom_sum: K device pointers
   const size_t* lengths;          // hom_sum: K input lengths (may be null)
 };
+// Largest prime, in 32-bit limbs, that a secret key may hold (the 3072-bit
+// class admits primes of up to 1565 bits).
+constexpr int LS_MAX = 50;
+
 // A work item: one wavefront's group of elements of one job.
 struct BatchItem {
   int job;
@@ -106,6 +110,7 @@ struct Launch {
   size_t slot_words;     // words of one tile's table slot
   int* err;              // latched error word
   void* stream;
+  uint32_t* aux;         // per-element staging after the tables (decryption halves)
 };
 
 }  // namespace pc2k

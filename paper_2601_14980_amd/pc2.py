@@ -45,6 +45,7 @@ EXPORTS = [
     "pc2_hom_add", "pc2_hom_scalar_mul", "pc2_hom_sum", "pc2_enc_sum_dec",
     "pc2_batch_create", "pc2_batch_run", "pc2_batch_destroy", "pc2_autotune",
     "pc2_runner_create", "pc2_runner_group_size", "pc2_runner_launch", "pc2_runner_destroy",
+    "pc2_admm_create", "pc2_admm_local", "pc2_admm_consensus", "pc2_admm_destroy",
 ]
 
 
@@ -105,6 +106,11 @@ def _load() -> ctypes.CDLL:
         "pc2_runner_launch": (c_int, [P, POINTER(pc2_job), POINTER(c_size_t), POINTER(c_size_t),
                                       c_size_t, P]),
         "pc2_runner_destroy": (c_int, [P]),
+        "pc2_admm_create": (c_int, [P, P, P, c_uint32, c_uint32, c_uint32, c_double, P,
+                                    POINTER(P)]),
+        "pc2_admm_local": (c_int, [P, P, P, P, P, P]),
+        "pc2_admm_consensus": (c_int, [P, P, P, c_double, P, P, P]),
+        "pc2_admm_destroy": (c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -42,35 +42,84 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def sliding_schedule(e: int, w: int) -> list[tuple[int, int]]:
+    """Left-to-right sliding windows of e: (squarings, odd digit or 0) per
+    entry, the first entry's digit being the starting power (the schedule
+    the kernels run for a wave-uniform exponent)."""
+    out, sq, i, first = [], 0, e.bit_length() - 1, True
+    while i >= 0:
+        if not (e >> i) & 1:
+            sq += 1
+            i -= 1
+            continue
+        j = max(i - w + 1, 0)
+        while not (e >> j) & 1:
+            j += 1
+        d = (e >> j) & ((1 << (i - j + 1)) - 1)
+        out.append((0 if first else sq + i - j + 1, d))
+        first, sq, i = False, 0, j - 1
+    if sq:
+        out.append((sq, 0))
+    return out
+
+
+def schedule_products(e: int, w: int) -> int:
+    """Montgomery products of the table (x^2, then the odd powers up to
+    x^(2^w - 1)) and of the powering."""
+    sched = sliding_schedule(e, w)
+    return (1 << (w - 1)) + sum(nsq for nsq, _ in sched[1:]) + sum(1 for _, d in sched[1:] if d)
+
+
 def montgomery_products_per_encrypt(nbits_n: int, n: int, window: int) -> tuple[int, int]:
-    """Montgomery products in the encryption schedule and the algorithmic
-    32x32-bit limb products they stand for (2 S^2 + S with S 32-bit limbs of
-    n^2, the textbook CIOS count)."""
-    w = window
-    nw = (n.bit_length() + w - 1) // w
-    digits = [(n >> (i * w)) & ((1 << w) - 1) for i in range(nw)]
-    mults = sum(1 for d in digits[:-1] if d != 0)
-    mm = 2 + ((1 << w) - 2) + w * (nw - 1) + mults + 1
+    """Montgomery products in the encryption schedule (g^m and r R before,
+    the table and sliding-window powering of r^n, one product after) and the
+    algorithmic 32x32-bit limb products they stand for (2 S^2 + S with S
+    32-bit limbs of n^2, the textbook CIOS count)."""
+    mm = 2 + schedule_products(n, window) + 1
     S = 2 * ((nbits_n + 31) // 32)
     return mm, mm * (2 * S * S + S)
 
 
 def montgomery_products_per_decrypt(p: int, q: int, window: int) -> tuple[int, int]:
-    """Both CRT halves: REDC + R^3 product + table + powering (zero windows
-    skipped) + conversion."""
-    w = window
+    """Both CRT halves: reduction of c + R^3 product + table + sliding-window
+    powering of c^(s-1) + conversion."""
     total_mm, total_prod = 0, 0
     for s in (p, q):
-        e = s - 1
-        eb = max((p - 1).bit_length(), (q - 1).bit_length())
-        nw = (eb + w - 1) // w
-        digits = [(e >> (i * w)) & ((1 << w) - 1) for i in range(nw)]
-        mults = sum(1 for d in digits[:-1] if d != 0)  # zero windows are skipped
-        mm = 1 + 1 + ((1 << w) - 2) + w * (nw - 1) + mults + 1
+        mm = 2 + schedule_products(s - 1, window) + 1
         S = (s * s).bit_length() + 31 >> 5
         total_mm += mm
         total_prod += mm * (2 * S * S + S)
     return total_mm, total_prod
+
+
+# ------------------------------------------------------- measured HBM traffic
+# Sources that define k_encrypt: a traffic record counts only while they are
+# unchanged since its counters were taken.
+KERNEL_SOURCES = ["kernels_paillier.hip", "paillier_ops.hpp", "engine.hpp", "mont_tile.hpp",
+                  "bn_scalar.hpp", "pc2_types.hpp", "launch.hpp"]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_encrypt_2048bit_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_14980_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(elements: int):
+    """HBM bytes per k_encrypt launch of `elements` from the committed
+    FETCH_SIZE / WRITE_SIZE record, or None if the kernel changed since."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("elements") != elements:
+        return None
+    return int(rec["hbm_bytes_per_launch"])
 
 
 # ------------------------------------------------------------- CPU baseline
@@ -295,13 +344,15 @@ ADMM_BITS = 3072
 ADMM_M, ADMM_N, ADMM_K = 4096, 16384, 32
 
 
-def run_admm(pc2, gen, ctx, torch, np, args) -> dict:
+def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
     """Distributed lasso, A 4096 x 16384 ~ N(0, 1/4096) split row-wise over 32
     nodes, x* 1 %-sparse with N(0,1) nonzeros, noise 1e-3; rho = 1,
     lambda = 0.1 ||A^T y||_inf.  Every iteration quantizes the 32 local
     16384-dim updates, encrypts them under a 3072-bit key, aggregates them
     homomorphically, decrypts and dequantizes the sum and applies the
-    consensus update, all on the device."""
+    consensus update, all on the device.  The loop runs once per engine of
+    the encryptions' Montgomery product ("valu", "mfma": i8 matrix cores),
+    each from z = u = 0; the iterates must agree exactly across engines."""
     from paper_2601_14980_amd.admm import EncryptedConsensusLasso
     M, N, K = ADMM_M, ADMM_N, ADMM_K
     t0 = time.perf_counter()
@@ -321,47 +372,56 @@ def run_admm(pc2, gen, ctx, torch, np, args) -> dict:
     yd = torch.from_numpy(y).cuda()
     del A
     drv = EncryptedConsensusLasso(ctx, sk, Ad, yd, K, 1.0, lam, qa.log2_scale, qa.offset, r_pool)
-    z = torch.zeros(N, dtype=torch.float64, device="cuda")
-    u = torch.zeros((K, N), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    times, enc_ms, dec_ms = [], [], []
-    for it in range(args.admm_warmup + args.admm_iters):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        drv.local(z, u)
-        pc2.pc2_quantize(ctx, qa.log2_scale, qa.offset, drv.xu.reshape(-1), drv.m)
-        ev[0].record(stream)
-        pc2.pc2_encrypt(sk.public, drv.m.view(torch.int32).reshape(K * N, 2), drv.r, drv.c)
-        ev[1].record(stream)
-        pc2.pc2_hom_sum(sk.public, drv.parts, drv.agg)
-        ev[2].record(stream)
-        pc2.pc2_decrypt(sk, drv.agg, drv.msum)
-        ev[3].record(stream)
-        pc2.pc2_dequantize(ctx, qa.log2_scale, qa.offset, drv.msum, K, drv.total)
-        drv.consensus(z, u)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        if it >= args.admm_warmup:
-            times.append(dt)
-            enc_ms.append(ev[0].elapsed_time(ev[1]))
-            dec_ms.append(ev[2].elapsed_time(ev[3]))
-        log(f"admm iteration {it + 1}: {dt * 1e3:.0f} ms")
-    if ctx.sync() != 0:
-        raise RuntimeError("device reported a data error in the ADMM loop")
-    zh = z.cpu().numpy()
+    out = {"workload": "lasso A 4096x16384 ~ N(0,1/4096), 32 nodes x 128 rows, x* 1% sparse, "
+                       "noise 1e-3, rho 1, lambda 0.1 ||A^T y||_inf; 3072-bit key, scale 2^44, "
+                       "offset 2^51", "lambda": lam}
+    final = {}
+    for engine in engines:
+        ctx.set_option(pc2.PC2_OPT_MODMUL,
+                       pc2.PC2_MODMUL_MFMA if engine == "mfma" else pc2.PC2_MODMUL_VALU)
+        z = torch.zeros(N, dtype=torch.float64, device="cuda")
+        u = torch.zeros((K, N), dtype=torch.float64, device="cuda")
+        times, enc_ms, dec_ms = [], [], []
+        for it in range(args.admm_warmup + args.admm_iters):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            drv.local(z, u)
+            pc2.pc2_quantize(ctx, qa.log2_scale, qa.offset, drv.xu.reshape(-1), drv.m)
+            ev[0].record(stream)
+            pc2.pc2_encrypt(sk.public, drv.m.view(torch.int32).reshape(K * N, 2), drv.r, drv.c)
+            ev[1].record(stream)
+            pc2.pc2_hom_sum(sk.public, drv.parts, drv.agg)
+            ev[2].record(stream)
+            pc2.pc2_decrypt(sk, drv.agg, drv.msum)
+            ev[3].record(stream)
+            pc2.pc2_dequantize(ctx, qa.log2_scale, qa.offset, drv.msum, K, drv.total)
+            drv.consensus(z, u)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            if it >= args.admm_warmup:
+                times.append(dt)
+                enc_ms.append(ev[0].elapsed_time(ev[1]))
+                dec_ms.append(ev[2].elapsed_time(ev[3]))
+            log(f"admm ({engine}) iteration {it + 1}: {dt * 1e3:.0f} ms")
+        ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_VALU)
+        if ctx.sync() != 0:
+            raise RuntimeError("device reported a data error in the ADMM loop")
+        zh = z.cpu().numpy()
+        final[engine] = zh
+        mt = float(np.median(times))
+        out[engine] = {"iterations_timed": len(times), "ms_per_iteration": round(mt * 1e3, 1),
+                       "encrypt_ms": round(float(np.median(enc_ms)), 1),
+                       "decrypt_ms": round(float(np.median(dec_ms)), 1),
+                       "enc_dec_ops_per_s": round((K * N + N) / mt, 1),
+                       "mse_z_vs_xstar": float(np.mean((zh - xstar) ** 2)),
+                       "nnz_z": int(np.count_nonzero(zh))}
     drv.close()
-    mt = float(np.median(times))
-    return {"workload": "lasso A 4096x16384 ~ N(0,1/4096), 32 nodes x 128 rows, x* 1% sparse, "
-                        "noise 1e-3, rho 1, lambda 0.1 ||A^T y||_inf; 3072-bit key, scale 2^44, "
-                        "offset 2^51",
-            "modmul": "valu", "iterations_timed": len(times), "ms_per_iteration": round(mt * 1e3, 1),
-            "encrypt_ms": round(float(np.median(enc_ms)), 1),
-            "decrypt_ms": round(float(np.median(dec_ms)), 1),
-            "enc_dec_ops_per_s": round((K * N + N) / mt, 1),
-            "lambda": lam,
-            "mse_z_vs_xstar": float(np.mean((zh - xstar) ** 2)),
-            "nnz_z": int(np.count_nonzero(zh))}
+    if len(final) > 1:
+        vals = list(final.values())
+        out["engines_agree_exactly"] = all(np.array_equal(vals[0], v) for v in vals[1:])
+    return out
 
 
 # --------------------------------------------------------------------- main
@@ -379,6 +439,13 @@ def main() -> int:
     ap.add_argument("--no-admm", action="store_true")
     ap.add_argument("--admm-iters", type=int, default=2)
     ap.add_argument("--admm-warmup", type=int, default=1)
+    ap.add_argument("--admm-modmul", default="valu,mfma",
+                    help="Montgomery engines to run the lasso leg with (comma-separated)")
+    ap.add_argument("--modmul", choices=("valu", "mfma"), default="valu",
+                    help="Montgomery engine of the main leg's encryptions")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run an elementwise kernel that reads and writes MIB MiB "
+                         "(reference for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
@@ -387,6 +454,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):          # an elementwise kernel: reads and writes MIB MiB each
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.calibrate_copy, "launches": 3}), flush=True)
+        return 0
 
     from paper_2601_14980_amd import pc2
     from workload import gen
@@ -401,6 +478,8 @@ def main() -> int:
     log(f"inputs generated in {time.perf_counter() - t0:.1f}s")
 
     ctx = pc2.Context(0)
+    if args.modmul == "mfma":
+        ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_MFMA)
     if args.window:
         ctx.set_option(pc2.PC2_OPT_WINDOW, args.window)
     ctx.reserve(NBITS)
@@ -494,7 +573,7 @@ def main() -> int:
         log(f"plain step {i + 1}/{args.plain_steps}: {t_plain[-1] * 1e3:.0f} ms")
     plain_value = ops_per_step / (sum(t_plain) / len(t_plain)) if t_plain else None
 
-    w = ctx.get_option(pc2.PC2_OPT_WINDOW) or 5
+    w = ctx.get_option(pc2.PC2_OPT_WINDOW) or 6   # the automatic width at 2048 bits
     mm_enc, prod_enc = montgomery_products_per_encrypt(NBITS, n, w)
     enc_avg_s = sum(enc_ms) / len(enc_ms) / 1e3
     achieved = prod_enc * total / enc_avg_s
@@ -511,7 +590,8 @@ def main() -> int:
 
     batching = None if args.no_batching else run_batching(pc2, gen, ctx, torch, np, args)
     serving = None if args.no_serving else run_serving(pc2, gen, ctx, sk, torch, np, args)
-    admm = None if args.no_admm else run_admm(pc2, gen, ctx, torch, np, args)
+    admm = None if args.no_admm else run_admm(pc2, gen, ctx, torch, np, args,
+                                              args.admm_modmul.split(","))
 
     out = {
         "metric": "2048-bit Paillier enc+dec ops/sec, batched vs plain; serving p50/p99 latency",
@@ -529,7 +609,7 @@ def main() -> int:
         "config": {"workload": "2048-bit key, 8 nodes x 65536 float64 ~ N(0,1), scale 2^20, "
                                "offset 2^23: quantize, encrypt 524288, 8-way sum, decrypt 65536, "
                                "dequantize", "nbits": NBITS, "nodes": NODES, "length": LENGTH,
-                   "window": w, "path": "batched"},
+                   "window": w, "path": "batched", "modmul": args.modmul},
         "enc_per_s": round(total / enc_avg_s, 1),
         "dec_per_s": round(LENGTH / (sum(dec_ms) / len(dec_ms) / 1e3), 1),
         "plain": ({"value": round(plain_value, 1), "unit": "ops/s",
@@ -542,7 +622,7 @@ def main() -> int:
                      "peak": round(PEAK_PRODUCTS / 1e12, 3),
                      "unit": "T limb-products/s (32x32->64, v_mad_u64_u32)",
                      "frac": round(achieved / PEAK_PRODUCTS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(total),
                      "per_launch_products": prod_enc * total,
                      "mm_per_encrypt": mm_enc,
                      "avg_launch_ms": round(enc_avg_s * 1e3, 3)},

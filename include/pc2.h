@@ -89,9 +89,15 @@ int pc2_ctx_take_error(pc2_ctx *ctx);
  * later data call allocates. */
 int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
 
-/* Options.  PC2_OPT_WINDOW: fixed window width w in {0 (auto), 2..6} of the
- * modular exponentiations.  PC2_OPT_MODMUL: limb-product engine for the
- * Montgomery products (PC2_MODMUL_VALU or PC2_MODMUL_MFMA). */
+/* Options.  PC2_OPT_WINDOW: window width w in {0 (auto), 2..6} of the
+ * modular exponentiations (sliding windows over the key's exponents n,
+ * p - 1, q - 1; fixed windows over per-element exponents).  PC2_OPT_MODMUL: limb-product engine for the
+ * Montgomery products of pc2_encrypt: PC2_MODMUL_VALU (default; 27/28-bit
+ * digits, one v_mad_u64_u32 per limb product) or PC2_MODMUL_MFMA (7-bit
+ * digits, the three limb-product matrices of each product on the i8 matrix
+ * cores with int32 accumulation, carries resolved on the vector ALUs).  Both
+ * give identical results; the other operations always use the VALU engine.
+ * Options apply to calls made after they are set. */
 enum { PC2_OPT_WINDOW = 1, PC2_OPT_MODMUL = 2 };
 enum { PC2_MODMUL_VALU = 0, PC2_MODMUL_MFMA = 1 };
 int pc2_ctx_set_option(pc2_ctx *ctx, int option, int64_t value);

@@ -152,10 +152,93 @@ pc2k::ModConst mod_const(const uint32_t* base, const ModOffsets& o) {
   return m;
 }
 
+
+// Left-to-right sliding-window schedule of e > 0 (see pc2k::Sched)
+std::vector<uint32_t> sliding_schedule(const Limbs& e0, int w) {
+  Limbs e = e0;
+  pc2h::trim(e);
+  auto bit = [&](int i) -> uint32_t { return (e[i / 32] >> (i % 32)) & 1u; };
+  std::vector<uint32_t> out;
+  int i = pc2h::bitlen(e) - 1;
+  uint32_t sq = 0;
+  bool first = true;
+  while (i >= 0) {
+    if (!bit(i)) {
+      ++sq;
+      --i;
+      continue;
+    }
+    int j = std::max(i - w + 1, 0);
+    while (!bit(j)) ++j;
+    uint32_t d = 0;
+    for (int k = i; k >= j; --k) d = (d << 1) | bit(k);
+    if (!first) sq += (uint32_t)(i - j + 1);
+    out.push_back((sq << 16) | d);
+    first = false;
+    sq = 0;
+    i = j - 1;
+  }
+  if (sq) out.push_back(sq << 16);
+  return out;
+}
+
+struct SchedOffsets {
+  size_t off[pc2k::SCHED_WMAX - pc2k::SCHED_WMIN + 1];
+  int n[pc2k::SCHED_WMAX - pc2k::SCHED_WMIN + 1];
+};
+SchedOffsets add_schedules(DevBuf& buf, const Limbs& e) {
+  SchedOffsets o{};
+  for (int w = pc2k::SCHED_WMIN; w <= pc2k::SCHED_WMAX; ++w) {
+    std::vector<uint32_t> sc = sliding_schedule(e, w);
+    o.off[w - pc2k::SCHED_WMIN] = buf.add(sc);
+    o.n[w - pc2k::SCHED_WMIN] = (int)sc.size();
+  }
+  return o;
+}
+pc2k::Sched sched_const(const uint32_t* base, const SchedOffsets& o) {
+  pc2k::Sched c{};
+  for (int i = 0; i <= pc2k::SCHED_WMAX - pc2k::SCHED_WMIN; ++i) {
+    c.p[i] = base + o.off[i];
+    c.n[i] = o.n[i];
+  }
+  return c;
+}
+
 struct PkOffsets {
   ModOffsets n2;
   size_t nR, Rk, n;
+  size_t mN, mNp, mR2, mnR, mN28;  // matrix-core product constants
+  int mS;
+  SchedOffsets nsch;
 };
+
+// v -> D = 4 S forward 7-bit digits, one per byte, zero-padded to 16 bytes
+std::vector<uint32_t> to_digits7(const Limbs& v, int S) {
+  const int D = 4 * S, D16 = (D + 15) & ~15;
+  std::vector<uint32_t> out(D16 / 4, 0);
+  for (int i = 0; i < D; ++i) {
+    const long bit = (long)i * 7;
+    const size_t w = bit / 32;
+    const int sh = bit % 32;
+    const uint64_t lo = w < v.size() ? v[w] : 0, hi = w + 1 < v.size() ? v[w + 1] : 0;
+    const uint32_t d = (uint32_t)(((hi << 32) | lo) >> sh) & 0x7Fu;
+    out[i / 4] |= d << (8 * (i % 4));
+  }
+  return out;
+}
+
+// v -> S limbs of 28 bits
+std::vector<uint32_t> to_limbs28(const Limbs& v, int S) {
+  std::vector<uint32_t> out(S, 0);
+  for (int i = 0; i < S; ++i) {
+    const long bit = (long)i * 28;
+    const size_t w = bit / 32;
+    const int sh = bit % 32;
+    const uint64_t lo = w < v.size() ? v[w] : 0, hi = w + 1 < v.size() ? v[w + 1] : 0;
+    out[i] = (uint32_t)(((hi << 32) | lo) >> sh) & ((1u << 28) - 1u);
+  }
+  return out;
+}
 
 PkOffsets add_public(DevBuf& buf, const Limbs& n, int cls, int L) {
   const pc2k::ClassGeo g = pc2k::CLASS_GEO[cls];
@@ -177,6 +260,27 @@ PkOffsets add_public(DevBuf& buf, const Limbs& n, int cls, int L) {
   }
   o.Rk = buf.add(tab);
   o.n = buf.add(pc2h::resized(n, L));
+  // matrix-core form: R = 2^(28 S), N' = -N^-1 mod R
+  const int S = pc2k::MFMA_S[cls];
+  const uint64_t RBm = 28ull * S;
+  Limbs N = n2;
+  pc2h::trim(N);
+  const size_t nw = (RBm + 31) / 32;
+  Limbs inv = pc2h::inv_pow2(N, nw);
+  Limbs Rm = pc2h::resized(Limbs{}, nw + 1);
+  Rm[RBm / 32] |= 1u << (RBm % 32);  // 2^RBm (RBm < 32 nw + 32)
+  Limbs invR = pc2h::resized(inv, nw);
+  if (RBm % 32) invR[nw - 1] &= (1u << (RBm % 32)) - 1u;  // inv mod 2^RBm
+  pc2h::trim(invR);
+  Limbs np = pc2h::sub(Rm, invR);  // 2^RBm - inv (inv != 0 for odd N)
+  pc2h::trim(np);
+  o.mS = S;
+  o.mN = buf.add(to_digits7(N, S));
+  o.mNp = buf.add(to_digits7(np, S));
+  o.mR2 = buf.add(to_digits7(pc2h::pow2_mod(2 * RBm, N), S));
+  o.mnR = buf.add(to_digits7(pc2h::shl_mod(n, RBm, N), S));
+  o.mN28 = buf.add(to_limbs28(N, S));
+  o.nsch = add_schedules(buf, n);
   return o;
 }
 
@@ -188,6 +292,13 @@ pc2k::PkConst pk_const(const uint32_t* base, const PkOffsets& o, int L, int nbit
   c.n = base + o.n;
   c.L = L;
   c.nbits = nbits;
+  c.mf.N = (const uint8_t*)(base + o.mN);
+  c.mf.Np = (const uint8_t*)(base + o.mNp);
+  c.mf.R2 = (const uint8_t*)(base + o.mR2);
+  c.mf.nR = (const uint8_t*)(base + o.mnR);
+  c.mf.N28 = base + o.mN28;
+  c.mf.S = o.mS;
+  c.nsch = sched_const(base, o.nsch);
   return c;
 }
 
@@ -196,6 +307,7 @@ struct HalfOffsets {
   size_t s, e, sinv, H;
   uint32_t s_n0;
   int Ls;
+  SchedOffsets esch;
 };
 
 // constants for the prime s (other prime t, n = s t) of the CRT decryption
@@ -220,6 +332,7 @@ HalfOffsets add_half(DevBuf& buf, const Limbs& s, const Limbs& t, const Limbs& n
   o.H = buf.add(pc2h::resized(H, Ls));
   o.s_n0 = 0u - pc2h::inv32(s[0]);
   o.Ls = Ls;
+  o.esch = add_schedules(buf, pc2h::sub(s, Limbs{1}));
   (void)t;
   return o;
 }
@@ -233,6 +346,7 @@ pc2k::HalfConst half_const(const uint32_t* base, const HalfOffsets& o) {
   h.H = base + o.H;
   h.s_n0 = o.s_n0;
   h.Ls = o.Ls;
+  h.esch = sched_const(base, o.esch);
   return h;
 }
 
@@ -256,13 +370,16 @@ int upload(pc2_ctx* ctx, const DevBuf& buf, void** dev) {
 
 int auto_window(int cls, int op) {
   // window width minimising products for the exponent lengths of each class
+  // (sliding windows for the wave-uniform exponents of encryption and
+  // decryption)
   if (op == pc2k::OP_SMUL) return 4;
-  return cls >= 5 ? 5 : (cls >= 3 ? 4 : 3);
+  return cls >= 6 ? 6 : (cls >= 5 ? 5 : (cls >= 3 ? 4 : 3));
 }
 
 int window_for(const pc2_ctx* ctx, int cls, int op) {
   if (ctx->window) return ctx->window;
   const int t = ctx->tuned[cls][op == pc2k::OP_FUSED ? pc2k::OP_ENC : op];
+  if (op == pc2k::OP_ENC_MFMA) return t ? t : (cls >= 5 ? 5 : 4);
   return t ? t : auto_window(cls, op);
 }
 
@@ -270,7 +387,9 @@ int occupancy(pc2_ctx* ctx, int cls, int op) {
   int& o = ctx->occ[cls][op];
   if (o == 0) {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, pc2k::kernel_for(cls, op), 64, 0) !=
+    const void* k = op == pc2k::OP_ENC_MFMA ? pc2k::kernel_encrypt_mfma(cls)
+                                            : pc2k::kernel_for(cls, op);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, 64, 0) !=
             hipSuccess ||
         v <= 0)
       v = 1;
@@ -285,7 +404,7 @@ int occupancy(pc2_ctx* ctx, int cls, int op) {
 int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::Launch* l,
             void* stream, size_t aux_words = 0) {
   const int w = window_for(ctx, cls, op);
-  const size_t epb = (size_t)pc2k::elems_per_block(cls);
+  const size_t epb = op == pc2k::OP_ENC_MFMA ? 1 : (size_t)pc2k::elems_per_block(cls);
   const size_t groups = (count + epb - 1) / epb;
   const size_t cap = (size_t)ctx->cus * occupancy(ctx, cls, op);
   l->grid = (int)std::max<size_t>(1, std::min(groups, cap));
@@ -294,7 +413,12 @@ int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::La
   l->stream = stream;
   int tiles = 0;
   size_t words = 0;
-  pc2k::slot_shape(cls, op, w, Ls, L, &tiles, &words);
+  if (op == pc2k::OP_ENC_MFMA) {  // one table of 2^w digit arrays per workgroup
+    tiles = 1;
+    words = (pc2k::mfma_digit_bytes(cls) << w) / 4;
+  } else {
+    pc2k::slot_shape(cls, op, w, Ls, L, &tiles, &words);
+  }
   words = (words + 3) & ~(size_t)3;
   l->slot_words = words;
   const size_t aux = (aux_words + 63) & ~(size_t)63;
@@ -410,7 +534,7 @@ int pc2_ctx_set_option(pc2_ctx* ctx, int option, int64_t value) {
     return PC2_OK;
   }
   if (option == PC2_OPT_MODMUL) {
-    if (value == PC2_MODMUL_VALU) {
+    if (value == PC2_MODMUL_VALU || value == PC2_MODMUL_MFMA) {
       ctx->modmul = (int)value;
       return PC2_OK;
     }
@@ -572,6 +696,12 @@ int pc2_encrypt(const pc2_pk* pk, const uint32_t* m, uint32_t m_limbs, const uin
   if (count == 0) return PC2_OK;
   if (!m || !r || !c || m_limbs < 1 || (int)m_limbs > pk->L) return PC2_E_INVAL;
   pc2k::Launch l{};
+  if (pk->ctx->modmul == PC2_MODMUL_MFMA) {
+    int rc = prepare(pk->ctx, pk->cls, pc2k::OP_ENC_MFMA, count, 0, pk->L, &l, stream);
+    if (rc) return rc;
+    return status_of(
+        pc2k::launch_encrypt_mfma(pk->cls, l, pk->c, m, (int)m_limbs, r, c, count));
+  }
   int rc = prepare(pk->ctx, pk->cls, pc2k::OP_ENC, count, 0, pk->L, &l, stream);
   if (rc) return rc;
   return status_of(pc2k::launch_encrypt(pk->cls, l, pk->c, m, (int)m_limbs, r, c, count));

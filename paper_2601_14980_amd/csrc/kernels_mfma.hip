@@ -1,0 +1,136 @@
+// Paillier encryption (Sec. III-B, f_en with g = n + 1) with the modular
+// products on the i8 matrix cores: c = (1 + m n) r^n mod n^2.
+//
+// One wavefront per element (mfma_mont.hpp); workgroups stride over the
+// elements.  Per element: g^m = MM(m, n R) + 1 (exact: m n < n^2); r R =
+// MM(r, R^2); a table of (r R)^k, k < 2^w, in the workgroup's scratch slot;
+// left-to-right fixed windows over n (zero windows skipped); one product
+// with g^m leaves normal form; a conditional subtraction of n^2 makes it
+// canonical.  Data errors (m >= n, r = 0, r >= n) zero the element and set
+// ERR_RANGE.
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+#include "launch.hpp"
+#include "mfma_mont.hpp"
+#include "paillier_ops.hpp"
+
+namespace {
+
+using pc2k::PkConst;
+
+template <int S>
+__global__ __launch_bounds__(64, 2) void k_encrypt_mfma(PkConst pk, const uint32_t* __restrict__ m,
+                                                        int m_limbs,
+                                                        const uint32_t* __restrict__ r,
+                                                        uint32_t* __restrict__ c, size_t count,
+                                                        uint8_t* __restrict__ scratch, int w,
+                                                        int* err) {
+  using G = pc2m::MGeo<S>;
+  __shared__ __align__(16) pc2m::MWork<G> ws;
+  __shared__ uint32_t s_ok;
+  const int lane = threadIdx.x;
+  const pc2m::MConst& K = pk.mf;
+  uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::D8 << w);
+  const int L = pk.L;
+  pc2m::init_work<G>(ws, K, lane);
+  uint32_t U[G::LPL];
+  for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
+    const uint32_t* me = m + e * m_limbs;
+    const uint32_t* re = r + e * L;
+    if (lane == 0) s_ok = pc2ops::encrypt_inputs_ok(pk, me, m_limbs, re);
+    // g^m = 1 + m n
+    pc2m::load_x<G>(ws, me, m_limbs, lane, false);
+    pc2m::mont_mul<G>(ws, K.nR, lane, false, ws.gm, true, U);
+    // table entry 1 = r R, entries k = (r R)^k R^-(k-1)
+    pc2m::load_x<G>(ws, re, L, lane, false);
+    pc2m::mont_mul<G>(ws, K.R2, lane, false, table + G::D8, false, U);
+    for (int k = 2; k < (1 << w); ++k)
+      pc2m::mont_mul<G>(ws, table + G::D8, lane, false, table + (size_t)k * G::D8, false, U);
+    // (r R)^n by windows of n, most significant first
+    const int nw = (pk.nbits + w - 1) / w;
+    const uint32_t top = exp_window(pk.n, L, (nw - 1) * w, w);
+    pc2m::load_fwd<G>(ws, table + (size_t)top * G::D8, lane);
+    for (int win = nw - 2; win >= 0; --win) {
+      for (int s = 0; s < w; ++s) pc2m::mont_mul<G>(ws, ws.xf, lane, true, nullptr, false, U);
+      const uint32_t dig = exp_window(pk.n, L, win * w, w);
+      if (dig) pc2m::mont_mul<G>(ws, table + (size_t)dig * G::D8, lane, true, nullptr, false, U);
+    }
+    // r^n g^m = MM(r^n R, g^m), < 2 n^2
+    pc2m::mont_mul<G>(ws, ws.gm, lane, false, nullptr, false, U);
+    // canonical: subtract n^2 once if needed, then 28-bit limbs -> 32-bit words
+    uint32_t* u = reinterpret_cast<uint32_t*>(ws.cols);
+#pragma unroll
+    for (int i = 0; i < G::LPL; ++i) {
+      const int gi = lane * G::LPL + i - G::S;
+      if (gi >= 0 && gi < G::S) u[gi] = U[i];
+    }
+    pc2m::wave_sync();
+    if (lane == 0) {
+      int cmp = 0;
+      for (int i = G::S - 1; i >= 0 && cmp == 0; --i)
+        cmp = u[i] > K.N28[i] ? 1 : (u[i] < K.N28[i] ? -1 : 0);
+      if (cmp >= 0) {
+        int32_t bor = 0;
+        for (int i = 0; i < G::S; ++i) {
+          const int32_t d = (int32_t)u[i] - (int32_t)K.N28[i] - bor;
+          bor = d < 0 ? 1 : 0;
+          u[i] = (uint32_t)(d + (bor << 28));
+        }
+      }
+    }
+    pc2m::wave_sync();
+    const uint32_t ok = s_ok;
+    uint32_t* ce = c + e * 2 * (size_t)L;
+    for (int j = lane; j < 2 * L; j += 64) {
+      const int b = 32 * j, i = b / 28, s = b % 28;
+      const uint64_t acc = (uint64_t)(i < G::S ? u[i] : 0u) |
+                           ((uint64_t)(i + 1 < G::S ? u[i + 1] : 0u) << 28) |
+                           ((uint64_t)(i + 2 < G::S ? u[i + 2] : 0u) << 56);
+      ce[j] = ok ? (uint32_t)(acc >> s) : 0u;
+    }
+    if (lane == 0 && !ok) atomicOr(err, pc2k::ERR_RANGE);
+    pc2m::wave_sync();
+  }
+}
+
+template <int C>
+const void* mfma_kernel() {
+  return (const void*)&k_encrypt_mfma<pc2k::MFMA_S[C]>;
+}
+
+}  // namespace
+
+namespace pc2k {
+
+const void* kernel_encrypt_mfma(int cls) {
+  switch (cls) {
+    case 0: return mfma_kernel<0>();
+    case 1: return mfma_kernel<1>();
+    case 2: return mfma_kernel<2>();
+    case 3: return mfma_kernel<3>();
+    case 4: return mfma_kernel<4>();
+    case 5: return mfma_kernel<5>();
+    case 6: return mfma_kernel<6>();
+    case 7: return mfma_kernel<7>();
+  }
+  return nullptr;
+}
+
+size_t mfma_digit_bytes(int cls) {
+  const int D = 4 * MFMA_S[cls];
+  return (size_t)((D + 15) & ~15);
+}
+
+hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
+                               int m_limbs, const uint32_t* r, uint32_t* c, size_t count) {
+  const void* k = kernel_encrypt_mfma(cls);
+  if (!k) return hipErrorInvalidValue;
+  uint8_t* scratch = reinterpret_cast<uint8_t*>(l.scratch);
+  int w = l.window;
+  void* args[] = {(void*)&pk, (void*)&m, (void*)&m_limbs, (void*)&r, (void*)&c,
+                  (void*)&count, (void*)&scratch, (void*)&w, (void*)&l.err};
+  return hipLaunchKernel(k, dim3(l.grid), dim3(64), args, 0, (hipStream_t)l.stream);
+}
+
+}  // namespace pc2k

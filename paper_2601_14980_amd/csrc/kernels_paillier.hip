@@ -159,7 +159,7 @@ __global__ __launch_bounds__(64, 2) void k_enc_prod(PkConst pk, PtrList ms, PtrL
         const uint32_t* me = ms.p[k] + e * m_limbs;
         const uint32_t* re = rs.p[k] + e * L;
         if (tl == 0) okall &= encrypt_inputs_ok(pk, me, m_limbs, re);
-        P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl);
+        P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl, w);
         if (k > 0) {
           P.npost = 2;
           P.post1_a = op_x();
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(64, 2) void k_enc_prod(PkConst pk, PtrList ms, PtrL
         P.pre0_a = op_chunk(pk.Rk + (size_t)K * G::CH);
         P.pre0_b = op_chunk(slot_acc);
       }
-      run_program<G>(P, x, lds, slot, w, N, np, tl);
+      run_program<G, true>(P, x, lds, slot, w, N, np, tl);
       if (k < K) store_chunk<G>(slot_acc, x, tl);
     }
     lds_sync();
@@ -216,7 +216,12 @@ const void* kernel_for(int cls, int op) {
   return nullptr;
 }
 
-// Tiles (scratch slots) per workgroup and words per slot.
+// Tiles (scratch slots) per workgroup and words per slot.  A slot holds
+// entry 0 plus the window table: 2^w - 1 entries for fixed windows, 2^(w-1)
+// odd powers for the sliding windows of a wave-uniform exponent.
+inline size_t table_entries(int w, bool sliding) {
+  return sliding ? ((size_t)1 << (w - 1)) + 1 : (size_t)1 << w;
+}
 template <int C>
 static void slot_shape_t(int op, int w, int Ls, int L, int* tiles, size_t* words) {
   using Gn = typename Geos<C>::Gn;
@@ -225,17 +230,20 @@ static void slot_shape_t(int op, int w, int Ls, int L, int* tiles, size_t* words
   const size_t scal = (size_t)12 * Ls + 16;
   switch (op) {
     case OP_ENC:
+      *tiles = epw;
+      *words = (size_t)Gn::CH * table_entries(w, true);
+      break;
     case OP_SMUL:
       *tiles = epw;
       *words = (size_t)Gn::CH << w;
       break;
     case OP_DEC:
       *tiles = 64 / Gp::T;
-      *words = std::max((size_t)Gp::CH << w, scal);
+      *words = std::max((size_t)Gp::CH * table_entries(w, true), scal);
       break;
     case OP_FUSED:
       *tiles = 2 * epw;
-      *words = (size_t)Gn::CH << w;
+      *words = (size_t)Gn::CH * table_entries(w, true);
       break;
     default:
       *tiles = 0;

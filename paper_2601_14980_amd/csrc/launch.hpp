@@ -6,7 +6,11 @@
 
 namespace pc2k {
 
-enum Op { OP_ENC = 0, OP_DEC = 1, OP_SUM = 2, OP_SMUL = 3, OP_FUSED = 4, OP_COUNT = 5 };
+enum Op {
+  OP_ENC = 0, OP_DEC = 1, OP_SUM = 2, OP_SMUL = 3, OP_FUSED = 4,
+  OP_ENC_MFMA = 5,  // encryption with the matrix-core product (kernels_mfma.hip)
+  OP_COUNT = 6
+};
 
 const void* kernel_for(int cls, int op);
 void slot_shape(int cls, int op, int w, int Ls, int L, int* tiles, size_t* words);
@@ -26,6 +30,13 @@ hipError_t launch_scalar_mul(int cls, const Launch& l, const PkConst& pk, const 
 // first phase of the fused path: prod = prod_k Enc(m_k, r_k), 2L limbs per element
 hipError_t launch_enc_prod(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
                            const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count);
+
+// encryption with the i8-MFMA Montgomery product (kernels_mfma.hip); the
+// scratch holds 2^window forward digit arrays per workgroup
+const void* kernel_encrypt_mfma(int cls);
+size_t mfma_digit_bytes(int cls);
+hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
+                               int m_limbs, const uint32_t* r, uint32_t* c, size_t count);
 
 // persistent batch kernels (kernels_batch.hip)
 int batch_pair(int ca, int cb);

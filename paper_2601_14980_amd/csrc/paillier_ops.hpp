@@ -26,6 +26,15 @@ __device__ __forceinline__ void lds_canonical(uint32_t* lds, const ModConst& M) 
   if (sc_cmp(lds, M.nl + 1, M.Nl, M.nl) >= 0) sc_sub(lds, M.nl + 1, M.Nl, M.nl);
 }
 
+// The sliding-window schedule of a wave-uniform exponent for window w
+// (2 <= w <= 6, the range the context accepts).
+__device__ __forceinline__ void use_schedule(Program& P, const pc2k::Sched& sc, int w) {
+  const int i = w < pc2k::SCHED_WMIN ? 0 : (w > pc2k::SCHED_WMAX ? pc2k::SCHED_WMAX - pc2k::SCHED_WMIN
+                                                                   : w - pc2k::SCHED_WMIN);
+  P.sched = sc.p[i];
+  P.nsched = sc.n[i];
+}
+
 // Encryption of one element (Sec. III-B, f_en with g = n + 1):
 //   pre0:  MM(m, n R)      = m n  (exact: m n < n^2), + 1 -> g^m, kept in slot entry 0
 //   pre1:  MM(R^2, r)      = r R  (Montgomery form of r)
@@ -35,7 +44,7 @@ __device__ __forceinline__ void lds_canonical(uint32_t* lds, const ModConst& M) 
 template <class G>
 __device__ __forceinline__ Program encrypt_program(const PkConst& pk, const uint32_t* me,
                                                    int m_limbs, const uint32_t* re,
-                                                   uint32_t* slot, int tl) {
+                                                   uint32_t* slot, int tl, int w) {
   chunk_from_limbs<G>(slot, me, m_limbs, 0, tl);
   chunk_from_limbs<G>(slot + G::CH, re, pk.L, 0, tl);
   Program P = empty_program();
@@ -50,6 +59,7 @@ __device__ __forceinline__ Program encrypt_program(const PkConst& pk, const uint
   P.elimbs = pk.L;
   P.ebits = pk.nbits;
   P.uniform_e = true;
+  use_schedule(P, pk.nsch, w);
   P.one = pk.n2.R1;
   P.npost = 1;
   P.post0_a = op_chunk(slot);
@@ -62,10 +72,12 @@ __device__ __forceinline__ Program encrypt_program(const PkConst& pk, const uint
 //   pre1:  MM(R^3, c R^-1)     = c R
 //   pow:   (c R)^(s-1)         = c^(s-1) R
 //   post0: MM(., 1)            = c^(s-1) mod s^2
+// (uniform: the half is the same for the whole wavefront, so its sliding
+// schedule applies)
 template <class G>
 __device__ __forceinline__ Program decrypt_program(const HalfConst& H, int ebits,
                                                    const uint32_t* ce, int L2, uint32_t* slot,
-                                                   int tl) {
+                                                   int tl, int w, bool uniform) {
   chunk_from_limbs<G>(slot, ce, L2, 0, tl);
   Program P = empty_program();
   P.npre = 2;
@@ -78,7 +90,8 @@ __device__ __forceinline__ Program decrypt_program(const HalfConst& H, int ebits
   P.e = H.e;
   P.elimbs = H.Ls;
   P.ebits = ebits;
-  P.uniform_e = false;
+  P.uniform_e = uniform;
+  if (uniform) use_schedule(P, H.esch, w);
   P.one = H.s2.R1;
   P.npost = 1;
   P.post0_a = op_x();
@@ -181,9 +194,9 @@ __device__ __forceinline__ void enc_group(const PkConst& pk, const uint32_t* __r
   const uint32_t* re = r + e * L;
   uint32_t ok = 1;
   if (tl == 0) ok = encrypt_inputs_ok(pk, me, m_limbs, re);
-  Program P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl);
+  Program P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl, w);
   uint32_t x[G::K];
-  run_program<G>(P, x, lds, slot, w, N, np, tl);
+  run_program<G, true>(P, x, lds, slot, w, N, np, tl);
   lds_sync();
   to_lds<G>(lds, x, tl);
   lds_sync();
@@ -213,7 +226,7 @@ __device__ __forceinline__ void dec_group(const SkConst& sk, const uint32_t* __r
   const uint32_t* ce = c + e * L2;
   uint32_t cv = 1;
   if (tl == 0) cv = sc_cmp(ce, L2, sk.pk.n2.Nl, L2) < 0;
-  Program P = decrypt_program<Gp>(H, sk.ebits, ce, L2, slot, tl);
+  Program P = decrypt_program<Gp>(H, sk.ebits, ce, L2, slot, tl, w, false);
   uint32_t x[Gp::K];
   run_program<Gp>(P, x, lds, slot, w, N, np, tl);
   lds_sync();
@@ -252,10 +265,9 @@ __device__ __forceinline__ void dec_half_group(const SkConst& sk, int half,
   const uint32_t* ce = c + e * L2;
   uint32_t cv = 1;
   if (tl == 0) cv = sc_cmp(ce, L2, sk.pk.n2.Nl, L2) < 0;
-  Program P = decrypt_program<Gp>(H, sk.ebits, ce, L2, slot, tl);
-  P.uniform_e = true;
+  Program P = decrypt_program<Gp>(H, sk.ebits, ce, L2, slot, tl, w, true);
   uint32_t x[Gp::K];
-  run_program<Gp>(P, x, lds, slot, w, N, np, tl);
+  run_program<Gp, true>(P, x, lds, slot, w, N, np, tl);
   lds_sync();
   to_lds<Gp>(lds, x, tl);
   lds_sync();

@@ -26,6 +26,27 @@ struct ModConst {
   int nl;
 };
 
+// Sliding-window schedules of an exponent for window widths 2..6 (entry
+// (nsq << 16) | d: square nsq times, then multiply by x^d, d odd or 0; the
+// first entry's d is the starting power).
+constexpr int SCHED_WMIN = 2, SCHED_WMAX = 6;
+struct Sched {
+  const uint32_t* p[SCHED_WMAX - SCHED_WMIN + 1];
+  int n[SCHED_WMAX - SCHED_WMIN + 1];
+};
+
+// Constants of n^2 for the i8-MFMA Montgomery product (mfma_mont.hpp):
+// R = 2^(28 S); forward arrays of 7-bit digits, one per byte, zero-padded to
+// a multiple of 16 bytes.
+struct MfmaConst {
+  const uint8_t* N;      // n^2
+  const uint8_t* Np;     // -(n^2)^-1 mod R
+  const uint8_t* R2;     // R^2 mod n^2
+  const uint8_t* nR;     // n R mod n^2
+  const uint32_t* N28;   // n^2 as S limbs of 28 bits
+  int S;
+};
+
 struct PkConst {
   ModConst n2;           // modulus n^2; Nl has 2L limbs
   const uint32_t* nR;    // n R mod n^2 (chunked)
@@ -33,6 +54,8 @@ struct PkConst {
   const uint32_t* n;     // n, L limbs
   int L;                 // limbs of n (ABI: plaintexts L, ciphertexts 2L)
   int nbits;             // bit length of n (the exponent of r^n)
+  MfmaConst mf;          // the same modulus for the matrix-core product
+  Sched nsch;            // sliding-window schedules of n
 };
 
 // One prime s of the CRT decryption (s = p or q, p > q).
@@ -44,6 +67,7 @@ struct HalfConst {
   const uint32_t* H;     // h_s 2^(32 Ls) mod s, h_s = L_s(g^(s-1) mod s^2)^-1 mod s
   uint32_t s_n0;         // -s^-1 mod 2^32
   int Ls;
+  Sched esch;            // sliding-window schedules of s - 1
 };
 
 struct SkConst {
@@ -80,6 +104,10 @@ struct BatchItem {
   int pad;
   size_t group;
 };
+
+// Limbs (28-bit) of R for the matrix-core product per key class:
+// 28 S >= 2 * (class limit) + 2, so R > 4 n^2.
+constexpr int MFMA_S[8] = {3, 5, 10, 19, 37, 74, 147, 220};
 
 // Key size classes: index by ceil(log2) of the key.  n^2 and s^2 use
 // separate digit geometries (see mont_tile.hpp).

@@ -1,0 +1,95 @@
+"""Encryption with the i8-MFMA Montgomery product (GPU tests).
+
+With PC2_OPT_MODMUL = PC2_MODMUL_MFMA, pc2_encrypt runs its modular
+products on the matrix cores.  Every ciphertext must equal the oracle's and
+the VALU path's bit for bit; decryption must invert it."""
+from __future__ import annotations
+
+import math
+import random
+
+import pytest
+import torch
+
+from oracle import paillier as O
+from tests.gpu_helpers import gpu_decrypt, gpu_encrypt
+from workload import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mfma_ctx():
+    from paper_2601_14980_amd import pc2
+    ctx = pc2.Context(0)
+    ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_MFMA)
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _key(ctx, p, q, nbits=None):
+    from paper_2601_14980_amd import pc2
+    n = p * q
+    sk = pc2.SecretKey(ctx, nbits or n.bit_length(), p, q)
+    opk, osk = O.derive_keys(p, q)
+    return sk, opk, osk
+
+
+@pytest.mark.parametrize("p,q", [(3, 5), (7, 11), (11, 13)])
+def test_mfma_bruteforce_tiny(mfma_ctx, p, q):
+    sk, opk, _ = _key(mfma_ctx, p, q)
+    n = p * q
+    pairs = [(m, r) for m in range(n) for r in range(1, n) if math.gcd(r, n) == 1]
+    cs, st = gpu_encrypt(mfma_ctx, sk.public, [m for m, _ in pairs], [r for _, r in pairs])
+    assert st == 0
+    assert cs == [O.encrypt(opk, m, r) for m, r in pairs]
+
+
+@pytest.mark.parametrize("nbits", [64, 256, 1024, 2048, 3072])
+def test_mfma_matches_oracle_and_valu(gpu_ctx, mfma_ctx, nbits):
+    from paper_2601_14980_amd import pc2
+    p, q = gen.primes_for(1, nbits, extra=7)
+    n = p * q
+    sk, opk, osk = _key(mfma_ctx, p, q, nbits)
+    count = 150 if nbits >= 2048 else 300           # several waves of workgroups plus a tail
+    rng = random.Random(nbits)
+    ms = [0, 1, n - 1] + [rng.randrange(n) for _ in range(count - 3)]
+    rs = [1, n - 1, 2] + gen.gen_r(n, count - 3, 1, extra=nbits)
+    cs, st = gpu_encrypt(mfma_ctx, sk.public, ms, rs)
+    assert st == 0
+    sk_v = pc2.SecretKey(gpu_ctx, nbits, p, q)
+    cv, st = gpu_encrypt(gpu_ctx, sk_v.public, ms, rs)
+    assert st == 0
+    assert cs == cv, "MFMA and VALU ciphertexts differ"
+    for j in sorted({0, 1, 2, 3, count // 2, count - 1}):
+        assert cs[j] == O.encrypt(opk, ms[j], rs[j]), f"element {j}"
+    dec, st = gpu_decrypt(gpu_ctx, sk_v, cs)
+    assert st == 0 and dec == ms
+
+
+def test_mfma_small_plaintext_limbs(mfma_ctx):
+    """Quantized plaintexts arrive as two limbs."""
+    p, q = gen.primes_for(1, 2048, extra=8)
+    n = p * q
+    sk, opk, _ = _key(mfma_ctx, p, q, 2048)
+    rng = random.Random(5)
+    ms = [rng.getrandbits(64) for _ in range(70)]
+    rs = gen.gen_r(n, 70, 1, extra=99)
+    cs, st = gpu_encrypt(mfma_ctx, sk.public, ms, rs, m_limbs=2)
+    assert st == 0
+    for j in (0, 33, 69):
+        assert cs[j] == O.encrypt(opk, ms[j], rs[j])
+
+
+def test_mfma_range_errors(mfma_ctx):
+    p, q = gen.primes_for(1, 256, extra=9)
+    n = p * q
+    sk, opk, _ = _key(mfma_ctx, p, q, 256)
+    ms = [5, n, 7, 8]
+    rs = [3, 3, 0, n]
+    cs, st = gpu_encrypt(mfma_ctx, sk.public, ms, rs)
+    assert st != 0
+    assert cs[0] == O.encrypt(opk, 5, 3)
+    assert cs[1:] == [0, 0, 0]
+    assert mfma_ctx.sync() == 0   # the error latch was cleared

@@ -67,6 +67,7 @@ struct pc2_batch {
 
 struct pc2_pk {
   pc2_ctx* ctx = nullptr;
+  int device = 0;
   uint32_t nbits = 0;
   int L = 0;
   int cls = 0;
@@ -212,17 +213,18 @@ struct PkOffsets {
   SchedOffsets nsch;
 };
 
-// v -> D = 4 S forward 7-bit digits, one per byte, zero-padded to 16 bytes
+// v -> D = 4 S forward 7-bit digits, one per byte after 64 zero bytes, with
+// a zero tail to 64 + D8 + 16 bytes (D8 = D rounded up to 16)
 std::vector<uint32_t> to_digits7(const Limbs& v, int S) {
-  const int D = 4 * S, D16 = (D + 15) & ~15;
-  std::vector<uint32_t> out(D16 / 4, 0);
+  const int D = 4 * S, FB = 64 + ((D + 15) & ~15) + 16;
+  std::vector<uint32_t> out(FB / 4, 0);
   for (int i = 0; i < D; ++i) {
     const long bit = (long)i * 7;
     const size_t w = bit / 32;
     const int sh = bit % 32;
     const uint64_t lo = w < v.size() ? v[w] : 0, hi = w + 1 < v.size() ? v[w + 1] : 0;
     const uint32_t d = (uint32_t)(((hi << 32) | lo) >> sh) & 0x7Fu;
-    out[i / 4] |= d << (8 * (i % 4));
+    out[(64 + i) / 4] |= d << (8 * (i % 4));
   }
   return out;
 }
@@ -571,6 +573,7 @@ int pc2_pk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* n_limbs, pc2_pk*
     return rc;
   }
   pk->ctx = ctx;
+  pk->device = ctx->device;
   pk->nbits = nbits;
   pk->L = L;
   pk->cls = cls;
@@ -619,6 +622,7 @@ int pc2_sk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* p_limbs, const u
   const uint32_t* base = (const uint32_t*)sk->dev;
   sk->ctx = ctx;
   sk->pk.ctx = ctx;
+  sk->pk.device = ctx->device;
   sk->pk.nbits = nbits;
   sk->pk.L = L;
   sk->pk.cls = cls;
@@ -639,7 +643,7 @@ const pc2_pk* pc2_sk_public(const pc2_sk* sk) { return sk ? &sk->pk : nullptr; }
 int pc2_pk_destroy(pc2_pk* pk) {
   if (!pk || !pk->ctx) return PC2_E_INVAL;
   if (!pk->dev) return PC2_E_INVAL;  // the public part of a private key
-  (void)hipSetDevice(pk->ctx->device);
+  (void)hipSetDevice(pk->device);  // the context may already be gone
   (void)hipDeviceSynchronize();
   (void)hipFree(pk->dev);
   delete pk;
@@ -648,7 +652,7 @@ int pc2_pk_destroy(pc2_pk* pk) {
 
 int pc2_sk_destroy(pc2_sk* sk) {
   if (!sk || !sk->ctx) return PC2_E_INVAL;
-  (void)hipSetDevice(sk->ctx->device);
+  (void)hipSetDevice(sk->pk.device);  // the context may already be gone
   (void)hipDeviceSynchronize();
   (void)hipFree(sk->dev);
   delete sk;

@@ -31,39 +31,40 @@ __global__ __launch_bounds__(64, 2) void k_encrypt_mfma(PkConst pk, const uint32
   __shared__ uint32_t s_ok;
   const int lane = threadIdx.x;
   const pc2m::MConst& K = pk.mf;
-  uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::D8 << w);
+  uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::FB << w);
   const int L = pk.L;
   pc2m::init_work<G>(ws, K, lane);
-  uint32_t U[G::LPL];
+  pc2m::init_table<G>(table, 1 << w, lane);
+  uint32_t U[G::NT];
   for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
     const uint32_t* me = m + e * m_limbs;
     const uint32_t* re = r + e * L;
     if (lane == 0) s_ok = pc2ops::encrypt_inputs_ok(pk, me, m_limbs, re);
     // g^m = 1 + m n
-    pc2m::load_x<G>(ws, me, m_limbs, lane, false);
+    pc2m::load_x<G>(ws, me, m_limbs, lane);
     pc2m::mont_mul<G>(ws, K.nR, lane, false, ws.gm, true, U);
     // table entry 1 = r R, entries k = (r R)^k R^-(k-1)
-    pc2m::load_x<G>(ws, re, L, lane, false);
-    pc2m::mont_mul<G>(ws, K.R2, lane, false, table + G::D8, false, U);
+    pc2m::load_x<G>(ws, re, L, lane);
+    pc2m::mont_mul<G>(ws, K.R2, lane, false, table + G::FB, false, U);
     for (int k = 2; k < (1 << w); ++k)
-      pc2m::mont_mul<G>(ws, table + G::D8, lane, false, table + (size_t)k * G::D8, false, U);
+      pc2m::mont_mul<G>(ws, table + G::FB, lane, false, table + (size_t)k * G::FB, false, U);
     // (r R)^n by windows of n, most significant first
     const int nw = (pk.nbits + w - 1) / w;
     const uint32_t top = exp_window(pk.n, L, (nw - 1) * w, w);
-    pc2m::load_fwd<G>(ws, table + (size_t)top * G::D8, lane);
+    pc2m::load_fwd<G>(ws, table + (size_t)top * G::FB, lane);
     for (int win = nw - 2; win >= 0; --win) {
       for (int s = 0; s < w; ++s) pc2m::mont_mul<G>(ws, ws.xf, lane, true, nullptr, false, U);
       const uint32_t dig = exp_window(pk.n, L, win * w, w);
-      if (dig) pc2m::mont_mul<G>(ws, table + (size_t)dig * G::D8, lane, true, nullptr, false, U);
+      if (dig) pc2m::mont_mul<G>(ws, table + (size_t)dig * G::FB, lane, true, nullptr, false, U);
     }
     // r^n g^m = MM(r^n R, g^m), < 2 n^2
     pc2m::mont_mul<G>(ws, ws.gm, lane, false, nullptr, false, U);
     // canonical: subtract n^2 once if needed, then 28-bit limbs -> 32-bit words
-    uint32_t* u = reinterpret_cast<uint32_t*>(ws.cols);
+    uint32_t* u = reinterpret_cast<uint32_t*>(ws.tr);
 #pragma unroll
-    for (int i = 0; i < G::LPL; ++i) {
-      const int gi = lane * G::LPL + i - G::S;
-      if (gi >= 0 && gi < G::S) u[gi] = U[i];
+    for (int q = 0; q < G::NT; ++q) {
+      const int gi = 64 * q + lane - G::S;
+      if (gi >= 0 && gi < G::S) u[gi] = U[q];
     }
     pc2m::wave_sync();
     if (lane == 0) {
@@ -117,9 +118,9 @@ const void* kernel_encrypt_mfma(int cls) {
   return nullptr;
 }
 
-size_t mfma_digit_bytes(int cls) {
+size_t mfma_digit_bytes(int cls) {  // a forward digit array, with its zero pads
   const int D = 4 * MFMA_S[cls];
-  return (size_t)((D + 15) & ~15);
+  return (size_t)(64 + ((D + 15) & ~15) + 16);
 }
 
 hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,

@@ -9,16 +9,17 @@
 //     T = x y,    q = (T mod R) N' mod R  (N' = -N^-1 mod R),    U = (T + q N) / R
 //
 // are each computed exactly by v_mfma_i32_16x16x64_i8 with int32
-// accumulation: one instruction adds, for a 16 x 16 tile of output columns
-// p = 256 Q + 16 j + r, the 64 digit products a_i b_(p-i) with
-// i = 64 t + r - k (k < 64) -- a Toeplitz band of a times a block of b.
-// Column sums stay below D 127^2 < 2^24.  The carry propagation is explicit:
-// four columns fold into one 28-bit limb position of a 64-bit value, a
-// lane-local pass and one lane shift leave carries of 0 or 1, and a
-// wave-wide carry-lookahead (two ballots and one 64-bit add) resolves them.
-//
-// Work per product: D^2 digit products (7-bit digits), against 2 S^2 limb
-// products (28-bit) for the VALU form in mont_tile.hpp.
+// accumulation.  Output column p = 256 Q + 4 j + alpha(i), with
+// alpha(i) = 64 (i / 4) + i % 4, takes row i of tile Q from a Toeplitz band
+// of x (digits alpha(i) + 64 t - k, k < 64) and column j from a block of y
+// (digits 256 Q + 4 j - 64 t + k); summing over t covers every digit pair
+// once.  With that column order, lane l of tile Q ends up holding the four
+// columns of limb 64 Q + l in its four accumulators, so the digits fold into
+// 28-bit limbs in registers.  Column sums stay below D 127^2 < 2^24.  The
+// carries are explicit: two rounds of split-and-shift (a DPP lane rotation
+// between limbs) leave carries of 0 or 1, and a carry-lookahead over the
+// limbs (two ballots per tile and a multiword add on the scalar unit)
+// settles them.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,41 +34,42 @@ template <int S_>
 struct MGeo {
   static constexpr int S = S_;                       // 28-bit limbs of R
   static constexpr int D = 4 * S;                    // 7-bit digits
-  static constexpr int D8 = (D + 15) & ~15;          // bytes of a forward digit array
-  static constexpr int LPL = (2 * S + 1 + 63) / 64;  // limbs per lane of a double-length value
-  static constexpr int NT = LPL;                     // 256-column tiles of a full product
-  static constexpr int NTLO = (D + 255) / 256;       // tiles of a product taken mod R
-  static constexpr int TMAX = (D + 62) / 64;         // Toeplitz bands t = 0..TMAX
-  static constexpr int UMIN = -4;                    // forward chunks u that can reach [0, D)
+  static constexpr int D8 = (D + 15) & ~15;
+  static constexpr int PF = 64;                      // zero bytes before a forward array
+  static constexpr int FB = PF + D8 + 16;            // bytes of a forward digit array
+  static constexpr int NT = (2 * S + 1 + 63) / 64;   // 64-limb tiles of a double-length value
+  static constexpr int NTLO = (S + 63) / 64;         // tiles of a product taken mod R
+  static constexpr int TMIN = -3;                    // Toeplitz bands t = TMIN..TMAX
+  static constexpr int TMAX = (D + 62) / 64;
+  static constexpr int UMIN = -1;                    // forward chunks u that can reach [0, D)
   static constexpr int UMAX = (D - 1) / 64;
   static constexpr int NU = UMAX - UMIN + 1;
-  static constexpr int X0 = 64 * TMAX + 15;          // reversed array: byte X0 - i = digit i
-  static constexpr int RB = (X0 + 64 + 15) & ~15;    // bytes of a reversed digit array
-  static constexpr int COLS = 256 * NT;              // int32 column sums
+  static constexpr int X0 = 64 * TMAX + 195;         // reversed array: byte X0 - i = digit i
+  static constexpr int RB = (X0 + 256 + 15) & ~15;   // bytes of a reversed digit array
   static_assert(NTLO <= NT, "low product within the full one");
   static_assert((X0 & 3) == 3, "reversed limbs are dword aligned");
+  static_assert(4 * S <= RB, "the limb scratch fits in a reversed array");
 };
 
 // Per-wavefront LDS workspace.
 template <class G>
 struct MWork {
-  int cols[G::COLS];     // column sums of the last product
   uint8_t xr[G::RB];     // x, reversed (A operand)
-  uint8_t tr[G::RB];     // T mod R, reversed
+  uint8_t tr[G::RB];     // T mod R, reversed; the result's limbs at the end
   uint8_t qr[G::RB];     // q, reversed
-  uint8_t xf[G::D8];     // x, forward (B operand of a squaring)
-  uint8_t gm[G::D8];     // a per-element multiplier, forward
-  uint8_t nf[G::D8];     // N, forward
-  uint8_t npf[G::D8];    // N', forward
+  uint8_t xf[G::FB];     // x, forward (B operand of a squaring)
+  uint8_t gm[G::FB];     // a per-element multiplier, forward
+  uint8_t nf[G::FB];     // N, forward
+  uint8_t npf[G::FB];    // N', forward
 };
 
 using MConst = pc2k::MfmaConst;
 
 constexpr uint32_t M28 = (1u << 28) - 1u;
 
-// value of lane l - 1, 0 in lane 0
-__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF,
+// value of lane (l - 1) mod 64
+__device__ __forceinline__ uint32_t rotate_up(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C /* wave_ror:1 */, 0xF, 0xF,
                                                false);
 }
 
@@ -76,130 +78,135 @@ __device__ __forceinline__ uint32_t limb_digits(uint32_t v) {
   return (v & 0x7Fu) | ((v << 1) & 0x7F00u) | ((v << 2) & 0x7F0000u) | ((v << 3) & 0x7F000000u);
 }
 
-// B operand chunks of a forward digit array (LDS or global, 16-byte aligned):
-// lane (j, g) takes bytes [64 u + 16 j + 16 g, +16) for u = UMIN..UMAX.
+// B operand chunks of a forward digit array y (LDS or global; digit i at
+// byte PF + i): lane (j, g) takes digits [64 u + 4 j + 16 g, +16).
 template <class G>
 __device__ __forceinline__ void load_b(v4i (&B)[G::NU], const uint8_t* y, int lane) {
-  const int base = 16 * (lane & 15) + 16 * (lane >> 4);
+  const int base = 4 * (lane & 15) + 16 * (lane >> 4);
 #pragma unroll
   for (int u = 0; u < G::NU; ++u) {
-    const int off = 64 * (u + G::UMIN) + base;
-    B[u] = (off >= 0 && off < G::D8) ? *reinterpret_cast<const v4i*>(y + off) : v4i{0, 0, 0, 0};
+    const int off = 64 * (u + G::UMIN) + base;  // >= -64
+    v4i b = v4i{0, 0, 0, 0};
+    if (off < G::D8) __builtin_memcpy(&b, y + G::PF + off, 16);
+    B[u] = b;
   }
 }
 
-// Column sums of x y for the NTQ lowest tiles: x from its reversed array in
-// LDS (lane (r, g) reads bytes X0 - 64 t - r + 16 g .. +16, i.e. digits
-// 64 t + r - 16 g - s), y as preloaded B chunks.
+// Digit sums of x y for the NTQ lowest tiles: x from its reversed array in
+// LDS (lane (i, g) reads bytes X0 - alpha(i) - 64 t + 16 g .. +16, i.e.
+// digits alpha(i) + 64 t - 16 g - s), y as preloaded B chunks.  Tile Q,
+// lane l: limb 64 Q + l, digit c in accumulator c.
 template <class G, int NTQ>
 __device__ __forceinline__ void product(v4i (&C)[NTQ], const uint8_t* xr, const v4i (&B)[G::NU],
                                         int lane) {
-  const uint8_t* ap = xr + G::X0 - (lane & 15) + 16 * (lane >> 4);
+  const int i = lane & 15;
+  const uint8_t* ap = xr + G::X0 - (64 * (i >> 2) + (i & 3)) + 16 * (lane >> 4);
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
 #pragma unroll
-  for (int t = 0; t <= G::TMAX; ++t) {
+  for (int t = G::TMIN; t <= G::TMAX; ++t) {
     bool any = false;
 #pragma unroll
     for (int q = 0; q < NTQ; ++q) {
-      const int u = 4 * q - t - G::UMIN;
-      any |= (u >= 0 && u < G::NU);
+      const int u = 4 * q - t;
+      any |= (u >= G::UMIN && u <= G::UMAX);
     }
     if (!any) continue;
-    // 16 unaligned bytes as two 8-byte LDS reads
-    uint64_t lo, hi;
+    uint64_t lo, hi;  // 16 unaligned bytes as two 8-byte LDS reads
     __builtin_memcpy(&lo, ap - 64 * t, 8);
     __builtin_memcpy(&hi, ap - 64 * t + 8, 8);
     const v4i a = v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
                       (int)(uint32_t)(hi >> 32)};
 #pragma unroll
     for (int q = 0; q < NTQ; ++q) {
-      const int u = 4 * q - t - G::UMIN;
-      if (u >= 0 && u < G::NU)
-        C[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, B[u], C[q], 0, 0, 0);
+      const int u = 4 * q - t;
+      if (u >= G::UMIN && u <= G::UMAX)
+        C[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, B[u - G::UMIN], C[q], 0, 0, 0);
     }
   }
 }
 
-// C tile q, lane (j, g) holds columns 256 q + 16 j + 4 g + 0..3
 template <int NTQ>
-__device__ __forceinline__ void store_cols(int* cols, const v4i (&C)[NTQ], int lane) {
-  int* p = cols + 16 * (lane & 15) + 4 * (lane >> 4);
+__device__ __forceinline__ void fold(uint64_t (&v)[NTQ], const v4i (&C)[NTQ]) {
 #pragma unroll
-  for (int q = 0; q < NTQ; ++q) *reinterpret_cast<v4i*>(p + 256 * q) = C[q];
+  for (int q = 0; q < NTQ; ++q)
+    v[q] = (uint64_t)(uint32_t)C[q][0] + ((uint64_t)(uint32_t)C[q][1] << 7) +
+           ((uint64_t)(uint32_t)C[q][2] << 14) + ((uint64_t)(uint32_t)C[q][3] << 21);
 }
 
-// Lane l owns limbs l LPL .. l LPL + LPL - 1: four columns per limb.
-template <class G>
-__device__ __forceinline__ void fold(uint64_t (&v)[G::LPL], const int* cols, int lane) {
+// x[q] += the value of the previous limb (lane - 1 of tile q, or lane 63 of
+// tile q - 1 for lane 0)
+template <int NTQ>
+__device__ __forceinline__ void add_from_prev_limb(uint32_t (&x)[NTQ], const uint32_t (&c)[NTQ],
+                                                   int lane) {
+  uint32_t r[NTQ];
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i) {
-    const v4i c = *reinterpret_cast<const v4i*>(cols + 4 * (lane * G::LPL + i));
-    v[i] = (uint64_t)(uint32_t)c[0] + ((uint64_t)(uint32_t)c[1] << 7) +
-           ((uint64_t)(uint32_t)c[2] << 14) + ((uint64_t)(uint32_t)c[3] << 21);
-  }
+  for (int q = 0; q < NTQ; ++q) r[q] = rotate_up(c[q]);
+#pragma unroll
+  for (int q = 0; q < NTQ; ++q) x[q] += lane ? r[q] : (q ? r[q - 1] : 0u);
 }
 
-// 64-bit limb values (< 2^47) -> 28-bit limbs with all carries resolved
-// across the wavefront; the carry out of the top limb is dropped.
-template <class G>
-__device__ __forceinline__ void normalize(uint32_t (&o)[G::LPL], const uint64_t (&v)[G::LPL],
+// Limb values (< 2^47; limb 64 q + lane in v[q]) -> 28-bit limbs with every
+// carry resolved; the carry out of the top limb is dropped.
+template <int NTQ>
+__device__ __forceinline__ void normalize(uint32_t (&o)[NTQ], const uint64_t (&v)[NTQ],
                                           int lane) {
-  uint64_t c = 0;
+  uint32_t c[NTQ];
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i) {
-    const uint64_t s = v[i] + c;
-    o[i] = (uint32_t)s & M28;
-    c = s >> 28;
+  for (int q = 0; q < NTQ; ++q) {
+    o[q] = (uint32_t)v[q] & M28;
+    c[q] = (uint32_t)(v[q] >> 28);  // < 2^19
   }
-  // c < 2^20 for the values of a product (v < 2^47), so nothing wraps below
-  uint32_t k = from_prev_lane((uint32_t)c);
-  bool all = true;
+  add_from_prev_limb<NTQ>(o, c, lane);  // < 2^28 + 2^19
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i) {
-    const uint32_t s = o[i] + k;
-    o[i] = s & M28;
-    k = s >> 28;
-    all &= (o[i] == M28);
+  for (int q = 0; q < NTQ; ++q) {
+    c[q] = o[q] >> 28;  // 0 or 1
+    o[q] &= M28;
   }
-  // carry-lookahead over lanes: lane l generates (k = 1) or propagates
-  // (all limbs 2^28 - 1); the carry into lane l is bit l of
-  // ((G | P) + G) ^ (G | P) ^ G
-  const uint64_t gen = __ballot(k != 0);
-  const uint64_t prop = __ballot(all && k == 0);
-  const uint64_t a = gen | prop;
-  uint32_t cin = (uint32_t)((((a + gen) ^ a ^ gen) >> lane) & 1ull);
+  add_from_prev_limb<NTQ>(o, c, lane);  // <= 2^28
+  // carry-lookahead over the limbs: limb L generates (value 2^28) or
+  // propagates (2^28 - 1); with A = G | P, the carry into limb L is bit L of
+  // (A + G) ^ A ^ G, taken tile by tile as a multiword add
+  uint64_t carry = 0;
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i) {
-    const uint32_t s = o[i] + cin;
-    o[i] = s & M28;
-    cin = s >> 28;
+  for (int q = 0; q < NTQ; ++q) {
+    const bool gen = (o[q] >> 28) != 0;
+    o[q] &= M28;
+    const uint64_t gm = __ballot(gen);
+    const uint64_t pm = __ballot(!gen && o[q] == M28);
+    const uint64_t a = gm | pm;
+    const uint64_t s1 = a + gm;
+    const uint64_t s2 = s1 + carry;
+    carry = (s1 < a || s2 < s1) ? 1u : 0u;
+    o[q] = (o[q] + (uint32_t)(((s2 ^ a ^ gm) >> lane) & 1ull)) & M28;
   }
 }
 
-// Write limbs with index lo .. lo + S - 1 (as limbs 0 .. S - 1) as digits.
-template <class G>
-__device__ __forceinline__ void write_rev(uint8_t* xr, const uint32_t (&o)[G::LPL], int lane,
+// Write limbs lo .. lo + S - 1 (as limbs 0 .. S - 1) as digits.
+template <class G, int NTQ>
+__device__ __forceinline__ void write_rev(uint8_t* xr, const uint32_t (&o)[NTQ], int lane,
                                           int lo) {
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i) {
-    const int gi = lane * G::LPL + i - lo;
+  for (int q = 0; q < NTQ; ++q) {
+    const int gi = 64 * q + lane - lo;
     if (gi >= 0 && gi < G::S)
-      *reinterpret_cast<uint32_t*>(xr + G::X0 - 4 * gi - 3) = __builtin_bswap32(limb_digits(o[i]));
+      *reinterpret_cast<uint32_t*>(xr + G::X0 - 4 * gi - 3) = __builtin_bswap32(limb_digits(o[q]));
   }
 }
-// (forward arrays also get their zero padding [D, D8) written, since the
-// products read whole 8-byte chunks and global table entries start out
-// uninitialised)
-template <class G>
-__device__ __forceinline__ void write_fwd(uint8_t* y, const uint32_t (&o)[G::LPL], int lane,
+// (forward arrays also get their zero tail [D, D8 + 16) written, since the
+// products read whole 16-byte chunks and global table entries start out
+// uninitialised; the front pad is written once, with the table's slot)
+template <class G, int NTQ>
+__device__ __forceinline__ void write_fwd(uint8_t* y, const uint32_t (&o)[NTQ], int lane,
                                           int lo) {
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i) {
-    const int gi = lane * G::LPL + i - lo;
-    if (gi >= 0 && gi < G::S) *reinterpret_cast<uint32_t*>(y + 4 * gi) = limb_digits(o[i]);
+  for (int q = 0; q < NTQ; ++q) {
+    const int gi = 64 * q + lane - lo;
+    if (gi >= 0 && gi < G::S)
+      *reinterpret_cast<uint32_t*>(y + G::PF + 4 * gi) = limb_digits(o[q]);
   }
-  if (lane < G::D8 / 4 - G::S) *reinterpret_cast<uint32_t*>(y + 4 * (G::S + lane)) = 0u;
+  if (lane < (G::D8 + 16) / 4 - G::S)
+    *reinterpret_cast<uint32_t*>(y + G::PF + 4 * (G::S + lane)) = 0u;
 }
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
@@ -207,56 +214,52 @@ __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 // x <- x y R^-1 mod N (inputs < 2N, output < 2N), x in ws.xr; y a forward
 // digit array (LDS or global).  The result also goes, as forward digits, to
 // ws.xf (fwd) and to out (if not null); plus_one adds 1 to the result
-// before its carries are resolved.  U holds the result's limbs on return
-// (lane l: limbs l LPL + i - S).
+// before its carries are resolved.  U: the result's limbs (limb 64 q + lane
+// - S in U[q]).
 template <class G>
 __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lane, bool fwd,
-                                         uint8_t* out, bool plus_one, uint32_t (&U)[G::LPL]) {
+                                         uint8_t* out, bool plus_one, uint32_t (&U)[G::NT]) {
   v4i B[G::NU];
-  uint64_t v[G::LPL];
-  uint32_t T[G::LPL];
+  uint64_t v[G::NT];
+  uint32_t T[G::NT];
   {
     v4i C[G::NT];
     load_b<G>(B, y, lane);
     product<G, G::NT>(C, ws.xr, B, lane);
-    store_cols<G::NT>(ws.cols, C, lane);
+    fold<G::NT>(v, C);
   }
-  wave_sync();
-  fold<G>(v, ws.cols, lane);
-  normalize<G>(T, v, lane);
-  write_rev<G>(ws.tr, T, lane, 0);
+  normalize<G::NT>(T, v, lane);
+  write_rev<G, G::NT>(ws.tr, T, lane, 0);
   wave_sync();
   {
     v4i C[G::NTLO];
+    uint64_t vl[G::NTLO];
+    uint32_t Q[G::NTLO];
     load_b<G>(B, ws.npf, lane);
     product<G, G::NTLO>(C, ws.tr, B, lane);
-    store_cols<G::NTLO>(ws.cols, C, lane);
-  }
-  wave_sync();
-  fold<G>(v, ws.cols, lane);
+    fold<G::NTLO>(vl, C);
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i)
-    if (lane * G::LPL + i >= G::S) v[i] = 0;
-  normalize<G>(U, v, lane);
-  write_rev<G>(ws.qr, U, lane, 0);
+    for (int q = 0; q < G::NTLO; ++q)
+      if (64 * q + lane >= G::S) vl[q] = 0;
+    normalize<G::NTLO>(Q, vl, lane);
+    write_rev<G, G::NTLO>(ws.qr, Q, lane, 0);
+  }
   wave_sync();
   {
     v4i C[G::NT];
     load_b<G>(B, ws.nf, lane);
     product<G, G::NT>(C, ws.qr, B, lane);
-    store_cols<G::NT>(ws.cols, C, lane);
+    fold<G::NT>(v, C);
   }
-  wave_sync();
-  fold<G>(v, ws.cols, lane);
 #pragma unroll
-  for (int i = 0; i < G::LPL; ++i) {
-    v[i] += T[i];
-    if (plus_one && lane * G::LPL + i == G::S) v[i] += 1;
+  for (int q = 0; q < G::NT; ++q) {
+    v[q] += T[q];
+    if (plus_one && 64 * q + lane == G::S) v[q] += 1;
   }
-  normalize<G>(U, v, lane);
-  write_rev<G>(ws.xr, U, lane, G::S);
-  if (fwd) write_fwd<G>(ws.xf, U, lane, G::S);
-  if (out) write_fwd<G>(out, U, lane, G::S);
+  normalize<G::NT>(U, v, lane);
+  write_rev<G, G::NT>(ws.xr, U, lane, G::S);
+  if (fwd) write_fwd<G, G::NT>(ws.xf, U, lane, G::S);
+  if (out) write_fwd<G, G::NT>(out, U, lane, G::S);
   wave_sync();
 }
 
@@ -267,15 +270,12 @@ __device__ __forceinline__ uint32_t limb28_of(const uint32_t* a, int n, int i) {
   return (uint32_t)(((hi << 32) | lo) >> s) & M28;
 }
 
-// x (n 32-bit words, x < R) -> ws.xr (and ws.xf if fwd)
+// x (n 32-bit words, x < R) -> ws.xr
 template <class G>
-__device__ __forceinline__ void load_x(MWork<G>& ws, const uint32_t* x, int n, int lane,
-                                       bool fwd) {
-  for (int i = lane; i < G::S; i += 64) {
-    const uint32_t d = limb_digits(limb28_of(x, n, i));
-    *reinterpret_cast<uint32_t*>(ws.xr + G::X0 - 4 * i - 3) = __builtin_bswap32(d);
-    if (fwd) *reinterpret_cast<uint32_t*>(ws.xf + 4 * i) = d;
-  }
+__device__ __forceinline__ void load_x(MWork<G>& ws, const uint32_t* x, int n, int lane) {
+  for (int i = lane; i < G::S; i += 64)
+    *reinterpret_cast<uint32_t*>(ws.xr + G::X0 - 4 * i - 3) =
+        __builtin_bswap32(limb_digits(limb28_of(x, n, i)));
   wave_sync();
 }
 
@@ -283,9 +283,9 @@ __device__ __forceinline__ void load_x(MWork<G>& ws, const uint32_t* x, int n, i
 template <class G>
 __device__ __forceinline__ void load_fwd(MWork<G>& ws, const uint8_t* y, int lane) {
   for (int i = lane; i < G::S; i += 64) {
-    const uint32_t d = *reinterpret_cast<const uint32_t*>(y + 4 * i);
+    const uint32_t d = *reinterpret_cast<const uint32_t*>(y + G::PF + 4 * i);
     *reinterpret_cast<uint32_t*>(ws.xr + G::X0 - 4 * i - 3) = __builtin_bswap32(d);
-    *reinterpret_cast<uint32_t*>(ws.xf + 4 * i) = d;
+    *reinterpret_cast<uint32_t*>(ws.xf + G::PF + 4 * i) = d;
   }
   wave_sync();
 }
@@ -294,12 +294,21 @@ __device__ __forceinline__ void load_fwd(MWork<G>& ws, const uint8_t* y, int lan
 template <class G>
 __device__ __forceinline__ void init_work(MWork<G>& ws, const MConst& K, int lane) {
   uint32_t* z = reinterpret_cast<uint32_t*>(ws.xr);
-  constexpr int ZW = (3 * G::RB + 2 * G::D8) / 4;
+  constexpr int ZW = (3 * G::RB + 2 * G::FB) / 4;
   for (int i = lane; i < ZW; i += 64) z[i] = 0u;
-  for (int i = lane; i < G::D8 / 4; i += 64) {
+  for (int i = lane; i < G::FB / 4; i += 64) {
     reinterpret_cast<uint32_t*>(ws.nf)[i] = reinterpret_cast<const uint32_t*>(K.N)[i];
     reinterpret_cast<uint32_t*>(ws.npf)[i] = reinterpret_cast<const uint32_t*>(K.Np)[i];
   }
+  wave_sync();
+}
+
+// zero the front pads of a workgroup's table entries (global)
+template <class G>
+__device__ __forceinline__ void init_table(uint8_t* table, int entries, int lane) {
+  for (int k = 0; k < entries; ++k)
+    for (int i = lane; i < G::PF / 4; i += 64)
+      reinterpret_cast<uint32_t*>(table + (size_t)k * G::FB)[i] = 0u;
   wave_sync();
 }
 

@@ -36,8 +36,8 @@ struct Sched {
 };
 
 // Constants of n^2 for the i8-MFMA Montgomery product (mfma_mont.hpp):
-// R = 2^(28 S); forward arrays of 7-bit digits, one per byte, zero-padded to
-// a multiple of 16 bytes.
+// R = 2^(28 S); forward arrays of 7-bit digits, one per byte, after 64 zero
+// bytes and with a zero tail (64 + D8 + 16 bytes, D8 = 4 S rounded up to 16).
 struct MfmaConst {
   const uint8_t* N;      // n^2
   const uint8_t* Np;     // -(n^2)^-1 mod R

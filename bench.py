@@ -563,6 +563,18 @@ def main() -> int:
     got_int = got[:, 0].astype(object) + (got[:, 1].astype(object) << 32)
     exact = bool(np.all(got[:, 2:] == 0)) and bool(np.all(got_int == sums))
 
+    # key-holder encryption (CRT through p^2, q^2) of the same inputs, checked
+    # against the public-key ciphertexts of the last timed step
+    c_sk = torch.empty_like(c_all)
+    ev[0].record(stream)
+    pc2.pc2_encrypt_sk(sk, m2_all, r_all, c_sk)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    enc_sk_ms = ev[0].elapsed_time(ev[1])
+    enc_sk_same = bool(torch.equal(c_sk, c_all)) and ctx.sync() == 0
+    del c_sk
+    log(f"key-holder encryption: {enc_sk_ms:.1f} ms, identical ciphertexts: {enc_sk_same}")
+
     # plain path
     t_plain = []
     for i in range(args.plain_steps):
@@ -612,6 +624,8 @@ def main() -> int:
                    "window": w, "path": "batched", "modmul": args.modmul},
         "enc_per_s": round(total / enc_avg_s, 1),
         "dec_per_s": round(LENGTH / (sum(dec_ms) / len(dec_ms) / 1e3), 1),
+        "key_holder_enc_per_s": round(total / (enc_sk_ms / 1e3), 1),
+        "key_holder_enc_identical": enc_sk_same,
         "plain": ({"value": round(plain_value, 1), "unit": "ops/s",
                    "ms_per_step": round(1e3 * sum(t_plain) / len(t_plain), 2)}
                   if t_plain else None),

@@ -150,6 +150,16 @@ int pc2_dequantize(pc2_ctx *ctx, const pc2_qparams *q, const uint32_t *m,
 int pc2_encrypt(const pc2_pk *pk, const uint32_t *m, uint32_t m_limbs, const uint32_t *r,
                 uint32_t *c, size_t count, void *stream);
 
+/* Encryption by the key holder (Sec. III-B f_en evaluated through the split
+ * of Z_{n^2} into Z_{p^2} x Z_{q^2} of Sec. IV, the paper's "EP"): the same
+ * c = (1 + m n) r^n mod n^2 as pc2_encrypt, bit for bit, computed as
+ * c_s = (1 + m n) r^(n mod s(s-1)) mod s^2 for s = p, q and recombined
+ * modulo n^2 (Lemma 1 for the moduli p^2, q^2).  Arguments, layouts and data
+ * errors as pc2_encrypt.  Requires balanced primes (p < 2q for p > q;
+ * otherwise PC2_E_UNSUPPORTED), which every key of equal-length primes is. */
+int pc2_encrypt_sk(const pc2_sk *sk, const uint32_t *m, uint32_t m_limbs, const uint32_t *r,
+                   uint32_t *c, size_t count, void *stream);
+
 /* Decryption (Sec. III-C, f_de = L(c^eps mod n^2) mu mod n), evaluated through
  * the split into Z_{p^2} x Z_{q^2} (Sec. IV, Lemmas 1-2).  c: [count][2L],
  * c < n^2; m: [count][L]. */

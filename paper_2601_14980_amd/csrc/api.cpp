@@ -80,6 +80,7 @@ struct pc2_sk {
   pc2_pk pk;            // the public part (owns nothing; dev below owns all)
   void* dev = nullptr;
   pc2k::SkConst c{};
+  bool crt_ok = false;  // p < 2 q: the key-holder encryption's inputs fit mod q^2
 };
 
 namespace {
@@ -310,6 +311,8 @@ struct HalfOffsets {
   uint32_t s_n0;
   int Ls;
   SchedOffsets esch;
+  size_t nRs;
+  SchedOffsets nsch;
 };
 
 // constants for the prime s (other prime t, n = s t) of the CRT decryption
@@ -335,6 +338,15 @@ HalfOffsets add_half(DevBuf& buf, const Limbs& s, const Limbs& t, const Limbs& n
   o.s_n0 = 0u - pc2h::inv32(s[0]);
   o.Ls = Ls;
   o.esch = add_schedules(buf, pc2h::sub(s, Limbs{1}));
+  // key-holder encryption mod s^2: n R mod s^2 and n mod s (s - 1)
+  const uint64_t RBs = (uint64_t)g.pD * g.pK * g.pT;
+  o.nRs = buf.add(to_chunk(pc2h::shl_mod(n, RBs, s2), g.pD, g.pK, g.pT));
+  Limbs order = pc2h::mul(s, pc2h::sub(s, Limbs{1}));
+  pc2h::trim(order);
+  Limbs ne = pc2h::mod(n, order);
+  pc2h::trim(ne);
+  if (ne.empty()) ne = order;  // n = 0 mod s (s-1) cannot happen for n = p q, s | n
+  o.nsch = add_schedules(buf, ne);
   (void)t;
   return o;
 }
@@ -349,6 +361,8 @@ pc2k::HalfConst half_const(const uint32_t* base, const HalfOffsets& o) {
   h.s_n0 = o.s_n0;
   h.Ls = o.Ls;
   h.esch = sched_const(base, o.esch);
+  h.nRs = base + o.nRs;
+  h.nsch = sched_const(base, o.nsch);
   return h;
 }
 
@@ -612,6 +626,16 @@ int pc2_sk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* p_limbs, const u
   // q^-1 2^(32 Ls) mod p
   Limbs qinv = pc2h::inv_mod_prime(pc2h::mod(q, p), p);
   size_t qi = buf.add(pc2h::resized(pc2h::shl_mod(qinv, (uint64_t)32 * Ls, p), Ls));
+  // (q^2)^-1 2^(32 nl2) mod p^2: q^-2 mod p^2 by Euler (phi(p^2) = p (p - 1))
+  Limbs q2 = pc2h::mul(q, q);
+  pc2h::trim(q2);
+  pc2h::Mont32 MP2(p2);
+  Limbs phi = pc2h::mul(p, pc2h::sub(p, Limbs{1}));
+  pc2h::trim(phi);
+  Limbs q2inv = MP2.pow(pc2h::mod(q2, p2), pc2h::sub(phi, Limbs{1}));
+  size_t q2i = buf.add(pc2h::resized(pc2h::shl_mod(q2inv, (uint64_t)32 * nl2, p2), nl2));
+  // the key-holder encryption needs r, m < n < 2 q^2, i.e. p < 2 q
+  const bool crt_ok = pc2h::cmp(p, pc2h::add(q, q)) < 0;
   pc2_sk* sk = new (std::nothrow) pc2_sk();
   if (!sk) return PC2_E_NOMEM;
   int rc = upload(ctx, buf, &sk->dev);
@@ -632,6 +656,9 @@ int pc2_sk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* p_limbs, const u
   sk->c.h[0] = half_const(base, hp);
   sk->c.h[1] = half_const(base, hq);
   sk->c.QI = base + qi;
+  sk->c.Q2I = base + q2i;
+  sk->c.p2_n0 = 0u - pc2h::inv32(p2[0]);
+  sk->crt_ok = crt_ok;
   Limbs pm1 = pc2h::sub(p, Limbs{1}), qm1 = pc2h::sub(q, Limbs{1});
   sk->c.ebits = std::max(pc2h::bitlen(pm1), pc2h::bitlen(qm1));
   *out = sk;
@@ -728,6 +755,28 @@ int pc2_decrypt(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count, 
     const size_t n = std::min(chunk, count - b);
     rc = status_of(pc2k::launch_decrypt(sk->pk.cls, l, sk->c, c + b * L2, m + b * sk->pk.L, n,
                                         l.aux));
+    if (rc) return rc;
+  }
+  return PC2_OK;
+}
+
+int pc2_encrypt_sk(const pc2_sk* sk, const uint32_t* m, uint32_t m_limbs, const uint32_t* r,
+                   uint32_t* c, size_t count, void* stream) {
+  if (!sk || !sk->ctx) return PC2_E_INVAL;
+  if (count == 0) return PC2_OK;
+  if (!m || !r || !c || m_limbs < 1 || (int)m_limbs > sk->pk.L) return PC2_E_INVAL;
+  if (!sk->crt_ok) return PC2_E_UNSUPPORTED;
+  // the two halves of up to DEC_CHUNK elements are staged before the recombination
+  const int nl2 = sk->c.h[0].s2.nl, L = sk->pk.L, cls = sk->pk.cls;
+  const size_t chunk = std::min(count, pc2k::DEC_CHUNK);
+  pc2k::Launch l{};
+  int rc = prepare(sk->ctx, cls, pc2k::OP_ENC_CRT, chunk, sk->c.h[0].Ls, L, &l, stream,
+                   chunk * 2 * (size_t)(nl2 + 1));
+  if (rc) return rc;
+  for (size_t b = 0; b < count; b += chunk) {
+    const size_t n = std::min(chunk, count - b);
+    rc = status_of(pc2k::launch_encrypt_crt(cls, l, sk->c, m + b * m_limbs, (int)m_limbs,
+                                            r + b * (size_t)L, c + b * 2 * (size_t)L, n, l.aux));
     if (rc) return rc;
   }
   return PC2_OK;

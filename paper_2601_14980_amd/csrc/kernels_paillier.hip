@@ -65,6 +65,40 @@ __global__ __launch_bounds__(64) void k_garner(SkConst sk, const uint32_t* __res
   garner_elem(sk, hp, hp + Ls + 1, m + e * sk.pk.L, err, work);
 }
 
+// Key-holder encryption, phase 1: work item w covers element group w / 2
+// modulo the square of prime w % 2.
+template <class Gp>
+__global__ __launch_bounds__(64, 2) void k_encrypt_crt_half(SkConst sk,
+                                                            const uint32_t* __restrict__ m,
+                                                            int m_limbs,
+                                                            const uint32_t* __restrict__ r,
+                                                            size_t count,
+                                                            uint32_t* __restrict__ scratch,
+                                                            size_t slot_words, int w,
+                                                            uint32_t* __restrict__ stage) {
+  constexpr int EPW = 64 / Gp::T;
+  __shared__ __align__(16) uint32_t lds_all[EPW * Gp::SP];
+  uint32_t* slots = scratch + (size_t)blockIdx.x * EPW * slot_words;
+  const size_t nitems = 2 * ((count + EPW - 1) / EPW);
+  const size_t stride = (size_t)EPW * 2 * (sk.h[0].s2.nl + 1);
+  for (size_t it = blockIdx.x; it < nitems; it += gridDim.x)
+    enc_half_group<Gp>(sk, (int)(it & 1), m, m_limbs, r, count, it >> 1, lds_all, slots,
+                       slot_words, w, stage + (it >> 1) * stride);
+}
+
+// Key-holder encryption, phase 2: recombination modulo n^2, one lane per element.
+constexpr int NL2_MAX = 2 * pc2k::LS_MAX;
+__global__ __launch_bounds__(64) void k_garner_crt(SkConst sk, const uint32_t* __restrict__ stage,
+                                                   uint32_t* __restrict__ c, size_t count,
+                                                   int* err) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int n2 = sk.h[0].s2.nl;
+  uint32_t work[5 * NL2_MAX + 2];
+  const uint32_t* cp = stage + e * 2 * (size_t)(n2 + 1);
+  garner_crt_elem(sk, cp, cp + n2 + 1, c + e * 2 * (size_t)sk.pk.L, err, work);
+}
+
 template <class G>
 __global__ __launch_bounds__(64, 2) void k_hom_sum(PkConst pk, PtrList cs, int K,
                                                    uint32_t* __restrict__ out, size_t count,
@@ -207,6 +241,7 @@ static const void* kernel_ptr(int op) {
     case OP_SUM: return (const void*)&k_hom_sum<Gn>;
     case OP_SMUL: return (const void*)&k_scalar_mul<Gn>;
     case OP_FUSED: return (const void*)&k_enc_prod<Gn>;
+    case OP_ENC_CRT: return (const void*)&k_encrypt_crt_half<Gp>;
   }
   return nullptr;
 }
@@ -244,6 +279,10 @@ static void slot_shape_t(int op, int w, int Ls, int L, int* tiles, size_t* words
     case OP_FUSED:
       *tiles = 2 * epw;
       *words = (size_t)Gn::CH * table_entries(w, true);
+      break;
+    case OP_ENC_CRT:
+      *tiles = 64 / Gp::T;
+      *words = (size_t)Gp::CH * table_entries(w, true);
       break;
     default:
       *tiles = 0;
@@ -319,6 +358,26 @@ static hipError_t smul_t(const Launch& l, const PkConst& pk, const uint32_t* c,
 hipError_t launch_scalar_mul(int cls, const Launch& l, const PkConst& pk, const uint32_t* c,
                              const uint32_t* k, uint32_t* out, size_t count) {
   PC2_DISPATCH(cls, return smul_t<C>(l, pk, c, k, out, count));
+  return hipErrorInvalidValue;
+}
+
+template <int C>
+static hipError_t enc_crt_t(const Launch& l, const SkConst& sk, const uint32_t* m, int m_limbs,
+                            const uint32_t* r, uint32_t* c, size_t count, uint32_t* stage) {
+  if (sk.h[0].s2.nl > NL2_MAX || stage == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_encrypt_crt_half<typename Geos<C>::Gp>), dim3(l.grid), dim3(64), 0,
+                     (hipStream_t)l.stream, sk, m, m_limbs, r, count, l.scratch, l.slot_words,
+                     l.window, stage);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_garner_crt, dim3((unsigned)((count + 63) / 64)), dim3(64), 0,
+                     (hipStream_t)l.stream, sk, stage, c, count, l.err);
+  return hipGetLastError();
+}
+hipError_t launch_encrypt_crt(int cls, const Launch& l, const SkConst& sk, const uint32_t* m,
+                              int m_limbs, const uint32_t* r, uint32_t* c, size_t count,
+                              uint32_t* stage) {
+  PC2_DISPATCH(cls, return enc_crt_t<C>(l, sk, m, m_limbs, r, c, count, stage));
   return hipErrorInvalidValue;
 }
 

@@ -9,7 +9,8 @@ namespace pc2k {
 enum Op {
   OP_ENC = 0, OP_DEC = 1, OP_SUM = 2, OP_SMUL = 3, OP_FUSED = 4,
   OP_ENC_MFMA = 5,  // encryption with the matrix-core product (kernels_mfma.hip)
-  OP_COUNT = 6
+  OP_ENC_CRT = 6,   // key-holder encryption through p^2 and q^2
+  OP_COUNT = 7
 };
 
 const void* kernel_for(int cls, int op);
@@ -27,6 +28,11 @@ hipError_t launch_hom_sum(int cls, const Launch& l, const PkConst& pk, const Ptr
                           uint32_t* out, size_t count);
 hipError_t launch_scalar_mul(int cls, const Launch& l, const PkConst& pk, const uint32_t* c,
                              const uint32_t* k, uint32_t* out, size_t count);
+// key-holder encryption: the two prime halves, then the recombination mod
+// n^2; stage: 2 (nl2 + 1) words per element, count <= DEC_CHUNK per call
+hipError_t launch_encrypt_crt(int cls, const Launch& l, const SkConst& sk, const uint32_t* m,
+                              int m_limbs, const uint32_t* r, uint32_t* c, size_t count,
+                              uint32_t* stage);
 // first phase of the fused path: prod = prod_k Enc(m_k, r_k), 2L limbs per element
 hipError_t launch_enc_prod(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
                            const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count);

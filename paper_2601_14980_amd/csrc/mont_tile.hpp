@@ -120,7 +120,7 @@ __device__ __forceinline__ void semi_normalise(uint32_t (&out)[G::K], const uint
 // --------------------------------------------------------- Montgomery product
 // Digits of b consumed per LDS read (1, 2 or 4).
 #ifndef MM_BSTEP
-#define MM_BSTEP 4
+#define MM_BSTEP 2
 #endif
 // out = a * b * R^-1 mod N (lazy: out < 2N if a, b < 2N; also if a < 4N, b < N).
 // a, N: this lane's K digits; b: the tile's S digits in LDS (16-B aligned).

@@ -281,6 +281,96 @@ __device__ __forceinline__ void dec_half_group(const SkConst& sk, int half,
   }
 }
 
+// Key-holder encryption (the CRT route of Sec. IV applied to f_en): one
+// prime s per wavefront, c_s = (1 + m n mod s^2) r^(n mod s (s-1)) mod s^2
+// for the group gi of 64/Tp elements.  m, r < n < 2 s^2 (balanced primes),
+// so both enter the Montgomery products directly:
+//   pre0:  MM(m, n R)        = m n mod s^2, + 1 -> slot entry 0
+//   pre1:  MM(R^2, r)        = r R
+//   pow:   (r R)^e           (sliding windows of e = n mod s (s-1))
+//   post0: MM(g^m, r^e R)    = c_s
+// Lane 0 of tile t writes c_s (nl2 limbs) and an input-validity word to
+// stage[(2 t + half) (nl2 + 1) ..].
+template <class Gp>
+__device__ __forceinline__ void enc_half_group(const SkConst& sk, int half,
+                                               const uint32_t* __restrict__ m, int m_limbs,
+                                               const uint32_t* __restrict__ r, size_t count,
+                                               size_t gi, uint32_t* lds_all, uint32_t* slots,
+                                               size_t slot_words, int w,
+                                               uint32_t* __restrict__ stage) {
+  constexpr int EPW = 64 / Gp::T;
+  const int tl = threadIdx.x & (Gp::T - 1);
+  const int tile = threadIdx.x / Gp::T;
+  uint32_t* lds = lds_all + tile * Gp::SP;
+  uint32_t* slot = slots + tile * slot_words;
+  const HalfConst& H = sk.h[half];
+  uint32_t N[Gp::K];
+  load_chunk<Gp>(N, H.s2.N, tl);
+  const uint32_t np = H.s2.nprime;
+  const int L = sk.pk.L, nl2 = H.s2.nl;
+  size_t e = gi * EPW + tile;
+  const bool live = e < count;
+  if (!live) e = count - 1;
+  const uint32_t* me = m + e * m_limbs;
+  const uint32_t* re = r + e * L;
+  uint32_t ok = 1;
+  if (tl == 0) ok = encrypt_inputs_ok(sk.pk, me, m_limbs, re);
+  chunk_from_limbs<Gp>(slot, me, m_limbs, 0, tl);
+  chunk_from_limbs<Gp>(slot + Gp::CH, re, L, 0, tl);
+  Program P = empty_program();
+  P.npre = 2;
+  P.pre0_a = op_chunk(slot);
+  P.pre0_b = op_chunk(H.nRs);
+  P.pre0_to_slot = true;
+  P.pre0_add1 = 1;
+  P.pre1_a = op_chunk(H.s2.R2);
+  P.pre1_b = op_chunk(slot + Gp::CH);
+  P.ebits = sk.pk.nbits;
+  P.uniform_e = true;
+  use_schedule(P, H.nsch, w);
+  P.one = H.s2.R1;
+  P.npost = 1;
+  P.post0_a = op_chunk(slot);
+  P.post0_b = op_x();
+  uint32_t x[Gp::K];
+  run_program<Gp, true>(P, x, lds, slot, w, N, np, tl);
+  lds_sync();
+  to_lds<Gp>(lds, x, tl);
+  lds_sync();
+  if (tl == 0) {
+    lds_canonical<Gp>(lds, H.s2);
+    if (live) {
+      uint32_t* dst = stage + (size_t)(2 * tile + half) * (nl2 + 1);
+      for (int i = 0; i < nl2; ++i) dst[i] = lds[i];
+      dst[nl2] = ok;
+    }
+  }
+}
+
+// c = c_q + q^2 ((c_p - c_q) (q^2)^-1 mod p^2), the CRT recombination
+// modulo n^2 = p^2 q^2 (Lemma 1 for the moduli p^2, q^2), one lane per
+// element; writes 2L limbs.  work: 5 nl2 + 2 words.
+__device__ __forceinline__ void garner_crt_elem(const SkConst& sk, const uint32_t* __restrict__ cp,
+                                                const uint32_t* __restrict__ cq, uint32_t* dst,
+                                                int* err, uint32_t* work) {
+  const int n2 = sk.h[0].s2.nl, L2 = 2 * sk.pk.L;
+  const bool good = cp[n2] && cq[n2];
+  const uint32_t* P2 = sk.h[0].s2.Nl;
+  const uint32_t* Q2 = sk.h[1].s2.Nl;
+  uint32_t* d = work;                  // n2
+  uint32_t* h = work + n2;             // n2
+  uint32_t* tmp = work + 2 * n2;       // n2 + 2
+  uint32_t* prod = work + 3 * n2 + 2;  // 2 n2
+  for (int i = 0; i < n2; ++i) d[i] = cp[i];
+  // c_q < q^2 < p^2: one conditional addition of p^2 reduces the difference
+  if (sc_sub(d, n2, cq, n2)) sc_add(d, n2, P2, n2);
+  sc_montmul(h, d, sk.Q2I, P2, sk.p2_n0, n2, tmp);
+  sc_mul(prod, Q2, n2, h, n2);
+  sc_add(prod, 2 * n2, cq, n2);
+  for (int i = 0; i < L2; ++i) dst[i] = (good && i < 2 * n2) ? prod[i] : 0u;
+  if (!good) atomicOr(err, pc2k::ERR_RANGE);
+}
+
 // CRT recombination of one element from its two halves (one lane per element):
 // m = m_q + q ((m_p - m_q) q^-1 mod p), Lemma 1 for the moduli p, q in
 // Garner's form.  work: 5 Ls + 2 words.

@@ -68,12 +68,17 @@ struct HalfConst {
   uint32_t s_n0;         // -s^-1 mod 2^32
   int Ls;
   Sched esch;            // sliding-window schedules of s - 1
+  // key-holder encryption modulo s^2
+  const uint32_t* nRs;   // n R mod s^2 (chunked)
+  Sched nsch;            // sliding-window schedules of n mod s (s - 1)
 };
 
 struct SkConst {
   PkConst pk;
   HalfConst h[2];        // [0] = p, [1] = q
   const uint32_t* QI;    // q^-1 2^(32 Ls) mod p
+  const uint32_t* Q2I;   // (q^2)^-1 2^(32 nl2) mod p^2 (nl2 = limbs of p^2)
+  uint32_t p2_n0;        // -(p^2)^-1 mod 2^32
   int ebits;             // max bit length of p-1, q-1
 };
 

@@ -41,7 +41,8 @@ EXPORTS = [
     "pc2_ctx_create", "pc2_ctx_destroy", "pc2_ctx_sync", "pc2_ctx_take_error",
     "pc2_ctx_reserve", "pc2_ctx_set_option", "pc2_ctx_get_option", "pc2_strerror",
     "pc2_pk_create", "pc2_sk_create", "pc2_sk_public", "pc2_pk_destroy", "pc2_sk_destroy",
-    "pc2_pk_info", "pc2_quantize", "pc2_dequantize", "pc2_encrypt", "pc2_decrypt",
+    "pc2_pk_info", "pc2_quantize", "pc2_dequantize", "pc2_encrypt", "pc2_encrypt_sk",
+    "pc2_decrypt",
     "pc2_hom_add", "pc2_hom_scalar_mul", "pc2_hom_sum", "pc2_enc_sum_dec",
     "pc2_batch_create", "pc2_batch_run", "pc2_batch_destroy", "pc2_autotune",
     "pc2_runner_create", "pc2_runner_group_size", "pc2_runner_launch", "pc2_runner_destroy",
@@ -91,6 +92,7 @@ def _load() -> ctypes.CDLL:
         "pc2_dequantize": (c_int, [P, POINTER(pc2_qparams), P, c_uint32, c_uint64, P,
                                    c_size_t, P]),
         "pc2_encrypt": (c_int, [P, P, c_uint32, P, P, c_size_t, P]),
+        "pc2_encrypt_sk": (c_int, [P, P, c_uint32, P, P, c_size_t, P]),
         "pc2_decrypt": (c_int, [P, P, P, c_size_t, P]),
         "pc2_hom_add": (c_int, [P, P, P, P, c_size_t, P]),
         "pc2_hom_scalar_mul": (c_int, [P, P, P, P, c_size_t, P]),
@@ -283,6 +285,17 @@ def pc2_encrypt(pk: PublicKey, m: torch.Tensor, r: torch.Tensor, c: torch.Tensor
     _check(lib.pc2_encrypt(pk.handle, _dev_ptr(m, torch.int32, "m"), m.shape[1],
                            _dev_ptr(r, torch.int32, "r"), _dev_ptr(c, torch.int32, "c"), count,
                            _stream(stream)), "pc2_encrypt")
+
+
+def pc2_encrypt_sk(sk: SecretKey, m: torch.Tensor, r: torch.Tensor, c: torch.Tensor,
+                   stream=None) -> None:
+    count = _rows(r, sk.L, "r")
+    if m.dim() != 2 or m.shape[0] != count:
+        raise ValueError("m must be [count, m_limbs]")
+    _rows(c, 2 * sk.L, "c")
+    _check(lib.pc2_encrypt_sk(sk.handle, _dev_ptr(m, torch.int32, "m"), m.shape[1],
+                              _dev_ptr(r, torch.int32, "r"), _dev_ptr(c, torch.int32, "c"), count,
+                              _stream(stream)), "pc2_encrypt_sk")
 
 
 def pc2_decrypt(sk: SecretKey, c: torch.Tensor, m: torch.Tensor, stream=None) -> None:

@@ -159,12 +159,20 @@ def run_batching(pc2, gen, ctx, torch, np, args, reps: int = 3) -> dict:
     1024-bit key and odd nodes under a 2048-bit key.  Phases: encrypt every
     node vector; per key group, multiply element j over the nodes whose
     vector reaches j; decrypt both aggregates.  Batched: one persistent
-    graph-captured launch per phase.  Plain: one launch per call."""
+    graph-captured launch per phase.  Plain: one launch per call.  The
+    encryption tile (lanes per ciphertext) and the windows of both key
+    sizes come from the autotuner first; both paths use them."""
     lengths = gen.log_uniform_lengths(BATCH_SEED, BATCH_NODES, 1024, 65536)
     keys = []
+    tuned = {}
     for bits in (1024, 2048):
         p, q = gen.primes_for(BATCH_SEED, bits)
         keys.append(pc2.SecretKey(ctx, bits, p, q))
+        t1 = time.perf_counter()
+        we, wd, te = pc2.pc2_autotune(keys[-1])
+        tuned[str(bits)] = {"enc_lanes": te, "enc_window": we, "dec_window": wd,
+                            "tuning_s": round(time.perf_counter() - t1, 2)}
+        log(f"autotune {bits}-bit: encryption {te} lanes, w {we}; decryption w {wd}")
     xs = gen.normal_vectors(BATCH_SEED, lengths)
     qp = gen.Q_PLAIN
     nodes = []
@@ -253,7 +261,7 @@ def run_batching(pc2, gen, ctx, torch, np, args, reps: int = 3) -> dict:
             "ops": ops, "batched_ops_per_s": round(ops / mb, 1),
             "plain_ops_per_s": round(ops / mp, 1), "batched_over_plain": round(mp / mb, 3),
             "batched_ms": round(mb * 1e3, 2), "plain_ms": round(mp * 1e3, 2),
-            "end_to_end_exact": exact}
+            "autotuned": tuned, "end_to_end_exact": exact}
 
 
 # -------------------------------------------------------- serving (config 5)

@@ -97,8 +97,19 @@ int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
  * digits, the three limb-product matrices of each product on the i8 matrix
  * cores with int32 accumulation, carries resolved on the vector ALUs).  Both
  * give identical results; the other operations always use the VALU engine.
+ * PC2_OPT_TILE: the limb tile of the VALU encryption kernels (pc2_encrypt,
+ * batches and runners of encryptions), i.e. how many lanes of a wavefront
+ * share one ciphertext.  1024-bit keys run with 2 (own) or 4 lanes,
+ * 2048-bit keys with 4 (own) or 8; other sizes have their own tile only.
+ * Values: 0 = automatic (the tile pc2_autotune chose for the key's class,
+ * else the class's own); 2, 4 or 8 = that many lanes where the class has
+ * such a tile, else its own; PC2_TILE_WIDE = the alternative tile of every
+ * class that has one.  Fewer lanes mean more 27/28-bit digits per lane and
+ * fewer lane exchanges per digit; more lanes mean fewer registers and more
+ * resident wavefronts.  Results are identical in every tile.
  * Options apply to calls made after they are set. */
-enum { PC2_OPT_WINDOW = 1, PC2_OPT_MODMUL = 2 };
+enum { PC2_OPT_WINDOW = 1, PC2_OPT_MODMUL = 2, PC2_OPT_TILE = 3 };
+enum { PC2_TILE_AUTO = 0, PC2_TILE_WIDE = 1 };
 enum { PC2_MODMUL_VALU = 0, PC2_MODMUL_MFMA = 1 };
 int pc2_ctx_set_option(pc2_ctx *ctx, int option, int64_t value);
 int pc2_ctx_get_option(pc2_ctx *ctx, int option, int64_t *value);
@@ -268,12 +279,15 @@ int pc2_admm_consensus(pc2_admm *admm, const double *sum, const double *x, doubl
                        double *z, double *u, void *hip_stream);
 int pc2_admm_destroy(pc2_admm *admm);
 
-/* Autotuner: times the exponentiation window w in {4, 5, 6} for encryption
- * and decryption under this key's size class on a device-filling synthetic
- * sample, keeps the fastest in the context (used by later calls and
- * batches of that class) and reports them.  Synchronises the stream;
- * allocates temporary buffers. */
-int pc2_autotune(const pc2_sk *sk, void *hip_stream, int *w_enc, int *w_dec);
+/* Autotuner: times encryption under this key's size class in every limb
+ * tile the class has (see PC2_OPT_TILE) with exponentiation windows w in
+ * {4, 5, 6}, and decryption with w in {4, 5, 6}, on the same synthetic
+ * sample of a few device-filling waves (VALU engine).  Keeps the fastest
+ * tile and windows in the context (used by later calls, batches and runners
+ * of that class while PC2_OPT_TILE and PC2_OPT_WINDOW are 0) and reports
+ * them: w_enc, w_dec, and tile_enc = lanes per ciphertext (any output may be
+ * NULL).  Synchronises the stream; allocates temporary buffers. */
+int pc2_autotune(const pc2_sk *sk, void *hip_stream, int *w_enc, int *w_dec, int *tile_enc);
 
 #ifdef __cplusplus
 }

@@ -23,8 +23,10 @@ struct pc2_ctx {
   size_t scratch_bytes = 0;
   int window = 0;              // 0 = automatic
   int modmul = PC2_MODMUL_VALU;
-  int occ[pc2k::NUM_CLASSES][pc2k::OP_COUNT] = {};  // workgroups per CU (0 = not queried)
-  int tuned[pc2k::NUM_CLASSES][pc2k::OP_COUNT] = {};  // autotuned windows (0 = none)
+  int tile = 0;                // PC2_OPT_TILE: 0 automatic, 1 wide, else lanes per ciphertext
+  int occ[pc2k::NUM_GEOS][pc2k::OP_COUNT] = {};    // workgroups per CU (0 = not queried)
+  int tuned[pc2k::NUM_GEOS][pc2k::OP_COUNT] = {};  // autotuned windows (0 = none)
+  int tuned_geo[pc2k::NUM_CLASSES] = {-1, -1, -1, -1, -1, -1, -1, -1};  // encryption tile
 };
 
 struct pc2_runner {
@@ -73,6 +75,7 @@ struct pc2_pk {
   int cls = 0;
   void* dev = nullptr;  // one allocation holding every constant
   pc2k::PkConst c{};
+  pc2k::PkConst alt{};  // n^2 constants in the alternative tile (ALT_GEO[cls] >= 0)
 };
 
 struct pc2_sk {
@@ -206,9 +209,13 @@ pc2k::Sched sched_const(const uint32_t* base, const SchedOffsets& o) {
   return c;
 }
 
-struct PkOffsets {
+struct GeoOffsets {  // the n^2 constants that depend on the digit geometry
   ModOffsets n2;
-  size_t nR, Rk, n;
+  size_t nR, Rk;
+};
+struct PkOffsets {
+  GeoOffsets g, alt;  // alt: only for classes with an alternative tile
+  size_t n;
   size_t mN, mNp, mR2, mnR, mN28;  // matrix-core product constants
   int mS;
   SchedOffsets nsch;
@@ -243,10 +250,10 @@ std::vector<uint32_t> to_limbs28(const Limbs& v, int S) {
   return out;
 }
 
-PkOffsets add_public(DevBuf& buf, const Limbs& n, int cls, int L) {
-  const pc2k::ClassGeo g = pc2k::CLASS_GEO[cls];
-  Limbs n2 = pc2h::mul(n, n);
-  PkOffsets o{};
+// n^2, n R and the powers R^k mod n^2 in the digit geometry `geo`
+GeoOffsets add_geo(DevBuf& buf, const Limbs& n, const Limbs& n2, int geo, int L) {
+  const pc2k::ClassGeo g = pc2k::CLASS_GEO[geo];
+  GeoOffsets o{};
   o.n2 = add_modulus(buf, n2, g.nD, g.nK, g.nT, 2 * L);
   const uint64_t RB = (uint64_t)g.nD * g.nK * g.nT;
   Limbs nR = pc2h::shl_mod(n, RB, n2);
@@ -262,6 +269,14 @@ PkOffsets add_public(DevBuf& buf, const Limbs& n, int cls, int L) {
     rkm = M.mm(rkm, r1m);
   }
   o.Rk = buf.add(tab);
+  return o;
+}
+
+PkOffsets add_public(DevBuf& buf, const Limbs& n, int cls, int L) {
+  Limbs n2 = pc2h::mul(n, n);
+  PkOffsets o{};
+  o.g = add_geo(buf, n, n2, cls, L);
+  if (pc2k::ALT_GEO[cls] >= 0) o.alt = add_geo(buf, n, n2, pc2k::ALT_GEO[cls], L);
   o.n = buf.add(pc2h::resized(n, L));
   // matrix-core form: R = 2^(28 S), N' = -N^-1 mod R
   const int S = pc2k::MFMA_S[cls];
@@ -289,9 +304,9 @@ PkOffsets add_public(DevBuf& buf, const Limbs& n, int cls, int L) {
 
 pc2k::PkConst pk_const(const uint32_t* base, const PkOffsets& o, int L, int nbits) {
   pc2k::PkConst c{};
-  c.n2 = mod_const(base, o.n2);
-  c.nR = base + o.nR;
-  c.Rk = base + o.Rk;
+  c.n2 = mod_const(base, o.g.n2);
+  c.nR = base + o.g.nR;
+  c.Rk = base + o.g.Rk;
   c.n = base + o.n;
   c.L = L;
   c.nbits = nbits;
@@ -303,6 +318,15 @@ pc2k::PkConst pk_const(const uint32_t* base, const PkOffsets& o, int L, int nbit
   c.mf.S = o.mS;
   c.nsch = sched_const(base, o.nsch);
   return c;
+}
+
+// the same key with the n^2 constants of the alternative tile
+pc2k::PkConst pk_const_alt(const uint32_t* base, const PkOffsets& o, const pc2k::PkConst& c) {
+  pc2k::PkConst a = c;
+  a.n2 = mod_const(base, o.alt.n2);
+  a.nR = base + o.alt.nR;
+  a.Rk = base + o.alt.Rk;
+  return a;
 }
 
 struct HalfOffsets {
@@ -384,29 +408,49 @@ int upload(pc2_ctx* ctx, const DevBuf& buf, void** dev) {
   return PC2_OK;
 }
 
-int auto_window(int cls, int op) {
+int auto_window(int geo, int op) {
   // window width minimising products for the exponent lengths of each class
   // (sliding windows for the wave-uniform exponents of encryption and
   // decryption)
+  const int cls = pc2k::GEO_CLASS[geo];
   if (op == pc2k::OP_SMUL) return 4;
   return cls >= 6 ? 6 : (cls >= 5 ? 5 : (cls >= 3 ? 4 : 3));
 }
 
-int window_for(const pc2_ctx* ctx, int cls, int op) {
+int window_for(const pc2_ctx* ctx, int geo, int op) {
   if (ctx->window) return ctx->window;
-  const int t = ctx->tuned[cls][op == pc2k::OP_FUSED ? pc2k::OP_ENC : op];
-  if (op == pc2k::OP_ENC_MFMA) return t ? t : (cls >= 5 ? 5 : 4);
-  return t ? t : auto_window(cls, op);
+  const int t = ctx->tuned[geo][op == pc2k::OP_FUSED ? pc2k::OP_ENC : op];
+  if (op == pc2k::OP_ENC_MFMA) return t ? t : (geo >= 5 ? 5 : 4);
+  return t ? t : auto_window(geo, op);
 }
 
-int occupancy(pc2_ctx* ctx, int cls, int op) {
-  int& o = ctx->occ[cls][op];
+// Geometry of an encryption under the key class cls: the alternative tile
+// if PC2_OPT_TILE asks for wide tiles or names its lane count, the class's
+// own tile for any other lane count, else (automatic) the autotuned one,
+// else the class's own.
+int enc_geo(const pc2_ctx* ctx, int cls) {
+  const int alt = pc2k::ALT_GEO[cls];
+  if (alt < 0) return cls;
+  if (ctx->tile == PC2_TILE_WIDE) return alt;
+  if (ctx->tile) return pc2k::CLASS_GEO[alt].nT == ctx->tile ? alt : cls;
+  return ctx->tuned_geo[cls] >= 0 ? ctx->tuned_geo[cls] : cls;
+}
+// the key's constants in geometry geo (its own class or its alternative tile)
+const pc2k::PkConst& geo_const(const pc2_pk* pk, int geo) {
+  return geo == pk->cls ? pk->c : pk->alt;
+}
+// the geometry a batched or queued job of operation op runs in
+int job_geo(const pc2_ctx* ctx, const pc2_pk* pk, int op) {
+  return op == pc2k::OP_ENC ? enc_geo(ctx, pk->cls) : pk->cls;
+}
+
+int occupancy(pc2_ctx* ctx, int geo, int op) {
+  int& o = ctx->occ[geo][op];
   if (o == 0) {
     int v = 0;
-    const void* k = op == pc2k::OP_ENC_MFMA ? pc2k::kernel_encrypt_mfma(cls)
-                                            : pc2k::kernel_for(cls, op);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, 64, 0) !=
-            hipSuccess ||
+    const void* k = op == pc2k::OP_ENC_MFMA ? pc2k::kernel_encrypt_mfma(geo)
+                                            : pc2k::kernel_for(geo, op);
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, 64, 0) != hipSuccess ||
         v <= 0)
       v = 1;
     o = v;
@@ -414,15 +458,16 @@ int occupancy(pc2_ctx* ctx, int cls, int op) {
   return o;
 }
 
-// grid + scratch for a Paillier launch over `count` elements.  The scratch
+// grid + scratch for a Paillier launch over `count` elements in geometry
+// geo (the key class, except for an encryption in an alternative tile).  The scratch
 // holds aux_words of per-call staging first (Launch::aux, at the same place
 // for every launch that asks for the same amount), then the tables.
-int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::Launch* l,
+int prepare(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, pc2k::Launch* l,
             void* stream, size_t aux_words = 0) {
-  const int w = window_for(ctx, cls, op);
-  const size_t epb = op == pc2k::OP_ENC_MFMA ? 1 : (size_t)pc2k::elems_per_block(cls);
+  const int w = window_for(ctx, geo, op);
+  const size_t epb = op == pc2k::OP_ENC_MFMA ? 1 : (size_t)pc2k::elems_per_block(geo);
   const size_t groups = (count + epb - 1) / epb;
-  const size_t cap = (size_t)ctx->cus * occupancy(ctx, cls, op);
+  const size_t cap = (size_t)ctx->cus * occupancy(ctx, geo, op);
   l->grid = (int)std::max<size_t>(1, std::min(groups, cap));
   l->window = w;
   l->err = ctx->err;
@@ -431,9 +476,9 @@ int prepare(pc2_ctx* ctx, int cls, int op, size_t count, int Ls, int L, pc2k::La
   size_t words = 0;
   if (op == pc2k::OP_ENC_MFMA) {  // one table of 2^w digit arrays per workgroup
     tiles = 1;
-    words = (pc2k::mfma_digit_bytes(cls) << w) / 4;
+    words = (pc2k::mfma_digit_bytes(geo) << w) / 4;
   } else {
-    pc2k::slot_shape(cls, op, w, Ls, L, &tiles, &words);
+    pc2k::slot_shape(geo, op, w, Ls, L, &tiles, &words);
   }
   words = (words + 3) & ~(size_t)3;
   l->slot_words = words;
@@ -539,6 +584,10 @@ int pc2_ctx_reserve(pc2_ctx* ctx, uint32_t max_nbits) {
     int rc = prepare(ctx, cls, op, big, Ls, L, &l, nullptr);
     if (rc) return rc;
   }
+  if (pc2k::ALT_GEO[cls] >= 0) {
+    int rc = prepare(ctx, pc2k::ALT_GEO[cls], pc2k::OP_ENC, big, Ls, L, &l, nullptr);
+    if (rc) return rc;
+  }
   return PC2_OK;
 }
 
@@ -556,6 +605,12 @@ int pc2_ctx_set_option(pc2_ctx* ctx, int option, int64_t value) {
     }
     return PC2_E_UNSUPPORTED;
   }
+  if (option == PC2_OPT_TILE) {
+    if (value != 0 && value != PC2_TILE_WIDE && value != 2 && value != 4 && value != 8)
+      return PC2_E_INVAL;
+    ctx->tile = (int)value;
+    return PC2_OK;
+  }
   return PC2_E_INVAL;
 }
 
@@ -563,6 +618,7 @@ int pc2_ctx_get_option(pc2_ctx* ctx, int option, int64_t* value) {
   if (!ctx || !value) return PC2_E_INVAL;
   if (option == PC2_OPT_WINDOW) *value = ctx->window;
   else if (option == PC2_OPT_MODMUL) *value = ctx->modmul;
+  else if (option == PC2_OPT_TILE) *value = ctx->tile;
   else return PC2_E_INVAL;
   return PC2_OK;
 }
@@ -592,6 +648,7 @@ int pc2_pk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* n_limbs, pc2_pk*
   pk->L = L;
   pk->cls = cls;
   pk->c = pk_const((const uint32_t*)pk->dev, o, L, nb);
+  if (pc2k::ALT_GEO[cls] >= 0) pk->alt = pk_const_alt((const uint32_t*)pk->dev, o, pk->c);
   *out = pk;
   return PC2_OK;
 }
@@ -652,6 +709,7 @@ int pc2_sk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* p_limbs, const u
   sk->pk.cls = cls;
   sk->pk.dev = nullptr;
   sk->pk.c = pk_const(base, po, L, nb);
+  if (pc2k::ALT_GEO[cls] >= 0) sk->pk.alt = pk_const_alt(base, po, sk->pk.c);
   sk->c.pk = sk->pk.c;
   sk->c.h[0] = half_const(base, hp);
   sk->c.h[1] = half_const(base, hq);
@@ -733,9 +791,11 @@ int pc2_encrypt(const pc2_pk* pk, const uint32_t* m, uint32_t m_limbs, const uin
     return status_of(
         pc2k::launch_encrypt_mfma(pk->cls, l, pk->c, m, (int)m_limbs, r, c, count));
   }
-  int rc = prepare(pk->ctx, pk->cls, pc2k::OP_ENC, count, 0, pk->L, &l, stream);
+  const int geo = enc_geo(pk->ctx, pk->cls);
+  int rc = prepare(pk->ctx, geo, pc2k::OP_ENC, count, 0, pk->L, &l, stream);
   if (rc) return rc;
-  return status_of(pc2k::launch_encrypt(pk->cls, l, pk->c, m, (int)m_limbs, r, c, count));
+  return status_of(
+      pc2k::launch_encrypt(geo, l, geo_const(pk, geo), m, (int)m_limbs, r, c, count));
 }
 
 int pc2_decrypt(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count, void* stream) {
@@ -897,16 +957,16 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
       ptr_words += 2 * (size_t)j.K;
     }
     if (op == pc2k::OP_DEC) Ls = std::max(Ls, j.sk->c.h[0].Ls);
-    const int c = pk->cls;
-    if (ca < 0 || ca == c) ca = c;
-    else if (cb < 0 || cb == c) cb = c;
+    const int g = job_geo(ctx, pk, op);
+    if (ca < 0 || ca == g) ca = g;
+    else if (cb < 0 || cb == g) cb = g;
     else return PC2_E_UNSUPPORTED;
   }
   if (ca < 0) return PC2_E_INVAL;  // every job empty
   if (cb < 0) cb = ca;
   const int pair = pc2k::batch_pair(ca, cb);
   if (pair < 0) return PC2_E_UNSUPPORTED;
-  const int pa = pc2k::batch_pair_class(pair, 0), pb = pc2k::batch_pair_class(pair, 1);
+  const int pa = pc2k::batch_pair_geo(pair, 0), pb = pc2k::batch_pair_geo(pair, 1);
   pc2_batch* b = new (std::nothrow) pc2_batch();
   if (!b) return PC2_E_NOMEM;
   b->ctx = ctx;
@@ -924,11 +984,11 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     if (j.count == 0) continue;
     pc2k::BatchJob d{};
     const pc2_pk* pk = (op == pc2k::OP_DEC) ? &j.sk->pk : j.pk;
-    d.cls = pk->cls;
+    d.geo = job_geo(ctx, pk, op);
     d.op = op;
     d.m_limbs = (int)j.m_limbs;
     d.K = (int)j.K;
-    d.pk = pk->c;
+    d.pk = geo_const(pk, d.geo);
     if (op == pc2k::OP_DEC) d.sk = j.sk->c;
     d.in0 = j.in0;
     d.in1 = j.in1;
@@ -942,12 +1002,13 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     ptr_off.push_back(off);
     dj.push_back(d);
   }
+  const int first_geo = pc2k::GEO_CLASS[pa] >= pc2k::GEO_CLASS[pb] ? pa : pb;
   for (int pass = 0; pass < 2; ++pass) {
-    const int want = pass == 0 ? std::max(pa, pb) : std::min(pa, pb);
+    const int want = pass == 0 ? first_geo : (first_geo == pa ? pb : pa);
     if (pass == 1 && pa == pb) break;
     for (size_t ji = 0; ji < dj.size(); ++ji) {
-      if (dj[ji].cls != want) continue;
-      const size_t epw = (size_t)pc2k::elems_per_block(dj[ji].cls);
+      if (dj[ji].geo != want) continue;
+      const size_t epw = (size_t)pc2k::elems_per_block(dj[ji].geo);
       const size_t groups = (dj[ji].count + epw - 1) / epw;
       for (size_t g = 0; g < groups; ++g) items.push_back(pc2k::BatchItem{(int)ji, 0, g});
     }
@@ -1053,16 +1114,24 @@ int pc2_batch_destroy(pc2_batch* b) {
 }
 
 // -------------------------------------------------------------- autotune
-int pc2_autotune(const pc2_sk* sk, void* hip_stream, int* w_enc, int* w_dec) {
+// Times encryption in each tile the key's class has (lanes per ciphertext)
+// with windows 4..6, and decryption with windows 4..6, on a few
+// device-filling waves of elements; keeps the fastest choices in the context.
+int pc2_autotune(const pc2_sk* sk, void* hip_stream, int* w_enc, int* w_dec, int* tile_enc) {
   if (!sk || !sk->ctx) return PC2_E_INVAL;
   pc2_ctx* ctx = sk->ctx;
   if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
   const int cls = sk->pk.cls, L = sk->pk.L;
-  // one device-filling wave of elements per trial
-  const size_t count = (size_t)ctx->cus * occupancy(ctx, cls, pc2k::OP_ENC) *
-                       (size_t)pc2k::elems_per_block(cls);
-  // the work of a fixed-window exponentiation does not depend on the data:
-  // m = 0, r = 1 is valid under every key
+  int geos[2] = {cls, pc2k::ALT_GEO[cls]};
+  const int ngeo = geos[1] >= 0 ? 2 : 1;
+  // the same element count for every candidate: four waves of the widest
+  size_t count = 0;
+  for (int g = 0; g < ngeo; ++g)
+    count = std::max(count, (size_t)ctx->cus * occupancy(ctx, geos[g], pc2k::OP_ENC) *
+                                (size_t)pc2k::elems_per_block(geos[g]));
+  count *= 4;
+  // the work of the exponentiations does not depend on the data: m = 0,
+  // r = 1 is valid under every key
   std::vector<uint32_t> hm(count, 0), hr(count * L, 0);
   for (size_t i = 0; i < count; ++i) hr[i * L] = 1;
   uint32_t *m = nullptr, *r = nullptr, *c = nullptr, *d = nullptr;
@@ -1076,34 +1145,44 @@ int pc2_autotune(const pc2_sk* sk, void* hip_stream, int* w_enc, int* w_dec) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = PC2_E_DEVICE;
-  const int saved_window = ctx->window;
-  int best[2] = {0, 0};
-  for (int which = 0; which < 2 && !rc; ++which) {
-    float best_ms = 1e30f;
+  const int saved_window = ctx->window, saved_tile = ctx->tile, saved_modmul = ctx->modmul;
+  ctx->modmul = PC2_MODMUL_VALU;
+  int best_w[2] = {0, 0}, best_geo = cls;
+  float best_ms[2] = {1e30f, 1e30f};
+  // trials: (encryption, geometry) for each tile, then decryption
+  for (int trial = 0; trial <= ngeo && !rc; ++trial) {
+    const bool dec = trial == ngeo;
+    if (!dec) ctx->tile = pc2k::CLASS_GEO[geos[trial]].nT;
     for (int w = 4; w <= 6 && !rc; ++w) {
       ctx->window = w;
       for (int rep = 0; rep < 2 && !rc; ++rep) {  // rep 0 warms up (and sizes scratch)
         if (hipEventRecord(e0, (hipStream_t)hip_stream) != hipSuccess) rc = PC2_E_DEVICE;
-        int st = which == 0 ? pc2_encrypt(&sk->pk, m, 1, r, c, count, hip_stream)
-                            : pc2_decrypt(sk, c, d, count, hip_stream);
+        int st = dec ? pc2_decrypt(sk, c, d, count, hip_stream)
+                     : pc2_encrypt(&sk->pk, m, 1, r, c, count, hip_stream);
         if (st) rc = st;
         if (!rc && (hipEventRecord(e1, (hipStream_t)hip_stream) != hipSuccess ||
                     hipEventSynchronize(e1) != hipSuccess))
           rc = PC2_E_DEVICE;
         float ms = 0;
-        if (!rc && rep == 1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-          best_ms = ms;
-          best[which] = w;
+        if (!rc && rep == 1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            ms < best_ms[dec]) {
+          best_ms[dec] = ms;
+          best_w[dec] = w;
+          if (!dec) best_geo = geos[trial];
         }
       }
     }
   }
   ctx->window = saved_window;
+  ctx->tile = saved_tile;
+  ctx->modmul = saved_modmul;
   if (!rc) {
-    ctx->tuned[cls][pc2k::OP_ENC] = best[0];
-    ctx->tuned[cls][pc2k::OP_DEC] = best[1];
-    if (w_enc) *w_enc = best[0];
-    if (w_dec) *w_dec = best[1];
+    ctx->tuned_geo[cls] = best_geo;
+    ctx->tuned[best_geo][pc2k::OP_ENC] = best_w[0];
+    ctx->tuned[cls][pc2k::OP_DEC] = best_w[1];
+    if (w_enc) *w_enc = best_w[0];
+    if (w_dec) *w_dec = best_w[1];
+    if (tile_enc) *tile_enc = pc2k::CLASS_GEO[best_geo].nT;
     rc = pc2_ctx_take_error(ctx);
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -1158,19 +1237,20 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
     const int L = (int)((max_nbits + 31) / 32);
     const int Ls = std::min(L / 2 + 2, pc2k::LS_MAX);
     r->ls = Ls;
-    for (int c = 0; c <= cls; ++c) {
-      const int pair = pc2k::batch_pair(c, c);
-      if (pair < 0) continue;
-      const int w = std::max(window_for(ctx, c, op), 6);
+    for (int g = 0; g < pc2k::NUM_GEOS; ++g) {
+      if (pc2k::GEO_CLASS[g] > cls) continue;
+      const int pair = pc2k::batch_pair(g, g);
+      if (pair < 0 || !pc2k::batch_kernel(op, pair)) continue;
+      const int w = std::max(window_for(ctx, g, op), 6);
       int t = 0;
       size_t wd = 0;
-      pc2k::batch_slot_shape(op, c, w, Ls, &t, &wd);
+      pc2k::batch_slot_shape(op, g, w, Ls, &t, &wd);
       tiles = std::max(tiles, t);
       words = std::max(words, wd);
     }
-    for (int pair = 0; pair < 8; ++pair) {
+    for (int pair = 0; pair < pc2k::batch_npairs(); ++pair) {
       const void* k = pc2k::batch_kernel(op, pair);
-      if (!k) break;
+      if (!k) continue;
       int occ = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 64, 0) == hipSuccess)
         occ_max = std::max(occ_max, occ);
@@ -1193,8 +1273,8 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
 }
 
 int pc2_runner_group_size(const pc2_pk* pk, int op_abi, uint32_t* elems) {
-  if (!pk || !elems || op_from_abi(op_abi) < 0) return PC2_E_INVAL;
-  *elems = (uint32_t)pc2k::elems_per_block(pk->cls);
+  if (!pk || !pk->ctx || !elems || op_from_abi(op_abi) < 0) return PC2_E_INVAL;
+  *elems = (uint32_t)pc2k::elems_per_block(job_geo(pk->ctx, pk, op_from_abi(op_abi)));
   return PC2_OK;
 }
 
@@ -1211,7 +1291,8 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     if (op_from_abi(j.op) != op) return PC2_E_INVAL;
     const pc2_pk* pk = (op == pc2k::OP_DEC) ? (j.sk ? &j.sk->pk : nullptr) : j.pk;
     if (!pk || pk->ctx != ctx || !j.out || pk->cls > r->max_cls) return PC2_E_INVAL;
-    const size_t epw = (size_t)pc2k::elems_per_block(pk->cls);
+    const int g = job_geo(ctx, pk, op);
+    const size_t epw = (size_t)pc2k::elems_per_block(g);
     if (first[i] + ngroups[i] > (j.count + epw - 1) / epw) return PC2_E_INVAL;
     if (op == pc2k::OP_ENC && (!j.in0 || !j.in1 || j.m_limbs < 1 || (int)j.m_limbs > pk->L))
       return PC2_E_INVAL;
@@ -1223,9 +1304,8 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
       nptrs += 2 * (size_t)j.K;
     }
     nitems += ngroups[i];
-    const int c = pk->cls;
-    if (ca < 0 || ca == c) ca = c;
-    else if (cb < 0 || cb == c) cb = c;
+    if (ca < 0 || ca == g) ca = g;
+    else if (cb < 0 || cb == g) cb = g;
     else return PC2_E_UNSUPPORTED;
   }
   if (nitems == 0) return PC2_OK;
@@ -1243,16 +1323,16 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
   auto* hp = (size_t*)(hb + r->jobs_b + r->items_b);
   auto* dp = (size_t*)(db + r->jobs_b + r->items_b);
   size_t pofs = 0, it = 0;
-  const int pa = pc2k::batch_pair_class(pair, 0), pb = pc2k::batch_pair_class(pair, 1);
+  const int pa = pc2k::batch_pair_geo(pair, 0), pb = pc2k::batch_pair_geo(pair, 1);
   for (size_t i = 0; i < njobs; ++i) {
     const pc2_job& j = jobs[i];
     const pc2_pk* pk = (op == pc2k::OP_DEC) ? &j.sk->pk : j.pk;
     pc2k::BatchJob d{};
-    d.cls = pk->cls;
+    d.geo = job_geo(ctx, pk, op);
     d.op = op;
     d.m_limbs = (int)j.m_limbs;
     d.K = (int)j.K;
-    d.pk = pk->c;
+    d.pk = geo_const(pk, d.geo);
     if (op == pc2k::OP_DEC) d.sk = j.sk->c;
     d.in0 = j.in0;
     d.in1 = j.in1;
@@ -1268,11 +1348,12 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     hj[i] = d;
   }
   // most expensive class first
+  const int first_geo = pc2k::GEO_CLASS[pa] >= pc2k::GEO_CLASS[pb] ? pa : pb;
   for (int pass = 0; pass < 2; ++pass) {
-    const int want = pass == 0 ? std::max(pa, pb) : std::min(pa, pb);
+    const int want = pass == 0 ? first_geo : (first_geo == pa ? pb : pa);
     if (pass == 1 && pa == pb) break;
     for (size_t i = 0; i < njobs; ++i) {
-      if (hj[i].cls != want) continue;
+      if (hj[i].geo != want) continue;
       for (size_t g = 0; g < ngroups[i]; ++g) hi[it++] = pc2k::BatchItem{(int)i, 0, first[i] + g};
     }
   }

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64, 2) void k_batch(const pc2k::BatchJob* __restric
     if constexpr (CA == CB) {
       run_item<OP, CA>(job, item.group, lds_all, slots, slot_words, w_a, err);
     } else {
-      if (job.cls == CA)
+      if (job.geo == CA)
         run_item<OP, CA>(job, item.group, lds_all, slots, slot_words, w_a, err);
       else
         run_item<OP, CB>(job, item.group, lds_all, slots, slot_words, w_b, err);
@@ -83,14 +83,20 @@ __global__ __launch_bounds__(64, 2) void k_batch(const pc2k::BatchJob* __restric
   }
 }
 
-// (CA, CB) pairs with a compiled batch kernel: single classes and the
-// 1024 + 2048-bit mix.
-constexpr int PAIRS[][2] = {{3, 3}, {5, 5}, {6, 6}, {7, 7}, {5, 6}};
+// (CA, CB) pairs of geometry ids with a compiled batch kernel: single
+// classes and the 1024 + 2048-bit mix, each also with the alternative
+// encryption tiles (ids 8 and 9) of those two classes.
+constexpr int PAIRS[][2] = {{3, 3}, {5, 5}, {6, 6}, {7, 7}, {5, 6},
+                            {8, 8}, {9, 9}, {5, 9}, {6, 8}, {8, 9}};
 constexpr int NPAIRS = sizeof(PAIRS) / sizeof(PAIRS[0]);
 
 template <int OP, int P>
 const void* batch_ptr() {
-  return (const void*)&k_batch<OP, PAIRS[P][0], PAIRS[P][1]>;
+  constexpr bool alt = PAIRS[P][0] >= pc2k::NUM_CLASSES || PAIRS[P][1] >= pc2k::NUM_CLASSES;
+  if constexpr (alt && OP != pc2k::OP_ENC)
+    return nullptr;
+  else
+    return (const void*)&k_batch<OP, PAIRS[P][0], PAIRS[P][1]>;
 }
 
 template <int OP>
@@ -101,9 +107,15 @@ const void* batch_kernel_op(int pair) {
     case 2: return batch_ptr<OP, 2>();
     case 3: return batch_ptr<OP, 3>();
     case 4: return batch_ptr<OP, 4>();
+    case 5: return batch_ptr<OP, 5>();
+    case 6: return batch_ptr<OP, 6>();
+    case 7: return batch_ptr<OP, 7>();
+    case 8: return batch_ptr<OP, 8>();
+    case 9: return batch_ptr<OP, 9>();
   }
   return nullptr;
 }
+static_assert(NPAIRS == 10, "one case per pair above");
 
 template <int OP, int C>
 void shape_of(int w, int Ls, int* tiles, size_t* words) {
@@ -119,12 +131,14 @@ void shape_of(int w, int Ls, int* tiles, size_t* words) {
 }
 
 template <int OP>
-void shape_cls(int cls, int w, int Ls, int* tiles, size_t* words) {
-  switch (cls) {
+void shape_geo(int geo, int w, int Ls, int* tiles, size_t* words) {
+  switch (geo) {
     case 3: shape_of<OP, 3>(w, Ls, tiles, words); return;
     case 5: shape_of<OP, 5>(w, Ls, tiles, words); return;
     case 6: shape_of<OP, 6>(w, Ls, tiles, words); return;
     case 7: shape_of<OP, 7>(w, Ls, tiles, words); return;
+    case 8: if constexpr (OP == pc2k::OP_ENC) { shape_of<OP, 8>(w, Ls, tiles, words); return; } break;
+    case 9: if constexpr (OP == pc2k::OP_ENC) { shape_of<OP, 9>(w, Ls, tiles, words); return; } break;
   }
   *tiles = 0;
   *words = 0;
@@ -134,14 +148,16 @@ void shape_cls(int cls, int w, int Ls, int* tiles, size_t* words) {
 
 namespace pc2k {
 
-int batch_pair(int ca, int cb) {
-  if (ca > cb) std::swap(ca, cb);
+int batch_pair(int ga, int gb) {
+  if (ga > gb) std::swap(ga, gb);
   for (int i = 0; i < NPAIRS; ++i)
-    if (PAIRS[i][0] == ca && PAIRS[i][1] == cb) return i;
+    if (PAIRS[i][0] == ga && PAIRS[i][1] == gb) return i;
   return -1;
 }
 
-int batch_pair_class(int pair, int which) { return PAIRS[pair][which]; }
+int batch_pair_geo(int pair, int which) { return PAIRS[pair][which]; }
+
+int batch_npairs() { return NPAIRS; }
 
 const void* batch_kernel(int op, int pair) {
   switch (op) {
@@ -152,11 +168,11 @@ const void* batch_kernel(int op, int pair) {
   return nullptr;
 }
 
-void batch_slot_shape(int op, int cls, int w, int Ls, int* tiles, size_t* words) {
+void batch_slot_shape(int op, int geo, int w, int Ls, int* tiles, size_t* words) {
   switch (op) {
-    case OP_ENC: shape_cls<OP_ENC>(cls, w, Ls, tiles, words); return;
-    case OP_DEC: shape_cls<OP_DEC>(cls, w, Ls, tiles, words); return;
-    case OP_SUM: shape_cls<OP_SUM>(cls, w, Ls, tiles, words); return;
+    case OP_ENC: shape_geo<OP_ENC>(geo, w, Ls, tiles, words); return;
+    case OP_DEC: shape_geo<OP_DEC>(geo, w, Ls, tiles, words); return;
+    case OP_SUM: shape_geo<OP_SUM>(geo, w, Ls, tiles, words); return;
   }
   *tiles = 0;
   *words = 0;

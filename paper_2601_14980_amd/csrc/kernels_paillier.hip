@@ -230,24 +230,42 @@ namespace pc2k {
     case 6: { constexpr int C = 6; EXPR; } \
     case 7: { constexpr int C = 7; EXPR; } \
   }
+// the same over every geometry id, alternative encryption tiles included
+#define PC2_DISPATCH_GEO(geo, EXPR)        \
+  switch (geo) {                           \
+    case 0: { constexpr int C = 0; EXPR; } \
+    case 1: { constexpr int C = 1; EXPR; } \
+    case 2: { constexpr int C = 2; EXPR; } \
+    case 3: { constexpr int C = 3; EXPR; } \
+    case 4: { constexpr int C = 4; EXPR; } \
+    case 5: { constexpr int C = 5; EXPR; } \
+    case 6: { constexpr int C = 6; EXPR; } \
+    case 7: { constexpr int C = 7; EXPR; } \
+    case 8: { constexpr int C = 8; EXPR; } \
+    case 9: { constexpr int C = 9; EXPR; } \
+  }
 
 template <int C>
 static const void* kernel_ptr(int op) {
   using Gn = typename Geos<C>::Gn;
   using Gp = typename Geos<C>::Gp;
-  switch (op) {
-    case OP_ENC: return (const void*)&k_encrypt<Gn>;
-    case OP_DEC: return (const void*)&k_decrypt_half<Gp>;
-    case OP_SUM: return (const void*)&k_hom_sum<Gn>;
-    case OP_SMUL: return (const void*)&k_scalar_mul<Gn>;
-    case OP_FUSED: return (const void*)&k_enc_prod<Gn>;
-    case OP_ENC_CRT: return (const void*)&k_encrypt_crt_half<Gp>;
+  if constexpr (C >= NUM_CLASSES) {  // an alternative tile serves encryption only
+    return op == OP_ENC ? (const void*)&k_encrypt<Gn> : nullptr;
+  } else {
+    switch (op) {
+      case OP_ENC: return (const void*)&k_encrypt<Gn>;
+      case OP_DEC: return (const void*)&k_decrypt_half<Gp>;
+      case OP_SUM: return (const void*)&k_hom_sum<Gn>;
+      case OP_SMUL: return (const void*)&k_scalar_mul<Gn>;
+      case OP_FUSED: return (const void*)&k_enc_prod<Gn>;
+      case OP_ENC_CRT: return (const void*)&k_encrypt_crt_half<Gp>;
+    }
+    return nullptr;
   }
-  return nullptr;
 }
 
-const void* kernel_for(int cls, int op) {
-  PC2_DISPATCH(cls, return kernel_ptr<C>(op));
+const void* kernel_for(int geo, int op) {
+  PC2_DISPATCH_GEO(geo, return kernel_ptr<C>(op));
   return nullptr;
 }
 
@@ -290,14 +308,14 @@ static void slot_shape_t(int op, int w, int Ls, int L, int* tiles, size_t* words
   }
 }
 
-void slot_shape(int cls, int op, int w, int Ls, int L, int* tiles, size_t* words) {
+void slot_shape(int geo, int op, int w, int Ls, int L, int* tiles, size_t* words) {
   *tiles = 0;
   *words = 0;
-  PC2_DISPATCH(cls, slot_shape_t<C>(op, w, Ls, L, tiles, words); return);
+  PC2_DISPATCH_GEO(geo, slot_shape_t<C>(op, w, Ls, L, tiles, words); return);
 }
 
-int elems_per_block(int cls) {
-  PC2_DISPATCH(cls, return 64 / Geos<C>::Gn::T);
+int elems_per_block(int geo) {
+  PC2_DISPATCH_GEO(geo, return 64 / Geos<C>::Gn::T);
   return 0;
 }
 
@@ -309,9 +327,9 @@ static hipError_t enc_t(const Launch& l, const PkConst& pk, const uint32_t* m, i
                      l.window, l.err);
   return hipGetLastError();
 }
-hipError_t launch_encrypt(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
+hipError_t launch_encrypt(int geo, const Launch& l, const PkConst& pk, const uint32_t* m,
                           int m_limbs, const uint32_t* r, uint32_t* c, size_t count) {
-  PC2_DISPATCH(cls, return enc_t<C>(l, pk, m, m_limbs, r, c, count, l.slot_words));
+  PC2_DISPATCH_GEO(geo, return enc_t<C>(l, pk, m, m_limbs, r, c, count, l.slot_words));
   return hipErrorInvalidValue;
 }
 

@@ -13,11 +13,14 @@ enum Op {
   OP_COUNT = 7
 };
 
-const void* kernel_for(int cls, int op);
-void slot_shape(int cls, int op, int w, int Ls, int L, int* tiles, size_t* words);
-int elems_per_block(int cls);          // elements per workgroup pass (modulus n^2)
+// kernel_for, slot_shape, elems_per_block and launch_encrypt take a geometry
+// id (CLASS_GEO: a key class, or an alternative encryption tile); the other
+// launches take the key class.
+const void* kernel_for(int geo, int op);
+void slot_shape(int geo, int op, int w, int Ls, int L, int* tiles, size_t* words);
+int elems_per_block(int geo);          // elements per workgroup pass (modulus n^2)
 
-hipError_t launch_encrypt(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
+hipError_t launch_encrypt(int geo, const Launch& l, const PkConst& pk, const uint32_t* m,
                           int m_limbs, const uint32_t* r, uint32_t* c, size_t count);
 // halves: 2 (Ls + 1) words per element of staging between the two phases;
 // count <= DEC_CHUNK per launch pair
@@ -45,10 +48,13 @@ hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, cons
                                int m_limbs, const uint32_t* r, uint32_t* c, size_t count);
 
 // persistent batch kernels (kernels_batch.hip)
-int batch_pair(int ca, int cb);
-int batch_pair_class(int pair, int which);
+// pairs of geometry ids with a compiled kernel; alternative tiles are
+// compiled for encryption only (batch_kernel returns null otherwise)
+int batch_pair(int ga, int gb);
+int batch_pair_geo(int pair, int which);
+int batch_npairs();
 const void* batch_kernel(int op, int pair);
-void batch_slot_shape(int op, int cls, int w, int Ls, int* tiles, size_t* words);
+void batch_slot_shape(int op, int geo, int w, int Ls, int* tiles, size_t* words);
 hipError_t launch_batch(int op, int pair, int grid, const BatchJob* jobs, const BatchItem* items,
                         int nitems, int* queue, uint32_t* scratch, size_t slot_words, int w_a,
                         int w_b, int* err, void* stream);

@@ -87,9 +87,9 @@ struct PtrList {
 };
 
 // One job of a persistent batch launch (device copy).  All jobs of a launch
-// run the same operation; their key classes may differ.
+// run the same operation; their key classes (or tiles) may differ.
 struct BatchJob {
-  int cls, op, m_limbs, K;
+  int geo, op, m_limbs, K;        // geo: geometry id of the job's key (CLASS_GEO)
   PkConst pk;                     // encrypt, hom_sum
   SkConst sk;                     // decrypt
   const uint32_t* in0;            // encrypt: m; decrypt: c
@@ -124,16 +124,25 @@ inline int class_for_bits(int nbits) {
   return -1;
 }
 
-// geometry numbers per class (mirrors the template instantiations)
+// Digit geometries ("geometry ids").  Ids 0-7 are the key classes' own
+// tiles; the others are alternative tiles for the n^2 products of
+// encryption, with twice the lanes per ciphertext and half the digits per
+// lane (fewer registers, more waves per SIMD, more lane exchanges per digit).
+// The s^2 geometry of an alternative is its class's own.
 struct ClassGeo {
   int nD, nK, nT;  // n^2
   int pD, pK, pT;  // s^2
 };
-constexpr ClassGeo CLASS_GEO[NUM_CLASSES] = {
+constexpr int NUM_GEOS = 10;
+constexpr ClassGeo CLASS_GEO[NUM_GEOS] = {
     {28, 2, 2, 28, 2, 1},   {28, 3, 2, 28, 3, 1},   {28, 5, 2, 28, 5, 1},
     {28, 10, 2, 28, 10, 1}, {28, 19, 2, 28, 19, 1}, {28, 37, 2, 28, 37, 1},
     {27, 38, 4, 28, 37, 2}, {27, 29, 8, 27, 29, 4},
+    {28, 19, 4, 28, 37, 1},  // class 5 (1024-bit keys), 4 lanes per ciphertext
+    {27, 19, 8, 28, 37, 2},  // class 6 (2048-bit keys), 8 lanes per ciphertext
 };
+constexpr int GEO_CLASS[NUM_GEOS] = {0, 1, 2, 3, 4, 5, 6, 7, 5, 6};   // key class of a geometry
+constexpr int ALT_GEO[NUM_CLASSES] = {-1, -1, -1, -1, -1, 8, 9, -1};  // alternative tile, or -1
 
 // Launch configuration chosen by the host for a data call.
 struct Launch {

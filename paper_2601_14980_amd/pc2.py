@@ -31,6 +31,9 @@ PC2_E_UNSUPPORTED = -5
 PC2_E_BUSY = -6
 PC2_OPT_WINDOW = 1
 PC2_OPT_MODMUL = 2
+PC2_OPT_TILE = 3
+PC2_TILE_AUTO = 0
+PC2_TILE_WIDE = 1
 PC2_MODMUL_VALU = 0
 PC2_MODMUL_MFMA = 1
 PC2_OP_ENCRYPT = 1
@@ -102,7 +105,7 @@ def _load() -> ctypes.CDLL:
         "pc2_batch_create": (c_int, [P, POINTER(pc2_job), c_size_t, POINTER(P)]),
         "pc2_batch_run": (c_int, [P, P]),
         "pc2_batch_destroy": (c_int, [P]),
-        "pc2_autotune": (c_int, [P, P, POINTER(c_int), POINTER(c_int)]),
+        "pc2_autotune": (c_int, [P, P, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
         "pc2_runner_create": (c_int, [P, c_int, c_uint32, c_size_t, c_size_t, POINTER(P)]),
         "pc2_runner_group_size": (c_int, [P, c_int, POINTER(c_uint32)]),
         "pc2_runner_launch": (c_int, [P, POINTER(pc2_job), POINTER(c_size_t), POINTER(c_size_t),
@@ -466,11 +469,13 @@ def runner_group_size(pk: PublicKey, op: int) -> int:
     return v.value
 
 
-def pc2_autotune(sk: SecretKey, stream=None) -> tuple[int, int]:
-    """Tune the exponentiation windows of this key's class; returns (w_enc, w_dec)."""
-    we, wd = c_int(), c_int()
-    _check(lib.pc2_autotune(sk.handle, _stream(stream), byref(we), byref(wd)), "pc2_autotune")
-    return we.value, wd.value
+def pc2_autotune(sk: SecretKey, stream=None) -> tuple[int, int, int]:
+    """Tune the encryption tile and the exponentiation windows of this key's
+    class; returns (w_enc, w_dec, lanes per ciphertext in encryption)."""
+    we, wd, te = c_int(), c_int(), c_int()
+    _check(lib.pc2_autotune(sk.handle, _stream(stream), byref(we), byref(wd), byref(te)),
+           "pc2_autotune")
+    return we.value, wd.value, te.value
 
 
 # ---------------------------------------------------------------- marshalling

@@ -146,8 +146,8 @@ def test_batch_rejects_bad_jobs(gpu_ctx, setup):
 def test_autotune_keeps_results(gpu_ctx, setup):
     from paper_2601_14980_amd import pc2
     k = setup["keys"][0]
-    we, wd = pc2.pc2_autotune(k["sk"])
-    assert we in (4, 5, 6) and wd in (4, 5, 6)
+    we, wd, te = pc2.pc2_autotune(k["sk"])
+    assert we in (4, 5, 6) and wd in (4, 5, 6) and te in (2, 4)
     nd = setup["nodes"][0]
     out = torch.zeros_like(nd["c"])
     pc2.pc2_encrypt(k["sk"].public, nd["m"], nd["r"], out)

@@ -17,6 +17,10 @@ passage of the paper it writes out:
 * modular power       -- the bit-serial square-and-multiply skeleton of
                          Algorithm 2, with exact ``%`` in place of the FFT
                          product and Barrett reduction.
+* ciphertext mat-vec  -- Definition 2 with a matrix of constants (eq. (hemul))
+                         followed by Definition 1 with the encrypted offset
+                         alpha: the edge-node update of Sec. III-C
+                         (eq. (itq2)).
 * CRT decryption      -- Lemma 1 / Lemma 2 of Sec. IV applied to the
                          decryption (the paper states the decryption EP can be
                          split the same way as the encryption).  Used only as a
@@ -159,6 +163,37 @@ def hom_scalar_mul(pk: PublicKey, c: int, k: int) -> int:
     if k < 0:
         raise ValueError("negative scalar")
     return pow_plain(c, k, pk.n2)
+
+
+def hom_matvec(pk: PublicKey, B: Sequence[Sequence[int]], cs: Sequence[int],
+               alpha: Sequence[int] | None = None) -> list[int]:
+    """Ciphertext matrix-vector product of the edge-node update (Sec. III-C,
+    eq. (itq2)): row i is alpha_i (+) (B_i (x) c), where (x) is Definition 2
+    with the constants B_ij applied to the ciphertexts c_j (eq. (hemul)) and
+    the results, then alpha_i, are combined by Definition 1:
+
+        out_i = alpha_i * prod_j c_j^(B_ij) mod n^2     (alpha_i = 1 if absent)
+
+    It decrypts to alpha's plaintext + sum_j B_ij m_j mod n.  Ciphertexts and
+    alpha must lie in [0, n^2), the constants must be non-negative integers.
+    """
+    n2 = pk.n2
+    for c in cs:
+        if not (0 <= c < n2):
+            raise ValueError("ciphertext out of [0, n^2)")
+    out = []
+    for i, row in enumerate(B):
+        if len(row) != len(cs):
+            raise ValueError("row length differs from the vector length")
+        acc = 1
+        if alpha is not None:
+            if not (0 <= alpha[i] < n2):
+                raise ValueError("alpha out of [0, n^2)")
+            acc = alpha[i]
+        for bij, cj in zip(row, cs):
+            acc = hom_add(pk, acc, hom_scalar_mul(pk, cj, bij))
+        out.append(acc)
+    return out
 
 
 def enc_sum_dec(sk: SecretKey, ms: Sequence[int], rs: Sequence[int]) -> int:

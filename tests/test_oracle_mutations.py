@@ -15,6 +15,7 @@ PINS_CRYPTO = [
     lambda: pins.test_bruteforce_bijection(5, 7),
     lambda: pins.test_bruteforce_homomorphisms(3, 5),
     pins.test_pow_plain_vs_builtin,
+    lambda: pins.test_matvec_bruteforce_tiny(3, 5),
 ]
 PINS_QUANT = [
     pins.test_quantize_error_bound_and_aggregate,
@@ -28,7 +29,7 @@ def _caught(checks) -> bool:
     for chk in checks:
         try:
             chk()
-        except (AssertionError, ValueError, ArithmeticError, ZeroDivisionError):
+        except (AssertionError, ValueError, ArithmeticError, ZeroDivisionError, LookupError):
             return True
     return False
 
@@ -84,6 +85,39 @@ def _derive_phi_and_wrong_mu(p, q):
 ORIG_DERIVE = O.derive_keys
 
 
+def _matvec_transposed(pk, B, cs, alpha=None):
+    n2 = pk.n2
+    out = []
+    for i, row in enumerate(B):
+        acc = 1 if alpha is None else alpha[i]
+        for j, cj in enumerate(cs):
+            acc = (acc * O.pow_plain(cj, B[j][i], n2)) % n2  # mistake: B transposed
+        out.append(acc)
+    return out
+
+
+def _matvec_no_alpha(pk, B, cs, alpha=None):
+    n2 = pk.n2
+    out = []
+    for row in B:
+        acc = 1                                             # mistake: alpha dropped
+        for bij, cj in zip(row, cs):
+            acc = (acc * O.pow_plain(cj, bij, n2)) % n2
+        out.append(acc)
+    return out
+
+
+def _matvec_skip_first(pk, B, cs, alpha=None):
+    n2 = pk.n2
+    out = []
+    for i, row in enumerate(B):
+        acc = 1 if alpha is None else alpha[i]
+        for bij, cj in list(zip(row, cs))[1:]:             # mistake: column 0 skipped
+            acc = (acc * O.pow_plain(cj, bij, n2)) % n2
+        out.append(acc)
+    return out
+
+
 @pytest.mark.parametrize("name,target,mutant", [
     ("pow square-first", "pow_plain", _pow_square_first),
     ("pow drops top bit", "pow_plain", _pow_drop_last),
@@ -93,6 +127,9 @@ ORIG_DERIVE = O.derive_keys
     ("add as sum", "hom_add", _add_is_sum),
     ("scalar k+1", "hom_scalar_mul", _smul_off_by_one),
     ("phi for lcm", "derive_keys", _derive_phi_and_wrong_mu),
+    ("mat-vec transposed", "hom_matvec", _matvec_transposed),
+    ("mat-vec drops alpha", "hom_matvec", _matvec_no_alpha),
+    ("mat-vec skips a column", "hom_matvec", _matvec_skip_first),
 ])
 def test_crypto_mutants_caught(monkeypatch, name, target, mutant):
     monkeypatch.setattr(O, target, mutant)

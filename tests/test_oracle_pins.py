@@ -9,6 +9,8 @@
 * the CRT route reaching the plain decryption
 * Euler/Carmichael: (r^n)^lambda = 1 (mod n^2)
 * the quantizer's exact error bound and exact aggregate dequantization
+* the ciphertext mat-vec decrypting to the integer mat-vec, and its special
+  cases (identity and zero matrices, one column against built-in pow)
 """
 from __future__ import annotations
 
@@ -35,7 +37,10 @@ def _golden_rows():
         if not line:
             continue
         op, *kv = line.split()
-        rows.append((op, {k: int(v) for k, v in (x.split("=") for x in kv)}))
+        vals = {}
+        for k, v in (x.split("=") for x in kv):
+            vals[k] = [int(t) for t in v.split(",")] if "," in v else int(v)
+        rows.append((op, vals))
     return rows
 
 
@@ -55,7 +60,9 @@ def test_golden_hand_worked_example():
             assert O.hom_add(pk, r["c1"], r["c2"]) == r["c"]
         elif op == "smul":
             assert O.hom_scalar_mul(pk, r["c1"], r["k"]) == r["c"]
-    assert seen == {"key", "enc", "dec", "add", "smul"}
+        elif op == "matvec":
+            assert O.hom_matvec(pk, [r["b"]], r["c"], [r["alpha"]]) == [r["out"]]
+    assert seen == {"key", "enc", "dec", "add", "smul", "matvec"}
 
 
 @pytest.mark.parametrize("p,q", TINY)
@@ -214,3 +221,71 @@ def test_dequantize_rounding_above_2_53():
     # float(int) rounds to nearest even: 2^53 + 1 -> 2^53, 2^53 + 3 -> 2^53 + 4
     assert Q.dequantize((1 << 53) + 1, 0, 0, 1) == float(1 << 53)
     assert Q.dequantize((1 << 53) + 3, 0, 0, 1) == float((1 << 53) + 4)
+
+
+# ------------------------------------------------------ ciphertext mat-vec
+@pytest.mark.parametrize("p,q", TINY[:2])
+def test_matvec_bruteforce_tiny(p, q):
+    """Every 2 x 2 constant matrix with entries < 4 over two fixed
+    ciphertexts: the product decrypts to alpha + B m mod n (Definitions 1-2)."""
+    pk, sk = O.derive_keys(p, q)
+    n = p * q
+    units = [r for r in range(1, n) if math.gcd(r, n) == 1]
+    m = [2, n - 1]
+    cs = [O.encrypt(pk, m[0], units[0]), O.encrypt(pk, m[1], units[-1])]
+    a = [1, 3]
+    alpha = [O.encrypt(pk, a[0], units[1 % len(units)]), O.encrypt(pk, a[1], units[0])]
+    for b00 in range(4):
+        for b01 in range(4):
+            for b10 in range(4):
+                for b11 in range(4):
+                    B = [[b00, b01], [b10, b11]]
+                    out = O.hom_matvec(pk, B, cs, alpha)
+                    for i in range(2):
+                        want = (a[i] + B[i][0] * m[0] + B[i][1] * m[1]) % n
+                        assert O.decrypt(sk, out[i]) == want
+
+
+def test_matvec_decrypts_to_integer_matvec(key):
+    """Rows of 50-bit constants (the quantized matrix of Sec. III-C) against
+    the exact integer mat-vec of the plaintexts."""
+    p, q, pk, sk = key
+    n = pk.n
+    rng = random.Random(n % 10007)
+    rows, cols = (3, 5) if pk.nbits >= 1024 else (4, 9)
+    m = [rng.randrange(n) for _ in range(cols)]
+    rs = gen.gen_r(n, cols + rows, 11, extra=pk.nbits)
+    cs = [O.encrypt(pk, mj, rj) for mj, rj in zip(m, rs)]
+    a = [rng.randrange(n) for _ in range(rows)]
+    alpha = [O.encrypt(pk, ai, ri) for ai, ri in zip(a, rs[cols:])]
+    B = [[rng.getrandbits(50) for _ in range(cols)] for _ in range(rows)]
+    B[0][0] = 0
+    B[-1][-1] = (1 << 50) - 1
+    out = O.hom_matvec(pk, B, cs, alpha)
+    for i in range(rows):
+        want = (a[i] + sum(bij * mj for bij, mj in zip(B[i], m))) % n
+        assert O.decrypt(sk, out[i]) == want
+    # without alpha the offset is the integer 1, an encryption of 0
+    out0 = O.hom_matvec(pk, B[:1], cs)
+    assert O.decrypt(sk, out0[0]) == sum(bij * mj for bij, mj in zip(B[0], m)) % n
+
+
+def test_matvec_special_cases(key):
+    _, _, pk, _ = key
+    n, n2 = pk.n, pk.n2
+    rng = random.Random(pk.nbits)
+    cols = 4
+    cs = [rng.randrange(1, n2) for _ in range(cols)]
+    alpha = [rng.randrange(1, n2) for _ in range(cols)]
+    ident = [[1 if i == j else 0 for j in range(cols)] for i in range(cols)]
+    assert O.hom_matvec(pk, ident, cs, alpha) == [(x * c) % n2 for x, c in zip(alpha, cs)]
+    zero = [[0] * cols for _ in range(2)]
+    assert O.hom_matvec(pk, zero, cs, alpha[:2]) == alpha[:2]
+    assert O.hom_matvec(pk, zero, cs) == [1, 1]
+    ks = [rng.getrandbits(64) for _ in range(3)]
+    one_col = O.hom_matvec(pk, [[k] for k in ks], cs[:1], alpha[:3])
+    assert one_col == [(x * pow(cs[0], k, n2)) % n2 for x, k in zip(alpha, ks)]
+    with pytest.raises(ValueError):
+        O.hom_matvec(pk, [[1]], [n2])
+    with pytest.raises(ValueError):
+        O.hom_matvec(pk, [[1, 2]], cs[:1])

@@ -199,6 +199,47 @@ int pc2_enc_sum_dec(const pc2_sk *sk, const uint32_t *const *m_k, const uint32_t
                     uint32_t K, uint32_t m_limbs, uint32_t *m_out, size_t count,
                     void *stream);
 
+/* ------------------------------------------- ciphertext matrix-vector */
+
+/* The edge node's update in the paper's column form (Sec. III-C, eq. (itq2)):
+ *     out_i = alpha_i * prod_j c_j^(B_ij) mod n^2,   i < rows, j < cols,
+ * i.e. Definition 2 with a matrix of non-negative integer constants B applied
+ * to the ciphertext vector c (eq. (hemul)), then Definition 1 with the
+ * ciphertexts alpha.  It decrypts to Dec(alpha_i) + sum_j B_ij Dec(c_j) mod n.
+ *
+ * A plan holds fixed-base tables of the bases: for column j and window t,
+ * (c_j^(2^(w t)))^d for d = 1 .. 2^w - 1 in Montgomery form, so that a row
+ * costs one modular product per nonzero w-bit digit of its constants and no
+ * squarings; the tables take cols * ceil(ebits / w) * (2^w - 1) entries of
+ * the n^2 digit layout (640 B at 2048 bits).
+ *
+ * pc2_matvec_create: cols >= 1; ebits in 1..64 bounds the constants
+ * (B_ij < 2^ebits); window w in 1..12, or 0 = automatic: the w minimising
+ * ceil(ebits / w) (rows_hint + 2^w) (rows_hint = 0: w = 8) among those whose
+ * tables fit in a quarter of the free device memory.  Allocates the tables
+ * (PC2_E_NOMEM if they do not fit).
+ * pc2_matvec_info: the window and the table bytes of a plan (either may be NULL).
+ * pc2_matvec_load: builds the tables of c ([cols][2L], device) on the stream.
+ *   c_j >= n^2 latches PC2_E_RANGE and zeroes that column's tables.
+ * pc2_matvec_apply: B: device uint64 [rows][cols] row-major; alpha: device
+ *   [rows][2L] or NULL (then alpha_i = 1, the encryption of 0 with r = 1);
+ *   out: device [rows][2L], may be alpha itself (no partial overlap).  Needs a
+ *   completed load on the same stream order.  rows = 0 is a no-op.  A row with
+ *   B_ij >= 2^ebits or alpha_i >= n^2 is written as zero with PC2_E_RANGE
+ *   latched; rows that use a zeroed column come out zero.  Staging for
+ *   partial products (rows split over column chunks to fill the device) is
+ *   allocated on the first call that needs more than the plan holds.
+ * The plan's device memory is owned by the plan; the caller owns c, B, alpha,
+ * out.  A plan is used from one host thread at a time. */
+typedef struct pc2_matvec pc2_matvec;
+int pc2_matvec_create(const pc2_pk *pk, size_t cols, uint32_t ebits, uint32_t window,
+                      size_t rows_hint, pc2_matvec **out);
+int pc2_matvec_info(const pc2_matvec *mv, uint32_t *window, size_t *table_bytes);
+int pc2_matvec_load(pc2_matvec *mv, const uint32_t *c, void *hip_stream);
+int pc2_matvec_apply(pc2_matvec *mv, const uint64_t *B, const uint32_t *alpha, uint32_t *out,
+                     size_t rows, void *hip_stream);
+int pc2_matvec_destroy(pc2_matvec *mv);
+
 /* ------------------------------------------------------ batched launches */
 
 /* One job of a batch.  A batch runs one phase of many edge nodes' work --

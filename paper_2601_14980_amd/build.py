@@ -31,6 +31,7 @@ UNITS = {
     "kernels_paillier.hip": [],
     "kernels_batch.hip": [],
     "kernels_mfma.hip": [],
+    "kernels_matvec.hip": [],
     "kernels_quant.hip": ["-ffp-contract=off"],
     "kernels_admm.hip": ["-ffp-contract=off"],
     "api.cpp": [],

@@ -67,6 +67,18 @@ struct pc2_batch {
   void* graph_stream = nullptr;
 };
 
+struct pc2_matvec {
+  pc2_ctx* ctx = nullptr;
+  const pc2_pk* pk = nullptr;
+  int w = 0, nw = 0, ebits = 0;
+  size_t cols = 0, table_bytes = 0;
+  uint32_t* tab = nullptr;    // fixed-base tables [cols][nw][2^w - 1] entries
+  uint32_t* parts = nullptr;  // partial products of row chunks [chunks][rows][2L]
+  size_t parts_bytes = 0;
+  int cap_table = 1, cap_apply = 1;  // resident workgroups of the two kernels
+  bool loaded = false;
+};
+
 struct pc2_pk {
   pc2_ctx* ctx = nullptr;
   int device = 0;
@@ -1384,6 +1396,156 @@ int pc2_runner_destroy(pc2_runner* r) {
   if (r->scratch) (void)hipFree(r->scratch);
   if (r->copied) (void)hipEventDestroy(r->copied);
   delete r;
+  return PC2_OK;
+}
+
+// ------------------------------------------------------ ciphertext mat-vec
+namespace {
+size_t matvec_table_bytes(int cls, size_t cols, int ebits, int w) {
+  const size_t nw = (size_t)((ebits + w - 1) / w);
+  return cols * nw * (((size_t)1 << w) - 1) * pc2k::matvec_entry_words(cls) * 4;
+}
+int resident_groups(pc2_ctx* ctx, const void* k) {
+  int occ = 0;
+  if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 64, 0) != hipSuccess || occ <= 0)
+    occ = 1;
+  return ctx->cus * occ;
+}
+}  // namespace
+
+int pc2_matvec_create(const pc2_pk* pk, size_t cols, uint32_t ebits, uint32_t window,
+                      size_t rows_hint, pc2_matvec** out) {
+  if (!pk || !pk->ctx || !out || cols == 0 || ebits < 1 || ebits > 64 || window > 12)
+    return PC2_E_INVAL;
+  *out = nullptr;
+  pc2_ctx* ctx = pk->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  int w = (int)window;
+  if (w == 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return PC2_E_DEVICE;
+    double best = 0;
+    for (int c = 1; c <= 12; ++c) {
+      if (matvec_table_bytes(pk->cls, cols, (int)ebits, c) > free_b / 4) break;
+      const double nwc = (double)((ebits + c - 1) / c);
+      // products per column: rows x windows (rows), windows x table entries (tables)
+      const double cost = rows_hint ? nwc * ((double)rows_hint + (double)((1 << c) - 1))
+                                    : (c <= 8 ? 1.0 / c : 1e300);
+      if (w == 0 || cost < best) {
+        w = c;
+        best = cost;
+      }
+    }
+    if (w == 0) return PC2_E_NOMEM;
+  }
+  pc2_matvec* mv = new (std::nothrow) pc2_matvec();
+  if (!mv) return PC2_E_NOMEM;
+  mv->ctx = ctx;
+  mv->pk = pk;
+  mv->w = w;
+  mv->nw = ((int)ebits + w - 1) / w;
+  mv->ebits = (int)ebits;
+  mv->cols = cols;
+  mv->table_bytes = matvec_table_bytes(pk->cls, cols, (int)ebits, w);
+  if (hipMalloc(&mv->tab, mv->table_bytes) != hipSuccess) {
+    delete mv;
+    return PC2_E_NOMEM;
+  }
+  mv->cap_table = resident_groups(ctx, pc2k::kernel_matvec(pk->cls, 0));
+  mv->cap_apply = resident_groups(ctx, pc2k::kernel_matvec(pk->cls, 1));
+  *out = mv;
+  return PC2_OK;
+}
+
+int pc2_matvec_info(const pc2_matvec* mv, uint32_t* window, size_t* table_bytes) {
+  if (!mv) return PC2_E_INVAL;
+  if (window) *window = (uint32_t)mv->w;
+  if (table_bytes) *table_bytes = mv->table_bytes;
+  return PC2_OK;
+}
+
+int pc2_matvec_load(pc2_matvec* mv, const uint32_t* c, void* hip_stream) {
+  if (!mv || !mv->ctx || !c) return PC2_E_INVAL;
+  if (hipSetDevice(mv->ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  const int cls = mv->pk->cls;
+  const size_t epw = (size_t)pc2k::elems_per_block(cls);
+  const size_t groups = (mv->cols + epw - 1) / epw * (size_t)mv->nw;
+  const int grid = (int)std::max<size_t>(1, std::min<size_t>(groups, (size_t)mv->cap_table));
+  int rc = status_of(pc2k::launch_mv_table(cls, grid, mv->pk->c, c, mv->cols, mv->nw, mv->w,
+                                           mv->tab, mv->ctx->err, hip_stream));
+  if (!rc) mv->loaded = true;
+  return rc;
+}
+
+int pc2_matvec_apply(pc2_matvec* mv, const uint64_t* B, const uint32_t* alpha, uint32_t* out,
+                     size_t rows, void* hip_stream) {
+  if (!mv || !mv->ctx) return PC2_E_INVAL;
+  if (rows == 0) return PC2_OK;
+  if (!B || !out || !mv->loaded) return PC2_E_INVAL;
+  pc2_ctx* ctx = mv->ctx;
+  const pc2_pk* pk = mv->pk;
+  const int cls = pk->cls;
+  const size_t L2 = 2 * (size_t)pk->L, row_bytes = L2 * 4;
+  if (alpha && alpha != out) {  // exact aliasing is allowed, partial overlap is not
+    const char *a0 = (const char*)alpha, *o0 = (const char*)out;
+    if (a0 < o0 + rows * row_bytes && o0 < a0 + rows * row_bytes) return PC2_E_INVAL;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  // column chunks: the count (up to the aggregation limit) whose whole
+  // wavefront groups fill the resident capacity best; fewer on a near tie
+  const size_t epw = (size_t)pc2k::elems_per_block(cls);
+  const size_t gpc = (rows + epw - 1) / epw;
+  const size_t cap = (size_t)mv->cap_apply;
+  size_t nch = 1, chunk_cols = mv->cols;
+  double best = -1;
+  for (size_t c = 1; c <= std::min(mv->cols, (size_t)pc2k::RK_MAX); ++c) {
+    const size_t cc = (mv->cols + c - 1) / c;
+    if ((mv->cols + cc - 1) / cc != c) continue;  // the same split as a smaller count
+    const size_t groups = gpc * c;
+    const double eff = (double)groups / (double)(((groups + cap - 1) / cap) * cap);
+    if (eff > best + 0.02) {
+      best = eff;
+      nch = c;
+      chunk_cols = cc;
+    }
+  }
+  const size_t groups = gpc * nch;
+  const int grid = (int)std::max<size_t>(1, std::min(groups, cap));
+  if (nch == 1)
+    return status_of(pc2k::launch_mv_apply(cls, grid, pk->c, B, rows, mv->cols, mv->ebits,
+                                           mv->nw, mv->w, mv->tab, alpha, 1, chunk_cols, out,
+                                           0, ctx->err, hip_stream));
+  const size_t need = nch * rows * row_bytes;
+  if (need > mv->parts_bytes) {
+    // growing the staging: wait for in-flight work that may use the old one
+    if (hipDeviceSynchronize() != hipSuccess) return PC2_E_DEVICE;
+    if (mv->parts) (void)hipFree(mv->parts);
+    mv->parts = nullptr;
+    mv->parts_bytes = 0;
+    if (hipMalloc(&mv->parts, need) != hipSuccess) return PC2_E_NOMEM;
+    mv->parts_bytes = need;
+  }
+  int rc = status_of(pc2k::launch_mv_apply(cls, grid, pk->c, B, rows, mv->cols, mv->ebits,
+                                           mv->nw, mv->w, mv->tab, alpha, nch, chunk_cols,
+                                           mv->parts, rows * L2, ctx->err, hip_stream));
+  if (rc) return rc;
+  pc2k::PtrList lst{};
+  for (size_t k = 0; k < nch; ++k) lst.p[k] = mv->parts + k * rows * L2;
+  pc2k::Launch l{};
+  l.grid = (int)std::max<size_t>(
+      1, std::min(gpc, (size_t)ctx->cus * occupancy(ctx, cls, pc2k::OP_SUM)));
+  l.err = ctx->err;
+  l.stream = hip_stream;
+  return status_of(pc2k::launch_hom_sum(cls, l, pk->c, lst, (int)nch, out, rows));
+}
+
+int pc2_matvec_destroy(pc2_matvec* mv) {
+  if (!mv || !mv->ctx) return PC2_E_INVAL;
+  (void)hipSetDevice(mv->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (mv->tab) (void)hipFree(mv->tab);
+  if (mv->parts) (void)hipFree(mv->parts);
+  delete mv;
   return PC2_OK;
 }
 

@@ -47,6 +47,17 @@ size_t mfma_digit_bytes(int cls);
 hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
                                int m_limbs, const uint32_t* r, uint32_t* c, size_t count);
 
+// ciphertext matrix-vector product (kernels_matvec.hip), by key class:
+// which = 0 the table kernel, 1 the row kernel
+const void* kernel_matvec(int cls, int which);
+size_t matvec_entry_words(int cls);  // words of one table entry (chunked n^2 digits)
+hipError_t launch_mv_table(int cls, int grid, const PkConst& pk, const uint32_t* c, size_t cols,
+                           int nw, int w, uint32_t* tab, int* err, void* stream);
+hipError_t launch_mv_apply(int cls, int grid, const PkConst& pk, const uint64_t* B, size_t rows,
+                           size_t cols, int ebits, int nw, int w, const uint32_t* tab,
+                           const uint32_t* alpha, size_t nchunks, size_t chunk_cols,
+                           uint32_t* out, size_t chunk_stride, int* err, void* stream);
+
 // persistent batch kernels (kernels_batch.hip)
 // pairs of geometry ids with a compiled kernel; alternative tiles are
 // compiled for encryption only (batch_kernel returns null otherwise)

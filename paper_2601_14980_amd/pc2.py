@@ -47,6 +47,8 @@ EXPORTS = [
     "pc2_pk_info", "pc2_quantize", "pc2_dequantize", "pc2_encrypt", "pc2_encrypt_sk",
     "pc2_decrypt",
     "pc2_hom_add", "pc2_hom_scalar_mul", "pc2_hom_sum", "pc2_enc_sum_dec",
+    "pc2_matvec_create", "pc2_matvec_info", "pc2_matvec_load", "pc2_matvec_apply",
+    "pc2_matvec_destroy",
     "pc2_batch_create", "pc2_batch_run", "pc2_batch_destroy", "pc2_autotune",
     "pc2_runner_create", "pc2_runner_group_size", "pc2_runner_launch", "pc2_runner_destroy",
     "pc2_admm_create", "pc2_admm_local", "pc2_admm_consensus", "pc2_admm_destroy",
@@ -102,6 +104,11 @@ def _load() -> ctypes.CDLL:
         "pc2_hom_sum": (c_int, [P, POINTER(P), c_uint32, P, c_size_t, P]),
         "pc2_enc_sum_dec": (c_int, [P, POINTER(P), POINTER(P), c_uint32, c_uint32, P,
                                     c_size_t, P]),
+        "pc2_matvec_create": (c_int, [P, c_size_t, c_uint32, c_uint32, c_size_t, POINTER(P)]),
+        "pc2_matvec_info": (c_int, [P, POINTER(c_uint32), POINTER(c_size_t)]),
+        "pc2_matvec_load": (c_int, [P, P, P]),
+        "pc2_matvec_apply": (c_int, [P, P, P, P, c_size_t, P]),
+        "pc2_matvec_destroy": (c_int, [P]),
         "pc2_batch_create": (c_int, [P, POINTER(pc2_job), c_size_t, POINTER(P)]),
         "pc2_batch_run": (c_int, [P, P]),
         "pc2_batch_destroy": (c_int, [P]),
@@ -359,6 +366,56 @@ def pc2_enc_sum_dec(sk: SecretKey, ms: Sequence[torch.Tensor], rs: Sequence[torc
     _check(lib.pc2_enc_sum_dec(sk.handle, mp, rp, len(ms), m_limbs,
                                _dev_ptr(m_out, torch.int32, "m_out"), count, _stream(stream)),
            "pc2_enc_sum_dec")
+
+
+# -------------------------------------------------------- ciphertext mat-vec
+class MatVec:
+    """Plan of the ciphertext matrix-vector product (pc2_matvec):
+    out_i = alpha_i * prod_j c_j^(B_ij) mod n^2 over fixed-base tables of c."""
+
+    def __init__(self, pk: PublicKey, cols: int, ebits: int = 64, window: int = 0,
+                 rows_hint: int = 0):
+        h = c_void_p()
+        _check(lib.pc2_matvec_create(pk.handle, cols, ebits, window, rows_hint, byref(h)),
+               "pc2_matvec_create")
+        self.handle = h
+        self.pk = pk
+        self.cols = cols
+        w, nb = c_uint32(), c_size_t()
+        _check(lib.pc2_matvec_info(h, byref(w), byref(nb)), "pc2_matvec_info")
+        self.window = w.value
+        self.table_bytes = nb.value
+
+    def load(self, c: torch.Tensor, stream=None) -> None:
+        if _rows(c, 2 * self.pk.L, "c") != self.cols:
+            raise ValueError("c must hold one ciphertext per column")
+        _check(lib.pc2_matvec_load(self.handle, _dev_ptr(c, torch.int32, "c"), _stream(stream)),
+               "pc2_matvec_load")
+
+    def apply(self, B: torch.Tensor, out: torch.Tensor, alpha: Optional[torch.Tensor] = None,
+              stream=None) -> None:
+        rows = _rows(out, 2 * self.pk.L, "out")
+        if B.dim() != 2 or B.shape[0] != rows or B.shape[1] != self.cols:
+            raise ValueError("B must be [rows][cols]")
+        a = None
+        if alpha is not None:
+            if _rows(alpha, 2 * self.pk.L, "alpha") != rows:
+                raise ValueError("alpha must have one ciphertext per row")
+            a = _dev_ptr(alpha, torch.int32, "alpha")
+        _check(lib.pc2_matvec_apply(self.handle, _dev_ptr(B, torch.int64, "B"), a,
+                                    _dev_ptr(out, torch.int32, "out"), rows, _stream(stream)),
+               "pc2_matvec_apply")
+
+    def close(self) -> None:
+        if self.handle:
+            lib.pc2_matvec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------- batches

@@ -352,6 +352,63 @@ ADMM_BITS = 3072
 ADMM_M, ADMM_N, ADMM_K = 4096, 16384, 32
 
 
+# -------------------------------------------------------- 4096-bit keys
+KEY4096_SEED = 7
+
+
+def run_key4096(pc2, gen, ctx, torch, np, args) -> dict:
+    """Encryption and CRT decryption under a 4096-bit key (n^2 of 8192 bits),
+    the largest key of the paper's timing table: quantized N(0,1) data, one
+    launch per call, then every decryption compared with its plaintext."""
+    count = args.key4096_count
+    nbits = 4096
+    t0 = time.perf_counter()
+    p, q = gen.primes_for(KEY4096_SEED, nbits)
+    sk = pc2.SecretKey(ctx, nbits, p, q)
+    log(f"4096-bit key generated in {time.perf_counter() - t0:.1f}s")
+    L = sk.L
+    rng = np.random.default_rng(gen.seed_seq(KEY4096_SEED, gen.DATA))
+    qp = gen.Q_PLAIN
+    x = torch.from_numpy(rng.standard_normal(count)).cuda()
+    mq = torch.empty(count, dtype=torch.int64, device="cuda")
+    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, x, mq)
+    m2 = mq.view(torch.int32).reshape(count, 2)
+    r = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, count, L, KEY4096_SEED))
+    c = torch.empty((count, 2 * L), dtype=torch.int32, device="cuda")
+    d = torch.empty((count, L), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    te, td = [], []
+    for rep in range(3):                      # rep 0 warms up
+        ev[0].record(stream)
+        pc2.pc2_encrypt(sk.public, m2, r, c)
+        ev[1].record(stream)
+        pc2.pc2_decrypt(sk, c, d)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            te.append(ev[0].elapsed_time(ev[1]))
+            td.append(ev[1].elapsed_time(ev[2]))
+    ok = ctx.sync() == 0
+    dh = d.cpu()
+    ok &= bool(torch.equal(dh[:, :2], m2.cpu())) and bool((dh[:, 2:] == 0).all())
+    w = 6
+    mm_e, prod_e = montgomery_products_per_encrypt(nbits, sk.n, w)
+    mm_d, prod_d = montgomery_products_per_decrypt(p, q, w)
+    me, md = float(np.median(te)) / 1e3, float(np.median(td)) / 1e3
+    achieved = prod_e * count / me
+    log(f"4096-bit: encrypt {count} in {me * 1e3:.1f} ms, decrypt in {md * 1e3:.1f} ms, "
+        f"round trip exact {ok}")
+    return {"workload": f"4096-bit key (n^2 8192 bits), {count} quantized N(0,1) values: "
+                        "encrypt, then decrypt, one launch per call",
+            "enc_per_s": round(count / me, 1), "dec_per_s": round(count / md, 1),
+            "enc_dec_ops_per_s": round(2 * count / (me + md), 1),
+            "mm_per_encrypt": mm_e, "mm_per_decrypt": mm_d,
+            "encrypt_T_products_per_s": round(achieved / 1e12, 3),
+            "encrypt_frac_of_peak": round(achieved / PEAK_PRODUCTS, 4),
+            "round_trip_exact": bool(ok)}
+
+
 # ------------------------------------------- ciphertext mat-vec (column form)
 MATVEC_SEED = 6
 MATVEC_EBITS = 50
@@ -526,6 +583,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--no-admm", action="store_true")
     ap.add_argument("--no-matvec", action="store_true")
+    ap.add_argument("--no-key4096", action="store_true")
+    ap.add_argument("--key4096-count", type=int, default=32768)
     ap.add_argument("--matvec-dim", type=int, default=9000)
     ap.add_argument("--admm-iters", type=int, default=2)
     ap.add_argument("--admm-warmup", type=int, default=1)
@@ -693,6 +752,7 @@ def main() -> int:
     batching = None if args.no_batching else run_batching(pc2, gen, ctx, torch, np, args)
     serving = None if args.no_serving else run_serving(pc2, gen, ctx, sk, torch, np, args)
     matvec = None if args.no_matvec else run_matvec(pc2, gen, ctx, sk, torch, np, args)
+    key4096 = None if args.no_key4096 else run_key4096(pc2, gen, ctx, torch, np, args)
     admm = None if args.no_admm else run_admm(pc2, gen, ctx, torch, np, args,
                                               args.admm_modmul.split(","))
 
@@ -735,6 +795,7 @@ def main() -> int:
         "batching": batching,
         "serving": serving,
         "matvec": matvec,
+        "key4096": key4096,
         "admm": admm,
         "host": platform.node(),
     }

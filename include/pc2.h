@@ -120,7 +120,7 @@ const char *pc2_strerror(int status);
 
 /* Public key (Sec. III-B key generation: public key (n, g), g = n + 1).
  * n: host array of ceil(nbits/32) limbs, odd, 15 <= n < 2^nbits, with
- * 2 <= nbits <= 3072. */
+ * 2 <= nbits <= 4096. */
 int pc2_pk_create(pc2_ctx *ctx, uint32_t nbits, const uint32_t *n, pc2_pk **out);
 
 /* Private key from the primes p and q (Sec. III-B: n = pq,
@@ -245,8 +245,8 @@ int pc2_matvec_destroy(pc2_matvec *mv);
 /* One job of a batch.  A batch runs one phase of many edge nodes' work --
  * all their encryptions, all their aggregations or all their decryptions --
  * in ONE persistent launch, whatever the vector lengths, under keys of up to
- * two size classes (supported mixes: one class of 256, 1024, 2048 or 3072
- * bits, or 1024 with 2048 bits).  Results are identical to the one-call-per-
+ * two size classes (supported mixes: one class of 256, 1024, 2048, 3072 or
+ * 4096 bits, or 1024 with 2048 bits).  Results are identical to the one-call-per-
  * job entry points above. */
 enum { PC2_OP_ENCRYPT = 1, PC2_OP_HOM_SUM = 2, PC2_OP_DECRYPT = 3 };
 typedef struct {

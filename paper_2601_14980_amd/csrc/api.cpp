@@ -26,7 +26,7 @@ struct pc2_ctx {
   int tile = 0;                // PC2_OPT_TILE: 0 automatic, 1 wide, else lanes per ciphertext
   int occ[pc2k::NUM_GEOS][pc2k::OP_COUNT] = {};    // workgroups per CU (0 = not queried)
   int tuned[pc2k::NUM_GEOS][pc2k::OP_COUNT] = {};  // autotuned windows (0 = none)
-  int tuned_geo[pc2k::NUM_CLASSES] = {-1, -1, -1, -1, -1, -1, -1, -1};  // encryption tile
+  int tuned_geo[pc2k::NUM_CLASSES] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};  // encryption tile
 };
 
 struct pc2_runner {

@@ -85,9 +85,9 @@ __global__ __launch_bounds__(64, 2) void k_batch(const pc2k::BatchJob* __restric
 
 // (CA, CB) pairs of geometry ids with a compiled batch kernel: single
 // classes and the 1024 + 2048-bit mix, each also with the alternative
-// encryption tiles (ids 8 and 9) of those two classes.
-constexpr int PAIRS[][2] = {{3, 3}, {5, 5}, {6, 6}, {7, 7}, {5, 6},
-                            {8, 8}, {9, 9}, {5, 9}, {6, 8}, {8, 9}};
+// encryption tiles (ids 9 and 10) of those two classes.
+constexpr int PAIRS[][2] = {{3, 3}, {5, 5}, {6, 6}, {7, 7}, {8, 8}, {5, 6},
+                            {9, 9}, {10, 10}, {5, 10}, {6, 9}, {9, 10}};
 constexpr int NPAIRS = sizeof(PAIRS) / sizeof(PAIRS[0]);
 
 template <int OP, int P>
@@ -112,10 +112,11 @@ const void* batch_kernel_op(int pair) {
     case 7: return batch_ptr<OP, 7>();
     case 8: return batch_ptr<OP, 8>();
     case 9: return batch_ptr<OP, 9>();
+    case 10: return batch_ptr<OP, 10>();
   }
   return nullptr;
 }
-static_assert(NPAIRS == 10, "one case per pair above");
+static_assert(NPAIRS == 11, "one case per pair above");
 
 template <int OP, int C>
 void shape_of(int w, int Ls, int* tiles, size_t* words) {
@@ -137,8 +138,9 @@ void shape_geo(int geo, int w, int Ls, int* tiles, size_t* words) {
     case 5: shape_of<OP, 5>(w, Ls, tiles, words); return;
     case 6: shape_of<OP, 6>(w, Ls, tiles, words); return;
     case 7: shape_of<OP, 7>(w, Ls, tiles, words); return;
-    case 8: if constexpr (OP == pc2k::OP_ENC) { shape_of<OP, 8>(w, Ls, tiles, words); return; } break;
+    case 8: shape_of<OP, 8>(w, Ls, tiles, words); return;
     case 9: if constexpr (OP == pc2k::OP_ENC) { shape_of<OP, 9>(w, Ls, tiles, words); return; } break;
+    case 10: if constexpr (OP == pc2k::OP_ENC) { shape_of<OP, 10>(w, Ls, tiles, words); return; } break;
   }
   *tiles = 0;
   *words = 0;

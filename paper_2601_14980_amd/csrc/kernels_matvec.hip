@@ -158,6 +158,7 @@ __global__ __launch_bounds__(64, 2) void k_mv_apply(PkConst pk, const uint64_t* 
     case 5: { constexpr int C = 5; EXPR; } \
     case 6: { constexpr int C = 6; EXPR; } \
     case 7: { constexpr int C = 7; EXPR; } \
+    case 8: { constexpr int C = 8; EXPR; } \
   }
 
 }  // namespace

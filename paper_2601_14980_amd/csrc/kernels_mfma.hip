@@ -114,6 +114,7 @@ const void* kernel_encrypt_mfma(int cls) {
     case 5: return mfma_kernel<5>();
     case 6: return mfma_kernel<6>();
     case 7: return mfma_kernel<7>();
+    case 8: return mfma_kernel<8>();
   }
   return nullptr;
 }

@@ -229,6 +229,7 @@ namespace pc2k {
     case 5: { constexpr int C = 5; EXPR; } \
     case 6: { constexpr int C = 6; EXPR; } \
     case 7: { constexpr int C = 7; EXPR; } \
+    case 8: { constexpr int C = 8; EXPR; } \
   }
 // the same over every geometry id, alternative encryption tiles included
 #define PC2_DISPATCH_GEO(geo, EXPR)        \
@@ -243,6 +244,7 @@ namespace pc2k {
     case 7: { constexpr int C = 7; EXPR; } \
     case 8: { constexpr int C = 8; EXPR; } \
     case 9: { constexpr int C = 9; EXPR; } \
+    case 10: { constexpr int C = 10; EXPR; } \
   }
 
 template <int C>

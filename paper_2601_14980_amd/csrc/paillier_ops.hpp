@@ -447,7 +447,7 @@ __device__ __forceinline__ void sum_group(const PkConst& pk, const uint32_t* con
 namespace pc2k {
 
 // Digit geometry of each geometry id: Gn for n^2, Gp for p^2 and q^2
-// (mirrors CLASS_GEO in pc2_types.hpp; ids 8 and 9 are the alternative
+// (mirrors CLASS_GEO in pc2_types.hpp; ids 9 and 10 are the alternative
 // encryption tiles of classes 5 and 6).
 template <int CLS>
 struct Geos;
@@ -465,8 +465,9 @@ PC2_CLASS(4, 28, 19, 2, 28, 19, 1)
 PC2_CLASS(5, 28, 37, 2, 28, 37, 1)
 PC2_CLASS(6, 27, 38, 4, 28, 37, 2)
 PC2_CLASS(7, 27, 29, 8, 27, 29, 4)
-PC2_CLASS(8, 28, 19, 4, 28, 37, 1)
-PC2_CLASS(9, 27, 19, 8, 28, 37, 2)
+PC2_CLASS(8, 27, 38, 8, 27, 38, 4)
+PC2_CLASS(9, 28, 19, 4, 28, 37, 1)
+PC2_CLASS(10, 27, 19, 8, 28, 37, 2)
 #undef PC2_CLASS
 
 }  // namespace pc2k

@@ -99,9 +99,9 @@ struct BatchJob {
   const uint32_t* const* inputs;  // hom_sum: K device pointers
   const size_t* lengths;          // hom_sum: K input lengths (may be null)
 };
-// Largest prime, in 32-bit limbs, that a secret key may hold (the 3072-bit
-// class admits primes of up to 1565 bits).
-constexpr int LS_MAX = 50;
+// Largest prime, in 32-bit limbs, that a secret key may hold (the 4096-bit
+// class admits primes of up to 2093 bits).
+constexpr int LS_MAX = 66;
 
 // A work item: one wavefront's group of elements of one job.
 struct BatchItem {
@@ -112,13 +112,13 @@ struct BatchItem {
 
 // Limbs (28-bit) of R for the matrix-core product per key class:
 // 28 S >= 2 * (class limit) + 2, so R > 4 n^2.
-constexpr int MFMA_S[8] = {3, 5, 10, 19, 37, 74, 147, 220};
+constexpr int MFMA_S[9] = {3, 5, 10, 19, 37, 74, 147, 220, 293};
 
 // Key size classes: index by ceil(log2) of the key.  n^2 and s^2 use
 // separate digit geometries (see mont_tile.hpp).
-constexpr int NUM_CLASSES = 8;
+constexpr int NUM_CLASSES = 9;
 inline int class_for_bits(int nbits) {
-  const int lim[NUM_CLASSES] = {32, 64, 128, 256, 512, 1024, 2048, 3072};
+  const int lim[NUM_CLASSES] = {32, 64, 128, 256, 512, 1024, 2048, 3072, 4096};
   for (int i = 0; i < NUM_CLASSES; ++i)
     if (nbits <= lim[i]) return i;
   return -1;
@@ -133,16 +133,16 @@ struct ClassGeo {
   int nD, nK, nT;  // n^2
   int pD, pK, pT;  // s^2
 };
-constexpr int NUM_GEOS = 10;
+constexpr int NUM_GEOS = 11;
 constexpr ClassGeo CLASS_GEO[NUM_GEOS] = {
     {28, 2, 2, 28, 2, 1},   {28, 3, 2, 28, 3, 1},   {28, 5, 2, 28, 5, 1},
     {28, 10, 2, 28, 10, 1}, {28, 19, 2, 28, 19, 1}, {28, 37, 2, 28, 37, 1},
-    {27, 38, 4, 28, 37, 2}, {27, 29, 8, 27, 29, 4},
+    {27, 38, 4, 28, 37, 2}, {27, 29, 8, 27, 29, 4}, {27, 38, 8, 27, 38, 4},
     {28, 19, 4, 28, 37, 1},  // class 5 (1024-bit keys), 4 lanes per ciphertext
     {27, 19, 8, 28, 37, 2},  // class 6 (2048-bit keys), 8 lanes per ciphertext
 };
-constexpr int GEO_CLASS[NUM_GEOS] = {0, 1, 2, 3, 4, 5, 6, 7, 5, 6};   // key class of a geometry
-constexpr int ALT_GEO[NUM_CLASSES] = {-1, -1, -1, -1, -1, 8, 9, -1};  // alternative tile, or -1
+constexpr int GEO_CLASS[NUM_GEOS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 5, 6};  // key class of a geometry
+constexpr int ALT_GEO[NUM_CLASSES] = {-1, -1, -1, -1, -1, 9, 10, -1, -1};  // alternative tile, or -1
 
 // Launch configuration chosen by the host for a data call.
 struct Launch {

@@ -74,8 +74,8 @@ def test_bruteforce_hom_ops_tiny(gpu_ctx, p, q):
     assert sm == [O.hom_scalar_mul(opk, c, k) for c, k in zip(ca, ks)]
 
 
-SIZES = [64, 128, 256, 512, 1024, 2048, 3072]
-COUNTS = {64: 200, 128: 150, 256: 130, 512: 100, 1024: 70, 2048: 21, 3072: 11}
+SIZES = [64, 128, 256, 512, 1024, 2048, 3072, 4096]
+COUNTS = {64: 200, 128: 150, 256: 130, 512: 100, 1024: 70, 2048: 21, 3072: 11, 4096: 4}
 
 
 @pytest.fixture(scope="module", params=SIZES)

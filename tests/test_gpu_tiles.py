@@ -85,7 +85,7 @@ def test_tile_one_call_identical(tctx, setup, tile):
         tctx.set_option(pc2.PC2_OPT_TILE, 0)
 
 
-@pytest.mark.parametrize("tile", [2, 4, 8, 1])  # pairs (5,6), (6,8), (5,9), (8,9)
+@pytest.mark.parametrize("tile", [2, 4, 8, 1])  # geometry pairs (5,6), (6,9), (5,10), (9,10)
 def test_tile_batch_mixed_identical(tctx, setup, tile):
     from paper_2601_14980_amd import pc2
     tctx.set_option(pc2.PC2_OPT_TILE, tile)

@@ -15,4 +15,6 @@ paillier  Key derivation, encryption, decryption and the two homomorphic
           (no Montgomery form, no windows, no CRT on the parity path).
 quant     The affine form of the quantizer of Sec. III-A and its inverse.
 admm      The consensus-lasso iteration used by the ADMM driver, in float64.
+colsplit  The column-split iteration of Algorithm 1 with its quantized,
+          homomorphic node step evaluated by the exact plaintext equivalent.
 """

@@ -164,3 +164,75 @@ def _dq_truncating(M, k, o, W):
 def test_quant_mutants_caught(monkeypatch, name, target, mutant):
     monkeypatch.setattr(Q, target, mutant)
     assert _caught(PINS_QUANT), f"mutant '{name}' survived the pins"
+
+
+# ------------------------------------------------- column-split ADMM oracle
+import numpy as np  # noqa: E402
+
+import oracle.colsplit as CS  # noqa: E402
+from tests import test_oracle_colsplit as cpins  # noqa: E402
+
+PINS_COLSPLIT = [
+    cpins.test_gram_and_gauss_jordan_against_lapack,
+    cpins.test_single_node_converges_to_least_squares,
+    lambda: cpins.test_master_update_is_the_soft_threshold_prox(2.5, 0.3),
+    lambda: cpins.test_quantized_node_within_theorem_bound(30),
+    cpins.test_inverse_quantization_expands_to_centered_sums,
+]
+
+
+def _dq_single_row_terms(self, kk, P, W):
+    k, Nk = self.k, self.Nk
+    o, o1 = 1 << (k + 3), 1 << (2 * k + 3)
+    S = sum(W)
+    # mistake: the paper's N = 1 cross terms (2 N o^2 written as 2 o^2)
+    return np.array([math.ldexp(float(P[i] - o1 - 2 * o * self.R[kk][i] - o * S + 2 * o * o),
+                                -2 * k) for i in range(Nk)])
+
+
+def _dq_sign(self, kk, P, W):
+    k, Nk = self.k, self.Nk
+    o, o1 = 1 << (k + 3), 1 << (2 * k + 3)
+    S = sum(W)
+    # mistake: + o S
+    return np.array([math.ldexp(float(P[i] - o1 - 2 * o * self.R[kk][i] + o * S
+                                      + 2 * Nk * o * o), -2 * k) for i in range(Nk)])
+
+
+def _iterate_lambda_unscaled(self, z, v, lam, quantized):
+    x = np.empty(self.N)
+    for kk in range(self.K):
+        x[kk * self.Nk:(kk + 1) * self.Nk] = self.node_plain(kk, z, v)
+    t = v + x
+    zn = CS.soft_threshold(t, lam)       # mistake: threshold lambda, not lambda / rho
+    return x, zn, t - zn
+
+
+def _gj_no_scaling(G):
+    Nk = G.shape[0]
+    T = np.hstack([G, np.eye(Nk)])
+    for p in range(Nk):
+        rp = T[p].copy()                   # mistake: the pivot row is not divided
+        f = T[:, p].copy() / T[p, p]
+        T -= np.outer(f, rp)
+        T[p] = rp
+    return T[:, Nk:].copy()
+
+
+def _gamma2_wrong_offset(u, k):
+    return np.rint(np.ldexp(u, k)).astype(np.int64) + np.int64(1 << (k + 2))  # mistake: o / 2
+
+
+@pytest.mark.parametrize("name,target,mutant", [
+    ("N = 1 cross terms", ("ColumnSplitLasso", "dequantize"), _dq_single_row_terms),
+    ("sign of o S", ("ColumnSplitLasso", "dequantize"), _dq_sign),
+    ("threshold lambda", ("ColumnSplitLasso", "iterate"), _iterate_lambda_unscaled),
+    ("unscaled pivot row", ("gauss_jordan_inverse",), _gj_no_scaling),
+    ("offset o / 2", ("gamma2",), _gamma2_wrong_offset),
+])
+def test_colsplit_mutants_caught(monkeypatch, name, target, mutant):
+    if len(target) == 2:
+        monkeypatch.setattr(getattr(CS, target[0]), target[1], mutant)
+    else:
+        monkeypatch.setattr(CS, target[0], mutant)
+    assert _caught(PINS_COLSPLIT), f"mutant '{name}' survived the pins"

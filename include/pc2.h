@@ -240,6 +240,46 @@ int pc2_matvec_apply(pc2_matvec *mv, const uint64_t *B, const uint32_t *alpha, u
                      size_t rows, void *hip_stream);
 int pc2_matvec_destroy(pc2_matvec *mv);
 
+/* --------------------------------------- column-split 3P-ADMM-PC2 loop */
+
+/* Algorithm 1 with A split by COLUMNS over K nodes (Sec. II, eqs. (sldi231),
+ * (sldo34), (iu43)): node k keeps B_k = (A_k^T A_k + rho I)^-1 and
+ * G_k = Gamma_2(rho B_k); the master sends Enc(Gamma_1(B_k A_k^T y)) once and
+ * Enc(Gamma_2(z_k)), Enc(Gamma_2(-v_k)) every iteration; the node returns
+ * alpha_k (+) G_k (x) (z_k (+) -v_k) (eq. (itq2)); the master decrypts,
+ * inverts the quantization and updates z = S_{lambda/rho}(v + x),
+ * v = v + x - z.  Quantizers with scale s = 2^log2_scale on [-8, 8):
+ * Gamma_2(u) = rint(u s) + 8 s, Gamma_1(u) = rint(u s^2) + 8 s^2; the inverse
+ * quantization of a row of Nk terms is
+ *   x_i = float64(P_i - 8 s^2 - 16 s R_i - 8 s S + 128 Nk s^2) / s^2
+ * with R_i = sum_j (G_k)_ij and S = sum_j (Gamma_2(z_k) + Gamma_2(-v_k))_j (the
+ * form of Theorem 1's cross terms for Nk > 1).  All work runs on the device:
+ * the setup computes A_k^T A_k + rho I and its Gauss-Jordan inverse in
+ * float64 in a fixed summation order.
+ *
+ * pc2_colsplit_create: A: device double [M][N] row-major, y: device double [M];
+ *   N a multiple of K; rho > 0; 1 <= log2_scale with 2 log2_scale + 9 +
+ *   ceil(log2(N / K)) bits below both 127 and the key's size
+ *   (PC2_E_UNSUPPORTED otherwise); r_pool: device [r_count][L] randomness
+ *   (0 < r < n), r_count >= N + 2 N / K: rows 0 .. N-1 encrypt alpha, and each
+ *   iteration and node takes the next 2 N / K rows of the rest, cyclically.
+ *   Synchronises the stream (the setup's workspace is released); A, y and
+ *   r_pool must stay valid while the object lives (r_pool is read every
+ *   iteration).
+ * pc2_colsplit_iterate: one iteration on device double [N] arrays x (out),
+ *   z and v (in and out).  quantized != 0 runs the encrypted node step;
+ *   quantized = 0 the same iteration in float64 without quantization
+ *   (x_k = alpha_k + (rho B_k)(z_k - v_k)), the reference of the
+ *   quantization error.  Values that leave [-8, 8) latch PC2_E_RANGE.  Asynchronous. */
+typedef struct pc2_colsplit pc2_colsplit;
+int pc2_colsplit_create(const pc2_sk *sk, const double *A, const double *y, uint32_t M,
+                        uint32_t N, uint32_t K, double rho, uint32_t log2_scale,
+                        const uint32_t *r_pool, size_t r_count, void *hip_stream,
+                        pc2_colsplit **out);
+int pc2_colsplit_iterate(pc2_colsplit *cs, double lambda, int quantized, double *x, double *z,
+                         double *v, void *hip_stream);
+int pc2_colsplit_destroy(pc2_colsplit *cs);
+
 /* ------------------------------------------------------ batched launches */
 
 /* One job of a batch.  A batch runs one phase of many edge nodes' work --

@@ -34,6 +34,7 @@ UNITS = {
     "kernels_matvec.hip": [],
     "kernels_quant.hip": ["-ffp-contract=off"],
     "kernels_admm.hip": ["-ffp-contract=off"],
+    "kernels_colsplit.hip": ["-ffp-contract=off"],
     "api.cpp": [],
 }
 

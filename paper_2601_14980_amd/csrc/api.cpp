@@ -79,6 +79,22 @@ struct pc2_matvec {
   bool loaded = false;
 };
 
+struct pc2_colsplit {
+  pc2_ctx* ctx = nullptr;
+  const pc2_sk* sk = nullptr;
+  int M = 0, N = 0, K = 0, Nk = 0, k = 0;
+  double rho = 1.0;
+  const uint32_t* r_pool = nullptr;
+  size_t r_count = 0, iter = 0;
+  std::vector<pc2_matvec*> mv;  // one plan per node over Gamma_2(rho B_k)
+  void* dev = nullptr;          // per-node constants, then per-iteration staging
+  double *alpha = nullptr, *rhoB = nullptr;       // [K][Nk], [K][Nk][Nk]
+  uint64_t *G = nullptr, *R = nullptr;            // [K][Nk][Nk], [K][Nk]
+  uint32_t* ahat = nullptr;                       // [K][Nk][2L] Enc(Gamma_1(alpha_k))
+  uint64_t *wz = nullptr, *wv = nullptr, *S = nullptr;
+  uint32_t *cz = nullptr, *cv = nullptr, *c = nullptr, *xhat = nullptr, *P = nullptr;
+};
+
 struct pc2_pk {
   pc2_ctx* ctx = nullptr;
   int device = 0;
@@ -1546,6 +1562,155 @@ int pc2_matvec_destroy(pc2_matvec* mv) {
   if (mv->tab) (void)hipFree(mv->tab);
   if (mv->parts) (void)hipFree(mv->parts);
   delete mv;
+  return PC2_OK;
+}
+
+// ------------------------------------------------- column-split ADMM
+namespace {
+void* carve(char*& at, size_t bytes) {  // 256-byte aligned sub-buffers of one allocation
+  void* p = at;
+  at += (bytes + 255) & ~(size_t)255;
+  return p;
+}
+int ceil_log2(size_t v) {
+  int b = 0;
+  while (((size_t)1 << b) < v) ++b;
+  return b;
+}
+}  // namespace
+
+int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint32_t M,
+                        uint32_t N, uint32_t K, double rho, uint32_t log2_scale,
+                        const uint32_t* r_pool, size_t r_count, void* hip_stream,
+                        pc2_colsplit** out) {
+  if (!sk || !sk->ctx || !A || !y || !r_pool || !out || M == 0 || N == 0 || K == 0 ||
+      N % K != 0 || !(rho > 0) || log2_scale < 1)
+    return PC2_E_INVAL;
+  *out = nullptr;
+  const int Nk = (int)(N / K), k = (int)log2_scale, L = sk->pk.L;
+  // plaintexts stay below 2^(2k + 9 + log2 Nk): they must fit 127 bits and n
+  const int pbits = 2 * k + 9 + ceil_log2((size_t)Nk);
+  if (pbits > 126 || pbits >= (int)sk->pk.c.nbits || L < 4) return PC2_E_UNSUPPORTED;
+  if (r_count < (size_t)N + 2 * (size_t)Nk) return PC2_E_INVAL;
+  pc2_ctx* ctx = sk->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  pc2_colsplit* cs = new (std::nothrow) pc2_colsplit();
+  if (!cs) return PC2_E_NOMEM;
+  cs->ctx = ctx;
+  cs->sk = sk;
+  cs->M = (int)M;
+  cs->N = (int)N;
+  cs->K = (int)K;
+  cs->Nk = Nk;
+  cs->k = k;
+  cs->rho = rho;
+  cs->r_pool = r_pool;
+  cs->r_count = r_count;
+  const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L;
+  const size_t bytes = 256 * 16 + K * nk * 8 * 2 + K * nk * nk * 16 + K * nk * L2 * 4 +
+                       nk * 8 * 2 + 8 + nk * L2 * 4 * 4 + nk * L * 4;
+  void* tmp = nullptr;
+  int rc = PC2_OK;
+  if (hipMalloc(&cs->dev, bytes) != hipSuccess) rc = PC2_E_NOMEM;
+  // setup workspace: T (Nk x 2Nk), rp (2Nk), f (Nk), aty (Nk), Gamma_1 limbs (Nk x 4)
+  const size_t tbytes = 256 * 8 + nk * 2 * nk * 8 + nk * 4 * 8 + nk * 16;
+  if (!rc && hipMalloc(&tmp, tbytes) != hipSuccess) rc = PC2_E_NOMEM;
+  if (!rc) {
+    char* at = (char*)cs->dev;
+    cs->alpha = (double*)carve(at, (K * nk) * sizeof(double));
+    cs->rhoB = (double*)carve(at, (K * nk * nk) * sizeof(double));
+    cs->G = (uint64_t*)carve(at, (K * nk * nk) * sizeof(uint64_t));
+    cs->R = (uint64_t*)carve(at, (K * nk) * sizeof(uint64_t));
+    cs->ahat = (uint32_t*)carve(at, (K * nk * L2) * sizeof(uint32_t));
+    cs->wz = (uint64_t*)carve(at, (nk) * sizeof(uint64_t));
+    cs->wv = (uint64_t*)carve(at, (nk) * sizeof(uint64_t));
+    cs->S = (uint64_t*)carve(at, (1) * sizeof(uint64_t));
+    cs->cz = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
+    cs->cv = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
+    cs->c = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
+    cs->xhat = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
+    cs->P = (uint32_t*)carve(at, (nk * L) * sizeof(uint32_t));
+    char* wt = (char*)tmp;
+    double* T = (double*)carve(wt, (nk * 2 * nk) * sizeof(double));
+    double* rp = (double*)carve(wt, (2 * nk) * sizeof(double));
+    double* f = (double*)carve(wt, (nk) * sizeof(double));
+    double* aty = (double*)carve(wt, (nk) * sizeof(double));
+    uint32_t* g1 = (uint32_t*)carve(wt, (nk * 4) * sizeof(uint32_t));
+    for (int kk = 0; kk < (int)K && !rc; ++kk) {
+      const size_t o1 = kk * nk, o2 = kk * nk * nk;
+      rc = status_of(pc2k::cs_setup_node(A, y, (int)M, (int)N, kk * Nk, Nk, rho, k, T, rp, f,
+                                         aty, cs->alpha + o1, cs->rhoB + o2, cs->G + o2,
+                                         cs->R + o1, g1, ctx->err, hip_stream));
+      // alpha_k = Enc(Gamma_1(B_k A_k^T y)), randomness rows kk Nk .. (kk + 1) Nk - 1
+      if (!rc)
+        rc = pc2_encrypt(&sk->pk, g1, 4, r_pool + o1 * L, cs->ahat + o1 * L2, nk, hip_stream);
+      pc2_matvec* mv = nullptr;
+      if (!rc) rc = pc2_matvec_create(&sk->pk, nk, (uint32_t)(k + 4), 0, nk, &mv);
+      if (!rc) cs->mv.push_back(mv);
+    }
+    // the workspace is released once the setup has run
+    if (!rc && hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) rc = PC2_E_DEVICE;
+  }
+  if (tmp) (void)hipFree(tmp);
+  if (rc) {
+    (void)hipDeviceSynchronize();
+    for (pc2_matvec* mv : cs->mv) pc2_matvec_destroy(mv);
+    if (cs->dev) (void)hipFree(cs->dev);
+    delete cs;
+    return rc;
+  }
+  *out = cs;
+  return PC2_OK;
+}
+
+int pc2_colsplit_iterate(pc2_colsplit* cs, double lambda, int quantized, double* x, double* z,
+                         double* v, void* hip_stream) {
+  if (!cs || !cs->ctx || !x || !z || !v || !(lambda >= 0)) return PC2_E_INVAL;
+  pc2_ctx* ctx = cs->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  const pc2_sk* sk = cs->sk;
+  const pc2_pk* pk = &sk->pk;
+  const int Nk = cs->Nk, L = pk->L, k = cs->k;
+  const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L;
+  // randomness of an iteration's 2 Nk encryptions per node: a window of the
+  // pool after the rows that encrypted alpha, advancing every node and iteration
+  const size_t span = cs->r_count - (size_t)cs->N - 2 * nk + 1;
+  int rc = PC2_OK;
+  for (int kk = 0; kk < cs->K && !rc; ++kk) {
+    const size_t k0 = kk * nk;
+    if (quantized) {
+      const size_t base = cs->N + ((cs->iter * cs->K + kk) * 2 * nk) % span;
+      rc = status_of(pc2k::cs_quant_zv(z + k0, v + k0, Nk, k, cs->wz, cs->wv, cs->S, ctx->err,
+                                       hip_stream));
+      if (!rc) rc = pc2_encrypt(pk, (const uint32_t*)cs->wz, 2, cs->r_pool + base * L, cs->cz,
+                                nk, hip_stream);
+      if (!rc) rc = pc2_encrypt(pk, (const uint32_t*)cs->wv, 2, cs->r_pool + (base + nk) * L,
+                                cs->cv, nk, hip_stream);
+      // the node step (eq. (itq2)): alpha_k (+) G_k (x) (z_k (+) -v_k)
+      if (!rc) rc = pc2_hom_add(pk, cs->cz, cs->cv, cs->c, nk, hip_stream);
+      if (!rc) rc = pc2_matvec_load(cs->mv[kk], cs->c, hip_stream);
+      if (!rc) rc = pc2_matvec_apply(cs->mv[kk], cs->G + kk * nk * nk, cs->ahat + k0 * L2,
+                                     cs->xhat, nk, hip_stream);
+      if (!rc) rc = pc2_decrypt(sk, cs->xhat, cs->P, nk, hip_stream);
+      if (!rc) rc = status_of(pc2k::cs_dequant(cs->P, L, Nk, cs->R + k0, cs->S, k, x + k0,
+                                               ctx->err, hip_stream));
+    } else {
+      rc = status_of(pc2k::cs_plain_node(cs->rhoB + kk * nk * nk, Nk, z + k0, v + k0,
+                                         cs->alpha + k0, x + k0, hip_stream));
+    }
+  }
+  if (!rc) rc = status_of(pc2k::cs_update(x, z, v, cs->N, lambda / cs->rho, hip_stream));
+  if (!rc) ++cs->iter;
+  return rc;
+}
+
+int pc2_colsplit_destroy(pc2_colsplit* cs) {
+  if (!cs || !cs->ctx) return PC2_E_INVAL;
+  (void)hipSetDevice(cs->ctx->device);
+  (void)hipDeviceSynchronize();
+  for (pc2_matvec* mv : cs->mv) pc2_matvec_destroy(mv);
+  if (cs->dev) (void)hipFree(cs->dev);
+  delete cs;
   return PC2_OK;
 }
 

@@ -58,6 +58,21 @@ hipError_t launch_mv_apply(int cls, int grid, const PkConst& pk, const uint64_t*
                            const uint32_t* alpha, size_t nchunks, size_t chunk_cols,
                            uint32_t* out, size_t chunk_stride, int* err, void* stream);
 
+// column-split ADMM (kernels_colsplit.hip): setup of one node's constants,
+// and the float64 / integer steps of an iteration around the encrypted node
+// step.  T: Nk x 2Nk doubles; rp: 2Nk; f, aty: Nk doubles of workspace.
+hipError_t cs_setup_node(const double* A, const double* y, int M, int N, int k0, int Nk,
+                         double rho, int k, double* T, double* rp, double* f, double* aty,
+                         double* alpha, double* rhoB, uint64_t* G, uint64_t* R, uint32_t* g1,
+                         int* err, void* stream);
+hipError_t cs_quant_zv(const double* z, const double* v, int Nk, int k, uint64_t* wz,
+                       uint64_t* wv, uint64_t* S, int* err, void* stream);
+hipError_t cs_dequant(const uint32_t* P, int L, int Nk, const uint64_t* R, const uint64_t* S,
+                      int k, double* x, int* err, void* stream);
+hipError_t cs_plain_node(const double* rhoB, int Nk, const double* z, const double* v,
+                         const double* alpha, double* x, void* stream);
+hipError_t cs_update(const double* x, double* z, double* v, int N, double kappa, void* stream);
+
 // persistent batch kernels (kernels_batch.hip)
 // pairs of geometry ids with a compiled kernel; alternative tiles are
 // compiled for encryption only (batch_kernel returns null otherwise)

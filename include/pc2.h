@@ -261,8 +261,8 @@ int pc2_matvec_destroy(pc2_matvec *mv);
  *   N a multiple of K; rho > 0; 1 <= log2_scale with 2 log2_scale + 9 +
  *   ceil(log2(N / K)) bits below both 127 and the key's size
  *   (PC2_E_UNSUPPORTED otherwise); r_pool: device [r_count][L] randomness
- *   (0 < r < n), r_count >= N + 2 N / K: rows 0 .. N-1 encrypt alpha, and each
- *   iteration and node takes the next 2 N / K rows of the rest, cyclically.
+ *   (0 < r < n), r_count >= 3 N: rows 0 .. N-1 encrypt alpha, and each
+ *   iteration takes the next 2 N rows of the rest, cyclically.
  *   Synchronises the stream (the setup's workspace is released); A, y and
  *   r_pool must stay valid while the object lives (r_pool is read every
  *   iteration).

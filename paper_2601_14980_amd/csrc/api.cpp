@@ -91,8 +91,8 @@ struct pc2_colsplit {
   double *alpha = nullptr, *rhoB = nullptr;       // [K][Nk], [K][Nk][Nk]
   uint64_t *G = nullptr, *R = nullptr;            // [K][Nk][Nk], [K][Nk]
   uint32_t* ahat = nullptr;                       // [K][Nk][2L] Enc(Gamma_1(alpha_k))
-  uint64_t *wz = nullptr, *wv = nullptr, *S = nullptr;
-  uint32_t *cz = nullptr, *cv = nullptr, *c = nullptr, *xhat = nullptr, *P = nullptr;
+  uint64_t *w = nullptr, *S = nullptr;            // [2][N] Gamma_2(z), Gamma_2(-v); [K]
+  uint32_t *cw = nullptr, *c = nullptr, *xhat = nullptr, *P = nullptr;  // [2N][2L], [N][2L] x2, [N][L]
 };
 
 struct pc2_pk {
@@ -1591,7 +1591,7 @@ int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint
   // plaintexts stay below 2^(2k + 9 + log2 Nk): they must fit 127 bits and n
   const int pbits = 2 * k + 9 + ceil_log2((size_t)Nk);
   if (pbits > 126 || pbits >= (int)sk->pk.c.nbits || L < 4) return PC2_E_UNSUPPORTED;
-  if (r_count < (size_t)N + 2 * (size_t)Nk) return PC2_E_INVAL;
+  if (r_count < 3 * (size_t)N) return PC2_E_INVAL;
   pc2_ctx* ctx = sk->ctx;
   if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
   pc2_colsplit* cs = new (std::nothrow) pc2_colsplit();
@@ -1606,9 +1606,9 @@ int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint
   cs->rho = rho;
   cs->r_pool = r_pool;
   cs->r_count = r_count;
-  const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L;
+  const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L, n = N;
   const size_t bytes = 256 * 16 + K * nk * 8 * 2 + K * nk * nk * 16 + K * nk * L2 * 4 +
-                       nk * 8 * 2 + 8 + nk * L2 * 4 * 4 + nk * L * 4;
+                       n * 8 * 2 + K * 8 + n * L2 * 4 * 4 + n * L * 4;
   void* tmp = nullptr;
   int rc = PC2_OK;
   if (hipMalloc(&cs->dev, bytes) != hipSuccess) rc = PC2_E_NOMEM;
@@ -1622,14 +1622,12 @@ int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint
     cs->G = (uint64_t*)carve(at, (K * nk * nk) * sizeof(uint64_t));
     cs->R = (uint64_t*)carve(at, (K * nk) * sizeof(uint64_t));
     cs->ahat = (uint32_t*)carve(at, (K * nk * L2) * sizeof(uint32_t));
-    cs->wz = (uint64_t*)carve(at, (nk) * sizeof(uint64_t));
-    cs->wv = (uint64_t*)carve(at, (nk) * sizeof(uint64_t));
-    cs->S = (uint64_t*)carve(at, (1) * sizeof(uint64_t));
-    cs->cz = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
-    cs->cv = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
-    cs->c = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
-    cs->xhat = (uint32_t*)carve(at, (nk * L2) * sizeof(uint32_t));
-    cs->P = (uint32_t*)carve(at, (nk * L) * sizeof(uint32_t));
+    cs->w = (uint64_t*)carve(at, (2 * n) * sizeof(uint64_t));
+    cs->S = (uint64_t*)carve(at, (size_t)K * sizeof(uint64_t));
+    cs->cw = (uint32_t*)carve(at, (2 * n * L2) * sizeof(uint32_t));
+    cs->c = (uint32_t*)carve(at, (n * L2) * sizeof(uint32_t));
+    cs->xhat = (uint32_t*)carve(at, (n * L2) * sizeof(uint32_t));
+    cs->P = (uint32_t*)carve(at, (n * L) * sizeof(uint32_t));
     char* wt = (char*)tmp;
     double* T = (double*)carve(wt, (nk * 2 * nk) * sizeof(double));
     double* rp = (double*)carve(wt, (2 * nk) * sizeof(double));
@@ -1671,30 +1669,32 @@ int pc2_colsplit_iterate(pc2_colsplit* cs, double lambda, int quantized, double*
   const pc2_sk* sk = cs->sk;
   const pc2_pk* pk = &sk->pk;
   const int Nk = cs->Nk, L = pk->L, k = cs->k;
-  const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L;
-  // randomness of an iteration's 2 Nk encryptions per node: a window of the
-  // pool after the rows that encrypted alpha, advancing every node and iteration
-  const size_t span = cs->r_count - (size_t)cs->N - 2 * nk + 1;
+  const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L, n = (size_t)cs->N;
   int rc = PC2_OK;
-  for (int kk = 0; kk < cs->K && !rc; ++kk) {
-    const size_t k0 = kk * nk;
-    if (quantized) {
-      const size_t base = cs->N + ((cs->iter * cs->K + kk) * 2 * nk) % span;
-      rc = status_of(pc2k::cs_quant_zv(z + k0, v + k0, Nk, k, cs->wz, cs->wv, cs->S, ctx->err,
-                                       hip_stream));
-      if (!rc) rc = pc2_encrypt(pk, (const uint32_t*)cs->wz, 2, cs->r_pool + base * L, cs->cz,
-                                nk, hip_stream);
-      if (!rc) rc = pc2_encrypt(pk, (const uint32_t*)cs->wv, 2, cs->r_pool + (base + nk) * L,
-                                cs->cv, nk, hip_stream);
-      // the node step (eq. (itq2)): alpha_k (+) G_k (x) (z_k (+) -v_k)
-      if (!rc) rc = pc2_hom_add(pk, cs->cz, cs->cv, cs->c, nk, hip_stream);
-      if (!rc) rc = pc2_matvec_load(cs->mv[kk], cs->c, hip_stream);
+  if (quantized) {
+    // master: Gamma_2(z) and Gamma_2(-v) of every node, encrypted in one launch
+    // with the next 2N rows of the randomness pool (after the rows of alpha)
+    const size_t span = cs->r_count - 3 * n + 1;
+    const size_t base = n + (cs->iter * 2 * n) % span;
+    rc = status_of(pc2k::cs_quant_zv(z, v, cs->N, cs->K, k, cs->w, cs->w + n, cs->S, ctx->err,
+                                     hip_stream));
+    if (!rc) rc = pc2_encrypt(pk, (const uint32_t*)cs->w, 2, cs->r_pool + base * L, cs->cw,
+                              2 * n, hip_stream);
+    // node k: alpha_k (+) G_k (x) (z_k (+) -v_k)  (eq. (itq2))
+    if (!rc) rc = pc2_hom_add(pk, cs->cw, cs->cw + n * L2, cs->c, n, hip_stream);
+    for (int kk = 0; kk < cs->K && !rc; ++kk) {
+      const size_t k0 = kk * nk;
+      rc = pc2_matvec_load(cs->mv[kk], cs->c + k0 * L2, hip_stream);
       if (!rc) rc = pc2_matvec_apply(cs->mv[kk], cs->G + kk * nk * nk, cs->ahat + k0 * L2,
-                                     cs->xhat, nk, hip_stream);
-      if (!rc) rc = pc2_decrypt(sk, cs->xhat, cs->P, nk, hip_stream);
-      if (!rc) rc = status_of(pc2k::cs_dequant(cs->P, L, Nk, cs->R + k0, cs->S, k, x + k0,
-                                               ctx->err, hip_stream));
-    } else {
+                                     cs->xhat + k0 * L2, nk, hip_stream);
+    }
+    // master: decrypt every node's result and invert the quantization
+    if (!rc) rc = pc2_decrypt(sk, cs->xhat, cs->P, n, hip_stream);
+    if (!rc) rc = status_of(pc2k::cs_dequant(cs->P, L, cs->N, cs->K, cs->R, cs->S, k, x,
+                                             ctx->err, hip_stream));
+  } else {
+    for (int kk = 0; kk < cs->K && !rc; ++kk) {
+      const size_t k0 = kk * nk;
       rc = status_of(pc2k::cs_plain_node(cs->rhoB + kk * nk * nk, Nk, z + k0, v + k0,
                                          cs->alpha + k0, x + k0, hip_stream));
     }

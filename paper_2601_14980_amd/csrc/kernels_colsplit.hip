@@ -10,10 +10,10 @@
 //   k_cs_rhob        rho B_k, G = Gamma_2(rho B_k) = rint(rho B 2^k) + 2^(k+3)
 //   k_cs_rowsum      R_i = sum_j G_ij
 //   k_cs_gamma1      Gamma_1(alpha) = rint(alpha 2^(2k)) + 2^(2k+3), 4 limbs
-// Per iteration:
-//   k_cs_quant_zv    W_z = Gamma_2(z_k), W_v = Gamma_2(-v_k)
-//   k_cs_sumw        S = sum_j (W_z + W_v)_j
-//   k_cs_dequant     x_i = float64(P_i - o1 - 2 o R_i - o S + 2 Nk o^2) 2^(-2k)
+// Per iteration (all nodes at once; node of element i = i / Nk):
+//   k_cs_quant_zv    W_z = Gamma_2(z), W_v = Gamma_2(-v)
+//   k_cs_sumw        S_k = sum_{j in node k} (W_z + W_v)_j   (one workgroup per node)
+//   k_cs_dequant     x_i = float64(P_i - o1 - 2 o R_i - o S_k + 2 Nk o^2) 2^(-2k)
 //   k_cs_plain_node  x_k = alpha_k + (rho B_k)(z_k - v_k)   (unquantized)
 //   k_cs_update      z = S_{lambda/rho}(v + x), v = v + x - z
 // The file is compiled without floating-point contraction, so every sum and
@@ -139,11 +139,11 @@ __global__ void k_cs_gamma1(const double* __restrict__ alpha, int Nk, int k,
   for (int l = 0; l < 4; ++l) out[(size_t)i * 4 + l] = (uint32_t)(w >> (32 * l));
 }
 
-__global__ void k_cs_quant_zv(const double* __restrict__ z, const double* __restrict__ v, int Nk,
+__global__ void k_cs_quant_zv(const double* __restrict__ z, const double* __restrict__ v, int N,
                               int k, uint64_t* __restrict__ wz, uint64_t* __restrict__ wv,
                               int* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Nk) return;
+  if (i >= N) return;
   const int64_t o = (int64_t)1 << (k + ZLOG2);
   const double a = z[i], b = -v[i];
   const bool ok = in_range(a) && in_range(b);
@@ -152,19 +152,20 @@ __global__ void k_cs_quant_zv(const double* __restrict__ z, const double* __rest
   if (!ok) atomicOr(err, pc2k::ERR_RANGE);
 }
 
-// one workgroup of 256 lanes
+// one workgroup of 256 lanes per node
 __global__ void k_cs_sumw(const uint64_t* __restrict__ wz, const uint64_t* __restrict__ wv, int Nk,
                           uint64_t* __restrict__ S) {
   __shared__ uint64_t part[256];
+  const size_t k0 = (size_t)blockIdx.x * Nk;
   uint64_t s = 0;
-  for (int i = threadIdx.x; i < Nk; i += blockDim.x) s += wz[i] + wv[i];
+  for (int i = threadIdx.x; i < Nk; i += blockDim.x) s += wz[k0 + i] + wv[k0 + i];
   part[threadIdx.x] = s;
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *S = part[0];
+  if (threadIdx.x == 0) S[blockIdx.x] = part[0];
 }
 
 // signed 128-bit integer -> double, rounded to nearest, ties to even
@@ -189,18 +190,18 @@ __device__ __forceinline__ double i128_to_double(__int128 x) {
 
 // x_i = float64(P_i - o1 - 2 o R_i - o S + 2 Nk o^2) 2^(-2k), o = 2^(k+3),
 // o1 = 2^(2k+3); P: decrypted plaintexts, L limbs (values must fit 127 bits)
-__global__ void k_cs_dequant(const uint32_t* __restrict__ P, int L, int Nk,
+__global__ void k_cs_dequant(const uint32_t* __restrict__ P, int L, int N, int Nk,
                              const uint64_t* __restrict__ R, const uint64_t* __restrict__ S,
                              int k, double* __restrict__ x, int* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Nk) return;
+  if (i >= N) return;
   const uint32_t* p = P + (size_t)i * L;
   bool ok = (p[3] >> 31) == 0;
   for (int l = 4; l < L; ++l) ok &= p[l] == 0;
   unsigned __int128 pu = 0;
   for (int l = 3; l >= 0; --l) pu = (pu << 32) | p[l];
   const __int128 X = (__int128)pu - ((__int128)1 << (2 * k + ZLOG2)) -
-                     ((__int128)R[i] << (k + ZLOG2 + 1)) - ((__int128)*S << (k + ZLOG2)) +
+                     ((__int128)R[i] << (k + ZLOG2 + 1)) - ((__int128)S[i / Nk] << (k + ZLOG2)) +
                      ((__int128)Nk << (2 * k + 2 * ZLOG2 + 1));
   x[i] = ok ? ldexp(i128_to_double(X), -2 * k) : __builtin_nan("");
   if (!ok) atomicOr(err, pc2k::ERR_RANGE);
@@ -255,19 +256,19 @@ hipError_t cs_setup_node(const double* A, const double* y, int M, int N, int k0,
   return hipGetLastError();
 }
 
-hipError_t cs_quant_zv(const double* z, const double* v, int Nk, int k, uint64_t* wz,
+hipError_t cs_quant_zv(const double* z, const double* v, int N, int K, int k, uint64_t* wz,
                        uint64_t* wv, uint64_t* S, int* err, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_cs_quant_zv, dim3(blocks(Nk, 256)), dim3(256), 0, s, z, v, Nk, k, wz, wv,
+  hipLaunchKernelGGL(k_cs_quant_zv, dim3(blocks(N, 256)), dim3(256), 0, s, z, v, N, k, wz, wv,
                      err);
-  hipLaunchKernelGGL(k_cs_sumw, dim3(1), dim3(256), 0, s, wz, wv, Nk, S);
+  hipLaunchKernelGGL(k_cs_sumw, dim3(K), dim3(256), 0, s, wz, wv, N / K, S);
   return hipGetLastError();
 }
 
-hipError_t cs_dequant(const uint32_t* P, int L, int Nk, const uint64_t* R, const uint64_t* S,
-                      int k, double* x, int* err, void* stream) {
-  hipLaunchKernelGGL(k_cs_dequant, dim3(blocks(Nk, 256)), dim3(256), 0, (hipStream_t)stream, P,
-                     L, Nk, R, S, k, x, err);
+hipError_t cs_dequant(const uint32_t* P, int L, int N, int K, const uint64_t* R,
+                      const uint64_t* S, int k, double* x, int* err, void* stream) {
+  hipLaunchKernelGGL(k_cs_dequant, dim3(blocks(N, 256)), dim3(256), 0, (hipStream_t)stream, P,
+                     L, N, N / K, R, S, k, x, err);
   return hipGetLastError();
 }
 

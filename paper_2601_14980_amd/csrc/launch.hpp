@@ -65,10 +65,11 @@ hipError_t cs_setup_node(const double* A, const double* y, int M, int N, int k0,
                          double rho, int k, double* T, double* rp, double* f, double* aty,
                          double* alpha, double* rhoB, uint64_t* G, uint64_t* R, uint32_t* g1,
                          int* err, void* stream);
-hipError_t cs_quant_zv(const double* z, const double* v, int Nk, int k, uint64_t* wz,
+// every node at once over N = K Nk elements (S: K sums, R: [K][Nk])
+hipError_t cs_quant_zv(const double* z, const double* v, int N, int K, int k, uint64_t* wz,
                        uint64_t* wv, uint64_t* S, int* err, void* stream);
-hipError_t cs_dequant(const uint32_t* P, int L, int Nk, const uint64_t* R, const uint64_t* S,
-                      int k, double* x, int* err, void* stream);
+hipError_t cs_dequant(const uint32_t* P, int L, int N, int K, const uint64_t* R,
+                      const uint64_t* S, int k, double* x, int* err, void* stream);
 hipError_t cs_plain_node(const double* rhoB, int Nk, const double* z, const double* v,
                          const double* alpha, double* x, void* stream);
 hipError_t cs_update(const double* x, double* z, double* v, int N, double kappa, void* stream);

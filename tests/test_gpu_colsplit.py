@@ -47,7 +47,7 @@ def test_colsplit_matches_oracle(gpu_ctx, M, N, K, rho, k, nbits, iters):
     p, q = gen.primes_for(12, nbits)
     sk = pc2.SecretKey(gpu_ctx, nbits, p, q)
     Nk = N // K
-    pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, N + 4 * Nk, sk.L, 12))
+    pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, 3 * N + 4 * Nk, sk.L, 12))
     Ad, yd = torch.from_numpy(A).cuda(), torch.from_numpy(y).cuda()
     ref = C.ColumnSplitLasso(A, y, K, rho, k)
     for quantized in (True, False):
@@ -75,7 +75,7 @@ def test_colsplit_quantized_close_to_plain(gpu_ctx):
     lam = 0.1 * float(np.max(np.abs(A.T @ y)))
     p, q = gen.primes_for(13, 512)
     sk = pc2.SecretKey(gpu_ctx, 512, p, q)
-    pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, 150 + 100, sk.L, 13))
+    pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, 3 * 150, sk.L, 13))
     Ad, yd = torch.from_numpy(A).cuda(), torch.from_numpy(y).cuda()
     runs = []
     for quantized in (True, False):
@@ -94,14 +94,14 @@ def test_colsplit_range_and_argument_errors(gpu_ctx):
     A, y = _data(20, 30, 4)
     p, q = gen.primes_for(14, 256)
     sk = pc2.SecretKey(gpu_ctx, 256, p, q)
-    pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, 60, sk.L, 14))
+    pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, 90, sk.L, 14))
     Ad, yd = torch.from_numpy(A).cuda(), torch.from_numpy(y).cuda()
     with pytest.raises(pc2.PC2Error):            # 30 columns do not split over 4 nodes
         ColumnSplitLasso(gpu_ctx, sk, Ad, yd, 4, 1.0, 20, pool)
     with pytest.raises(pc2.PC2Error):            # plaintexts would not fit 127 bits
         ColumnSplitLasso(gpu_ctx, sk, Ad, yd, 3, 1.0, 60, pool)
     with pytest.raises(pc2.PC2Error):            # pool too small
-        ColumnSplitLasso(gpu_ctx, sk, Ad, yd, 3, 1.0, 20, pool[:40])
+        ColumnSplitLasso(gpu_ctx, sk, Ad, yd, 3, 1.0, 20, pool[:89])
     cs = ColumnSplitLasso(gpu_ctx, sk, Ad, yd, 3, 1.0, 20, pool)
     cs.z[5] = 9.0                                # outside [-8, 8)
     cs.iterate(0.01, True)

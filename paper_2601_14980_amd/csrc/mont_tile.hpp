@@ -9,9 +9,12 @@
 // Product.  mont_mul computes a*b*R^-1 mod N (R = 2^(D*S)) by operand
 // scanning: for every digit b_i (read from LDS, broadcast to the tile) each
 // lane adds a_j*b_i + m*N_j into 64-bit column accumulators with one
-// v_mad_u64_u32 each -- no carry chain, the accumulators absorb up to 2S
-// products of < 2^(2D) (2S*2^(2D+1) < 2^64 for the sizes used) -- and the
-// division by 2^D is a register shift folded into the destination index.
+// v_mad_u64_u32 each -- no carry chain -- and the division by 2^D is a
+// register shift folded into the destination index.  An accumulator gains
+// two products per step; when S steps could overflow 64 bits (28-bit digits
+// beyond 127 steps) the product pauses every Geo::SEG steps to renormalise:
+// each accumulator keeps its low D bits and hands the rest to the next digit
+// position, which leaves the represented value unchanged.
 // Only digit 0 of the tile needs its carry resolved each step; the other
 // lanes pass their lowest accumulator one lane down (DPP).  With 4N < R the
 // result of inputs < 2N stays < 2N, so no conditional subtraction is needed
@@ -38,6 +41,14 @@ struct Geo {
   static constexpr int SP = ((S + 3) & ~3);      // LDS words of one number
   static constexpr int CH = T_ * K4;             // words of one number in chunked layout
   static constexpr uint32_t MASK = (1u << D_) - 1u;
+  // steps an accumulator can take from a renormalised start (< 2^40) with two
+  // products below (2^D + 2^11)^2 each per step and one carry (< 2^40)
+  static constexpr int NSTEP =
+      (int)((~0ull - (1ull << 41)) /
+            (2 * ((1ull << (2 * D_)) + (1ull << (D_ + 12)) + (1ull << 22))));
+  static constexpr int NSEG = (S + NSTEP - 1) / NSTEP;      // segments of a product
+  static constexpr int SEG = ((S + NSEG - 1) / NSEG + 1) & ~1;  // steps per segment, even
+  static_assert(SEG <= NSTEP, "a segment stays within the accumulators' headroom");
   static_assert(K_ >= 2, "at least two digits per lane");
   static_assert(T_ == 1 || T_ == 2 || T_ == 4 || T_ == 8, "tile of 1, 2, 4 or 8 lanes");
 };
@@ -117,6 +128,22 @@ __device__ __forceinline__ void semi_normalise(uint32_t (&out)[G::K], const uint
   }
 }
 
+// Between two steps of a product: every accumulator keeps its low D bits and
+// adds the high part of the one below; a lane's top carry goes to the next
+// lane's digit 0, and the top lane of the tile keeps its top accumulator
+// whole (it is zero between steps).  The value represented is unchanged.
+template <class G>
+__device__ __forceinline__ void renormalise(uint64_t (&acc)[G::K], int tl) {
+  constexpr int K = G::K, D = G::D;
+  const bool low = (tl == 0), top = (tl == G::T - 1);
+  const uint64_t cin = tile_from_prev<G::T>(acc[K - 1] >> D);
+  const uint64_t topmask = top ? ~0ull : (uint64_t)G::MASK;
+#pragma unroll
+  for (int j = K - 1; j >= 1; --j)
+    acc[j] = (acc[j] & (j == K - 1 ? topmask : (uint64_t)G::MASK)) + (acc[j - 1] >> D);
+  acc[0] = (acc[0] & G::MASK) + (low ? 0ull : cin);
+}
+
 // --------------------------------------------------------- Montgomery product
 // Digits of b consumed per LDS read (1, 2 or 4).
 #ifndef MM_BSTEP
@@ -144,23 +171,27 @@ __device__ __forceinline__ void mont_mul(uint32_t (&out)[G::K], const uint32_t (
     acc[0] += low ? (x0 >> D) : 0ull;
   };
   int i = 0;
-  if constexpr (MM_BSTEP == 4) {
-    for (; i + 4 <= G::S; i += 4) {
-      uint4 v = *reinterpret_cast<const uint4*>(b + i);
-      step(v.x);
-      step(v.y);
-      step(v.z);
-      step(v.w);
-    }
-  } else if constexpr (MM_BSTEP == 2) {
-    for (; i + 2 <= G::S; i += 2) {
-      uint2 v = *reinterpret_cast<const uint2*>(b + i);
-      step(v.x);
-      step(v.y);
-    }
-  } else {
+  for (int seg = 0; seg < G::NSEG; ++seg) {
+    const int end = (seg + 1) * G::SEG < G::S ? (seg + 1) * G::SEG : G::S;
+    if constexpr (MM_BSTEP == 4) {
+      for (; i + 4 <= end; i += 4) {
+        uint4 v = *reinterpret_cast<const uint4*>(b + i);
+        step(v.x);
+        step(v.y);
+        step(v.z);
+        step(v.w);
+      }
+    } else if constexpr (MM_BSTEP == 2) {
+      for (; i + 2 <= end; i += 2) {
+        uint2 v = *reinterpret_cast<const uint2*>(b + i);
+        step(v.x);
+        step(v.y);
+      }
+    } else {
 #pragma unroll 1
-    for (; i + 1 <= G::S; i += 1) step(b[i]);
+      for (; i + 1 <= end; i += 1) step(b[i]);
+    }
+    if (seg + 1 < G::NSEG) renormalise<G>(acc, tl);
   }
 #pragma unroll
   for (int r = 0; r < (G::S % MM_BSTEP); ++r) step(b[i + r]);

@@ -463,9 +463,9 @@ PC2_CLASS(2, 28, 5, 2, 28, 5, 1)
 PC2_CLASS(3, 28, 10, 2, 28, 10, 1)
 PC2_CLASS(4, 28, 19, 2, 28, 19, 1)
 PC2_CLASS(5, 28, 37, 2, 28, 37, 1)
-PC2_CLASS(6, 27, 38, 4, 28, 37, 2)
-PC2_CLASS(7, 27, 29, 8, 27, 29, 4)
-PC2_CLASS(8, 27, 38, 8, 27, 38, 4)
+PC2_CLASS(6, 28, 37, 4, 28, 37, 2)
+PC2_CLASS(7, 28, 28, 8, 28, 28, 4)
+PC2_CLASS(8, 28, 37, 8, 28, 37, 4)
 PC2_CLASS(9, 28, 19, 4, 28, 37, 1)
 PC2_CLASS(10, 27, 19, 8, 28, 37, 2)
 #undef PC2_CLASS

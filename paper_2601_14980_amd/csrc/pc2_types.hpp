@@ -137,7 +137,7 @@ constexpr int NUM_GEOS = 11;
 constexpr ClassGeo CLASS_GEO[NUM_GEOS] = {
     {28, 2, 2, 28, 2, 1},   {28, 3, 2, 28, 3, 1},   {28, 5, 2, 28, 5, 1},
     {28, 10, 2, 28, 10, 1}, {28, 19, 2, 28, 19, 1}, {28, 37, 2, 28, 37, 1},
-    {27, 38, 4, 28, 37, 2}, {27, 29, 8, 27, 29, 4}, {27, 38, 8, 27, 38, 4},
+    {28, 37, 4, 28, 37, 2}, {28, 28, 8, 28, 28, 4}, {28, 37, 8, 28, 37, 4},
     {28, 19, 4, 28, 37, 1},  // class 5 (1024-bit keys), 4 lanes per ciphertext
     {27, 19, 8, 28, 37, 2},  // class 6 (2048-bit keys), 8 lanes per ciphertext
 };

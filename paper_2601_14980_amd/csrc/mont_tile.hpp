@@ -91,9 +91,9 @@ __device__ __forceinline__ uint32_t tile_bcast0(uint32_t v) {
 }
 // value of tile lane t+1 (meaningless in the top lane of the tile)
 template <int T>
-__device__ __forceinline__ uint64_t tile_from_next(uint64_t v) {
+__device__ __forceinline__ uint32_t tile_from_next32(uint32_t v) {
   if constexpr (T == 1) return 0;
-  else return dpp64<DPP_ROW_SHL1>(v);
+  else return dpp32<DPP_ROW_SHL1>(v);
 }
 // value of tile lane t-1 (meaningless in lane 0 of the tile)
 template <int T>
@@ -159,16 +159,20 @@ __device__ __forceinline__ void mont_mul(uint32_t (&out)[G::K], const uint32_t (
   uint64_t acc[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) acc[j] = 0;
-  const bool low = (tl == 0), top = (tl == T - 1);
+  const bool top = (tl == T - 1);
+  // One step: the columns shift down one digit.  Digit 0's low D bits move to
+  // the previous lane's top digit (in lane 0 they are zero by the choice of
+  // m and leave the number) and its high part stays in this lane's digit 0,
+  // so only 32 bits cross lanes.
   auto step = [&](uint32_t bi) {
     uint64_t x0 = mad64(a[0], bi, acc[0]);
     uint32_t m = tile_bcast0<T>(((uint32_t)x0 * nprime) & G::MASK);
     x0 = mad64(m, N[0], x0);
 #pragma unroll
     for (int j = 1; j < K; ++j) acc[j - 1] = mad64(m, N[j], mad64(a[j], bi, acc[j]));
-    uint64_t inc = tile_from_next<T>(x0);
-    acc[K - 1] = top ? 0ull : inc;
-    acc[0] += low ? (x0 >> D) : 0ull;
+    const uint32_t lo = tile_from_next32<T>((uint32_t)x0 & G::MASK);
+    acc[K - 1] = top ? 0ull : (uint64_t)lo;
+    acc[0] += x0 >> D;
   };
   int i = 0;
   for (int seg = 0; seg < G::NSEG; ++seg) {
@@ -209,17 +213,17 @@ __device__ __forceinline__ void mont_redc_wide(uint32_t (&out)[G::K], const uint
   uint64_t acc[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) acc[j] = lo[j];
-  const bool low = (tl == 0), top = (tl == T - 1);
-  for (int i = 0; i < G::S; ++i) {
+  const bool top = (tl == T - 1);
+  for (int i = 0; i < G::S; ++i) {  // the step of mont_mul without the a*b products
     uint32_t hin = hi[i];
     uint64_t x0 = acc[0];
     uint32_t m = tile_bcast0<T>(((uint32_t)x0 * nprime) & G::MASK);
     x0 = mad64(m, N[0], x0);
 #pragma unroll
     for (int j = 1; j < K; ++j) acc[j - 1] = mad64(m, N[j], acc[j]);
-    uint64_t inc = tile_from_next<T>(x0);
-    acc[K - 1] = top ? (uint64_t)hin : inc;
-    acc[0] += low ? (x0 >> D) : 0ull;
+    const uint32_t lo = tile_from_next32<T>((uint32_t)x0 & G::MASK);
+    acc[K - 1] = top ? (uint64_t)hin : (uint64_t)lo;
+    acc[0] += x0 >> D;
   }
   semi_normalise<G>(out, acc, tl);
 }

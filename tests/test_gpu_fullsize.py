@@ -1,0 +1,137 @@
+"""The paper-sized workloads at full size, in the launch shapes bench.py times
+(GPU tests).  The oracle checks sampled elements one by one; every element is
+checked through the exact identity Dec(prod_k Enc(m_k)) = sum_k m_k.
+
+* 2048-bit key, 8 nodes x 65536 quantized N(0,1) values: one encryption
+  launch of 524288, an 8-way aggregation, one decryption launch of 65536.
+* 16 nodes of log-uniform lengths in [1024, 65536] under alternating
+  1024/2048-bit keys: one persistent batch launch per phase.
+* 3072-bit key, 32 x 16384 quantized values (one lasso iteration's
+  crypto): encryption of 524288, 32-way aggregation, decryption of 16384."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import paillier as O
+from oracle import quant as Q
+from workload import gen
+from workload.limbs import ints_from_limbs
+
+pytestmark = pytest.mark.gpu
+
+
+def _sums_exact(pc2, dec: torch.Tensor, mq: np.ndarray) -> bool:
+    """dec: [len][L] plaintexts; mq: [K][len] uint64 quantized addends."""
+    d = pc2.from_device_limbs(dec)
+    got = d[:, 0].astype(object) + (d[:, 1].astype(object) << 32)
+    want = mq.astype(object).sum(axis=0)
+    return bool(np.all(d[:, 2:] == 0)) and bool(np.all(got == want))
+
+
+@pytest.mark.parametrize("nbits,nodes,length,seed", [(2048, 8, 65536, 2), (3072, 32, 16384, 4)],
+                         ids=["2048bit_8x65536", "3072bit_32x16384"])
+def test_full_size_encrypt_aggregate_decrypt(gpu_ctx, nbits, nodes, length, seed):
+    from paper_2601_14980_amd import pc2
+    p, q = gen.primes_for(seed, nbits)
+    n = p * q
+    opk, osk = O.derive_keys(p, q)
+    sk = pc2.SecretKey(gpu_ctx, nbits, p, q)
+    L = sk.L
+    qp = gen.Q_PLAIN
+    xs = gen.normal_vectors(seed, [length] * nodes)
+    rs = np.concatenate([gen.gen_r_limbs(n, length, L, seed, extra=k) for k in range(nodes)])
+    total = nodes * length
+    m = torch.empty(total, dtype=torch.int64, device="cuda")
+    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, torch.from_numpy(np.concatenate(xs)).cuda(),
+                     m)
+    c = torch.empty((total, 2 * L), dtype=torch.int32, device="cuda")
+    pc2.pc2_encrypt(sk.public, m.view(torch.int32).reshape(total, 2), pc2.to_device_limbs(rs), c)
+    agg = torch.empty((length, 2 * L), dtype=torch.int32, device="cuda")
+    pc2.pc2_hom_sum(sk.public, [c[k * length:(k + 1) * length] for k in range(nodes)], agg)
+    dec = torch.empty((length, L), dtype=torch.int32, device="cuda")
+    pc2.pc2_decrypt(sk, agg, dec)
+    xo = torch.empty(length, dtype=torch.float64, device="cuda")
+    pc2.pc2_dequantize(gpu_ctx, qp.log2_scale, qp.offset, dec, nodes, xo)
+    assert gpu_ctx.sync() == 0
+    mq = m.cpu().numpy().view(np.uint64).reshape(nodes, length)
+    assert _sums_exact(pc2, dec, mq), "a decrypted aggregate differs from the integer sum"
+    # sampled elements against the oracle, one by one
+    rng = np.random.default_rng(nbits)
+    for node, j in zip(rng.integers(0, nodes, 3), rng.integers(0, length, 3)):
+        e = int(node) * length + int(j)
+        mv = Q.quantize(float(xs[node][j]), qp.log2_scale, qp.offset)
+        assert int(mq[node, j]) == mv
+        r = int(ints_from_limbs(rs[e:e + 1])[0])
+        want = O.encrypt(opk, mv, r)
+        assert ints_from_limbs(pc2.from_device_limbs(c[e:e + 1]))[0] == want, f"element {e}"
+    j = int(rng.integers(0, length))
+    cts = [ints_from_limbs(pc2.from_device_limbs(c[k * length + j:k * length + j + 1]))[0]
+           for k in range(nodes)]
+    want_agg = O.hom_sum(opk, cts)
+    assert ints_from_limbs(pc2.from_device_limbs(agg[j:j + 1]))[0] == want_agg
+    assert ints_from_limbs(pc2.from_device_limbs(dec[j:j + 1]))[0] == O.decrypt(osk, want_agg)
+    want_x = Q.dequantize(int(mq[:, j].astype(object).sum()), qp.log2_scale, qp.offset, nodes)
+    assert float(xo[j].item()) == want_x
+
+
+def test_full_size_batches(gpu_ctx):
+    """16 nodes, lengths log-uniform in [1024, 65536], keys alternating
+    1024/2048-bit: encryptions, ragged aggregation and decryptions, one
+    persistent launch each."""
+    from paper_2601_14980_amd import pc2
+    seed = 3
+    lengths = gen.log_uniform_lengths(seed, 16, 1024, 65536)
+    keys = []
+    for bits in (1024, 2048):
+        p, q = gen.primes_for(seed, bits)
+        keys.append(dict(sk=pc2.SecretKey(gpu_ctx, bits, p, q), opk=O.derive_keys(p, q)[0],
+                         n=p * q))
+    xs = gen.normal_vectors(seed, lengths)
+    qp = gen.Q_PLAIN
+    nodes = []
+    for i, Ln in enumerate(lengths):
+        k = keys[i % 2]
+        m = torch.empty(Ln, dtype=torch.int64, device="cuda")
+        pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, torch.from_numpy(xs[i]).cuda(), m)
+        rl = gen.gen_r_limbs(k["n"], Ln, k["sk"].L, seed, extra=i)
+        nodes.append(dict(k=k, L=Ln, m=m, rl=rl, r=pc2.to_device_limbs(rl),
+                          c=torch.empty((Ln, 2 * k["sk"].L), dtype=torch.int32, device="cuda")))
+    groups = []
+    for g, k in enumerate(keys):
+        mem = [nd for i, nd in enumerate(nodes) if i % 2 == g]
+        mx = max(nd["L"] for nd in mem)
+        groups.append(dict(k=k, mem=mem, mx=mx,
+                           agg=torch.empty((mx, 2 * k["sk"].L), dtype=torch.int32, device="cuda"),
+                           dec=torch.empty((mx, k["sk"].L), dtype=torch.int32, device="cuda")))
+    assert gpu_ctx.sync() == 0
+    enc = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_ENCRYPT, pk=nd["k"]["sk"].public,
+                                   m=nd["m"].view(torch.int32).reshape(nd["L"], 2), r=nd["r"],
+                                   out=nd["c"]) for nd in nodes])
+    agg = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_HOM_SUM, pk=g["k"]["sk"].public,
+                                   inputs=[nd["c"] for nd in g["mem"]],
+                                   lengths=[nd["L"] for nd in g["mem"]], out=g["agg"])
+                              for g in groups])
+    dec = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_DECRYPT, sk=g["k"]["sk"], c=g["agg"],
+                                   out=g["dec"]) for g in groups])
+    for b in (enc, agg, dec):
+        b.run(0)
+    assert gpu_ctx.sync() == 0
+    for g in groups:
+        want = np.zeros(g["mx"], dtype=object)
+        for nd in g["mem"]:
+            want[:nd["L"]] += nd["m"].cpu().numpy().view(np.uint64).astype(object)
+        d = pc2.from_device_limbs(g["dec"])
+        got = d[:, 0].astype(object) + (d[:, 1].astype(object) << 32)
+        assert bool(np.all(d[:, 2:] == 0)) and bool(np.all(got == want))
+    rng = np.random.default_rng(5)
+    for i in (0, 1, 15):
+        nd = nodes[i]
+        j = int(rng.integers(0, nd["L"]))
+        mv = int(nd["m"][j].item())
+        r = int(ints_from_limbs(nd["rl"][j:j + 1])[0])
+        got = ints_from_limbs(pc2.from_device_limbs(nd["c"][j:j + 1]))[0]
+        assert got == O.encrypt(nd["k"]["opk"], mv, r), f"node {i}, element {j}"
+    for b in (enc, agg, dec):
+        b.close()

@@ -318,7 +318,7 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
     budget = 4 << 30
 
     def serve(reqs):
-        sch = Scheduler(ex, hbm_budget=budget, tick_groups=4096)
+        sch = Scheduler(ex, hbm_budget=budget, tick_groups=args.serve_tick_groups)
         span = sch.run_trace(reqs)
         torch.cuda.synchronize()
         lat = [r.latency for r in sch.finished]
@@ -343,6 +343,7 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
         f"at 0.7x capacity ({0.7 * cap:.0f} req/s) p50 {sub['p50_ms']} ms p99 {sub['p99_ms']} ms")
     return {"workload": f"{n} requests per run, Poisson arrivals, encrypt/aggregate/decrypt 1/3 each, "
                         "lengths log-uniform [256, 65536], 2048-bit key, HBM budget 4 GiB",
+            "tick_groups": args.serve_tick_groups,
             "configured_2000_req_s": hot, "sub_saturation_0p7_capacity": sub}
 
 
@@ -642,6 +643,8 @@ def main() -> int:
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-tick-groups", type=int, default=2048,
+                    help="element groups per serving launch (16 encryptions each at 2048 bits)")
     ap.add_argument("--no-admm", action="store_true")
     ap.add_argument("--no-matvec", action="store_true")
     ap.add_argument("--no-key4096", action="store_true")

@@ -40,6 +40,7 @@ struct pc2_runner {
   void* host = nullptr;  // pinned staging, same layout
   size_t jobs_b = 0, items_b = 0, ptr_b = 0;
   uint32_t* scratch = nullptr;
+  uint32_t* stage = nullptr;  // decryption: CRT halves of one launch's groups
   hipEvent_t copied = nullptr;
   bool pending = false;
 };
@@ -63,6 +64,7 @@ struct pc2_batch {
   pc2k::BatchItem* items = nullptr;
   int* queue = nullptr;
   uint32_t* scratch = nullptr;
+  uint32_t* stage = nullptr;  // decryption: CRT halves of every job's elements
   hipGraphExec_t exec = nullptr;
   void* graph_stream = nullptr;
 };
@@ -1036,12 +1038,25 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     if (pass == 1 && pa == pb) break;
     for (size_t ji = 0; ji < dj.size(); ++ji) {
       if (dj[ji].geo != want) continue;
-      const size_t epw = (size_t)pc2k::elems_per_block(dj[ji].geo);
+      const size_t epw = (size_t)pc2k::batch_group_elems(op, dj[ji].geo);
       const size_t groups = (dj[ji].count + epw - 1) / epw;
-      for (size_t g = 0; g < groups; ++g) items.push_back(pc2k::BatchItem{(int)ji, 0, g});
+      for (size_t g = 0; g < groups; ++g) {
+        items.push_back(pc2k::BatchItem{(int)ji, 0, g});
+        if (op == pc2k::OP_DEC) items.push_back(pc2k::BatchItem{(int)ji, 1, g});
+      }
     }
   }
   b->nitems = (int)items.size();
+  // decryption: staging for the two CRT halves of every element
+  std::vector<size_t> stage_off(dj.size(), 0);
+  size_t stage_words = 0;
+  if (op == pc2k::OP_DEC) {
+    for (size_t ji = 0; ji < dj.size(); ++ji) {
+      const size_t epw = (size_t)pc2k::batch_group_elems(op, dj[ji].geo);
+      stage_off[ji] = stage_words;
+      stage_words += (dj[ji].count + epw - 1) / epw * epw * 2 * (size_t)(dj[ji].sk.h[0].Ls + 1);
+    }
+  }
   // one device allocation: jobs | items | pointer/length arrays | queue
   const size_t jobs_b = (dj.size() * sizeof(pc2k::BatchJob) + 255) & ~(size_t)255;
   const size_t items_b = (items.size() * sizeof(pc2k::BatchItem) + 255) & ~(size_t)255;
@@ -1050,6 +1065,13 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
   int rc = PC2_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) rc = PC2_E_DEVICE;
   if (!rc && hipMalloc(&b->dev, total) != hipSuccess) rc = PC2_E_NOMEM;
+  if (!rc && stage_words && hipMalloc(&b->stage, stage_words * 4) != hipSuccess)
+    rc = PC2_E_NOMEM;
+  if (!rc && stage_words)
+    for (size_t ji = 0; ji < dj.size(); ++ji) {
+      dj[ji].stage = b->stage + stage_off[ji];
+      dj[ji].stage_g0 = 0;
+    }
   if (!rc) {
     char* base = (char*)b->dev;
     b->jobs = (pc2k::BatchJob*)base;
@@ -1089,6 +1111,7 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
   if (rc) {
     if (b->dev) (void)hipFree(b->dev);
     if (b->scratch) (void)hipFree(b->scratch);
+    if (b->stage) (void)hipFree(b->stage);
     delete b;
     return rc;
   }
@@ -1137,6 +1160,7 @@ int pc2_batch_destroy(pc2_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->dev) (void)hipFree(b->dev);
   if (b->scratch) (void)hipFree(b->scratch);
+  if (b->stage) (void)hipFree(b->stage);
   delete b;
   return PC2_OK;
 }
@@ -1250,7 +1274,9 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
   r->max_groups = max_groups;
   r->max_ptrs = op == pc2k::OP_SUM ? 2 * (size_t)pc2k::RK_MAX * max_jobs : 0;
   r->jobs_b = (max_jobs * sizeof(pc2k::BatchJob) + 255) & ~(size_t)255;
-  r->items_b = (max_groups * sizeof(pc2k::BatchItem) + 255) & ~(size_t)255;
+  // a decryption group is two items (one per prime)
+  const size_t max_items = (op == pc2k::OP_DEC ? 2 : 1) * max_groups;
+  r->items_b = (max_items * sizeof(pc2k::BatchItem) + 255) & ~(size_t)255;
   r->ptr_b = (r->max_ptrs * sizeof(size_t) + 255) & ~(size_t)255;
   const size_t total = r->jobs_b + r->items_b + r->ptr_b + 256;
   int rc = PC2_OK;
@@ -1287,11 +1313,19 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
     r->slot_words = (words + 3) & ~(size_t)3;
     const size_t bytes = (size_t)r->grid_cap * tiles * r->slot_words * 4;
     if (bytes && hipMalloc(&r->scratch, bytes) != hipSuccess) rc = PC2_E_NOMEM;
+    if (!rc && op == pc2k::OP_DEC) {  // CRT halves of up to max_groups groups
+      size_t per = 0;
+      for (int g = 0; g < pc2k::NUM_GEOS; ++g)
+        if (pc2k::GEO_CLASS[g] <= cls && pc2k::batch_group_elems(op, g) > 0)
+          per = std::max(per, (size_t)pc2k::batch_group_elems(op, g) * 2 * (Ls + 1));
+      if (hipMalloc(&r->stage, max_groups * per * 4) != hipSuccess) rc = PC2_E_NOMEM;
+    }
   }
   if (rc) {
     if (r->dev) (void)hipFree(r->dev);
     if (r->host) (void)hipHostFree(r->host);
     if (r->scratch) (void)hipFree(r->scratch);
+    if (r->stage) (void)hipFree(r->stage);
     if (r->copied) (void)hipEventDestroy(r->copied);
     delete r;
     return rc;
@@ -1302,7 +1336,8 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
 
 int pc2_runner_group_size(const pc2_pk* pk, int op_abi, uint32_t* elems) {
   if (!pk || !pk->ctx || !elems || op_from_abi(op_abi) < 0) return PC2_E_INVAL;
-  *elems = (uint32_t)pc2k::elems_per_block(job_geo(pk->ctx, pk, op_from_abi(op_abi)));
+  const int op = op_from_abi(op_abi);
+  *elems = (uint32_t)pc2k::batch_group_elems(op, job_geo(pk->ctx, pk, op));
   return PC2_OK;
 }
 
@@ -1320,7 +1355,7 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     const pc2_pk* pk = (op == pc2k::OP_DEC) ? (j.sk ? &j.sk->pk : nullptr) : j.pk;
     if (!pk || pk->ctx != ctx || !j.out || pk->cls > r->max_cls) return PC2_E_INVAL;
     const int g = job_geo(ctx, pk, op);
-    const size_t epw = (size_t)pc2k::elems_per_block(g);
+    const size_t epw = (size_t)pc2k::batch_group_elems(op, g);
     if (first[i] + ngroups[i] > (j.count + epw - 1) / epw) return PC2_E_INVAL;
     if (op == pc2k::OP_ENC && (!j.in0 || !j.in1 || j.m_limbs < 1 || (int)j.m_limbs > pk->L))
       return PC2_E_INVAL;
@@ -1350,7 +1385,7 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
   auto* hi = (pc2k::BatchItem*)(hb + r->jobs_b);
   auto* hp = (size_t*)(hb + r->jobs_b + r->items_b);
   auto* dp = (size_t*)(db + r->jobs_b + r->items_b);
-  size_t pofs = 0, it = 0;
+  size_t pofs = 0, it = 0, sofs = 0;
   const int pa = pc2k::batch_pair_geo(pair, 0), pb = pc2k::batch_pair_geo(pair, 1);
   for (size_t i = 0; i < njobs; ++i) {
     const pc2_job& j = jobs[i];
@@ -1366,6 +1401,12 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     d.in1 = j.in1;
     d.out = j.out;
     d.count = j.count;
+    if (op == pc2k::OP_DEC) {  // this launch's groups of job i, back to back
+      const size_t epw = (size_t)pc2k::batch_group_elems(op, d.geo);
+      d.stage = r->stage + sofs;
+      d.stage_g0 = first[i];
+      sofs += ngroups[i] * epw * 2 * (size_t)(d.sk.h[0].Ls + 1);
+    }
     if (op == pc2k::OP_SUM) {
       for (uint32_t k = 0; k < j.K; ++k) hp[pofs + k] = (size_t)j.inputs[k];
       for (uint32_t k = 0; k < j.K; ++k) hp[pofs + j.K + k] = j.lengths ? j.lengths[k] : j.count;
@@ -1382,7 +1423,10 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     if (pass == 1 && pa == pb) break;
     for (size_t i = 0; i < njobs; ++i) {
       if (hj[i].geo != want) continue;
-      for (size_t g = 0; g < ngroups[i]; ++g) hi[it++] = pc2k::BatchItem{(int)i, 0, first[i] + g};
+      for (size_t g = 0; g < ngroups[i]; ++g) {
+        hi[it++] = pc2k::BatchItem{(int)i, 0, first[i] + g};
+        if (op == pc2k::OP_DEC) hi[it++] = pc2k::BatchItem{(int)i, 1, first[i] + g};
+      }
     }
   }
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1410,6 +1454,7 @@ int pc2_runner_destroy(pc2_runner* r) {
   if (r->dev) (void)hipFree(r->dev);
   if (r->host) (void)hipHostFree(r->host);
   if (r->scratch) (void)hipFree(r->scratch);
+  if (r->stage) (void)hipFree(r->stage);
   if (r->copied) (void)hipEventDestroy(r->copied);
   delete r;
   return PC2_OK;

@@ -82,6 +82,8 @@ int batch_pair_geo(int pair, int which);
 int batch_npairs();
 const void* batch_kernel(int op, int pair);
 void batch_slot_shape(int op, int geo, int w, int Ls, int* tiles, size_t* words);
+// elements per work item of a batch (decryption: per prime-half group)
+int batch_group_elems(int op, int geo);
 hipError_t launch_batch(int op, int pair, int grid, const BatchJob* jobs, const BatchItem* items,
                         int nitems, int* queue, uint32_t* scratch, size_t slot_words, int w_a,
                         int w_b, int* err, void* stream);

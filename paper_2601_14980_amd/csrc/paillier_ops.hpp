@@ -123,30 +123,6 @@ __device__ __forceinline__ void decrypt_half_finish(const HalfConst& H, uint32_t
   *flag = good ? 1u : 0u;
 }
 
-// Lane 0 of the p half-tile: CRT recombination m = m_q + q ((m_p - m_q) q^-1 mod p)
-// (Lemma 1 for the moduli p, q, in Garner's form) and the store of L limbs.
-__device__ __forceinline__ void garner_store(const SkConst& sk, const uint32_t* slot_p,
-                                             const uint32_t* slot_q, uint32_t* dst, bool live,
-                                             int* err, uint32_t* work) {
-  const int Ls = sk.h[0].Ls, L = sk.pk.L;
-  const uint32_t* mp = slot_p + 4 * Ls + 2;
-  const uint32_t* mq = slot_q + 4 * Ls + 2;
-  const bool good = slot_p[5 * Ls + 2] && slot_q[5 * Ls + 2];
-  uint32_t* d = work;                  // Ls
-  uint32_t* h = work + Ls;             // Ls
-  uint32_t* tmp = work + 2 * Ls;       // Ls + 2
-  uint32_t* prod = work + 3 * Ls + 2;  // 2 Ls
-  for (int i = 0; i < Ls; ++i) d[i] = mp[i];
-  // m_q < q < p, so one conditional addition of p reduces the difference
-  if (sc_sub(d, Ls, mq, Ls)) sc_add(d, Ls, sk.h[0].s, Ls);
-  sc_montmul(h, d, sk.QI, sk.h[0].s, sk.h[0].s_n0, Ls, tmp);
-  sc_mul(prod, sk.h[1].s, Ls, h, Ls);
-  sc_add(prod, 2 * Ls, mq, Ls);
-  if (live) {
-    for (int i = 0; i < L; ++i) dst[i] = (good && i < 2 * Ls) ? prod[i] : 0u;
-    if (!good) atomicOr(err, pc2k::ERR_RANGE);
-  }
-}
 
 // Lane 0 of a tile: canonical limbs of the tile's LDS value to dst (nl limbs),
 // zeros and the error latch if !ok.
@@ -201,41 +177,6 @@ __device__ __forceinline__ void enc_group(const PkConst& pk, const uint32_t* __r
   to_lds<G>(lds, x, tl);
   lds_sync();
   if (tl == 0) store_canonical<G>(lds, pk.n2, c + e * L2, live, ok, err);
-}
-
-template <class Gn, class Gp>
-__device__ __forceinline__ void dec_group(const SkConst& sk, const uint32_t* __restrict__ c,
-                                          uint32_t* __restrict__ m, size_t count, size_t gi,
-                                          uint32_t* lds_all, uint32_t* slots, size_t slot_words,
-                                          int w, int* err) {
-  constexpr int TP = Gp::T, EPW = 64 / (2 * TP);
-  const int tl = threadIdx.x & (TP - 1);
-  const int ht = threadIdx.x / TP;  // half-tile index
-  const int half = ht & 1;
-  const int elem = ht >> 1;
-  uint32_t* lds = lds_all + ht * Gp::SP;
-  uint32_t* slot = slots + ht * slot_words;
-  const HalfConst H = half ? sk.h[1] : sk.h[0];
-  uint32_t N[Gp::K];
-  load_chunk<Gp>(N, H.s2.N, tl);
-  const uint32_t np = H.s2.nprime;
-  const int L = sk.pk.L, L2 = 2 * L;
-  size_t e = gi * EPW + elem;
-  const bool live = e < count;
-  if (!live) e = count - 1;
-  const uint32_t* ce = c + e * L2;
-  uint32_t cv = 1;
-  if (tl == 0) cv = sc_cmp(ce, L2, sk.pk.n2.Nl, L2) < 0;
-  Program P = decrypt_program<Gp>(H, sk.ebits, ce, L2, slot, tl, w, false);
-  uint32_t x[Gp::K];
-  run_program<Gp>(P, x, lds, slot, w, N, np, tl);
-  lds_sync();
-  to_lds<Gp>(lds, x, tl);
-  lds_sync();
-  if (tl == 0) decrypt_half_finish<Gp>(H, lds, slot, cv);
-  lds_sync();
-  if (tl == 0 && half == 0)
-    garner_store(sk, slot, slot + slot_words, m + e * L, live, err, slot + 6 * H.Ls + 4);
 }
 
 // One CRT half (prime s = p for half 0, q for half 1) of the decryption of

@@ -98,15 +98,18 @@ struct BatchJob {
   size_t count;                   // output elements
   const uint32_t* const* inputs;  // hom_sum: K device pointers
   const size_t* lengths;          // hom_sum: K input lengths (may be null)
+  uint32_t* stage;                // decrypt: the CRT halves of groups stage_g0.. (2 (Ls + 1)
+  size_t stage_g0;                //   words per element, element-major)
 };
 // Largest prime, in 32-bit limbs, that a secret key may hold (the 4096-bit
 // class admits primes of up to 2093 bits).
 constexpr int LS_MAX = 66;
 
-// A work item: one wavefront's group of elements of one job.
+// A work item: one wavefront's group of elements of one job (decryption:
+// one prime, `half`, of the group).
 struct BatchItem {
   int job;
-  int pad;
+  int half;
   size_t group;
 };
 

@@ -38,6 +38,7 @@ def _rel(a, b):
 @pytest.mark.parametrize("M,N,K,rho,k,nbits,iters", [
     (40, 90, 3, 1.0, 30, 256, 6),
     (120, 600, 3, 1.5, 40, 1024, 3),
+    (30, 20, 1, 0.5, 24, 2048, 4),       # one node; rho < 1 scales the threshold up
 ])
 def test_colsplit_matches_oracle(gpu_ctx, M, N, K, rho, k, nbits, iters):
     from paper_2601_14980_amd import pc2

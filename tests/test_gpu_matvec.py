@@ -68,6 +68,21 @@ def test_matvec_matches_oracle(gpu_ctx, nbits, window, with_alpha):
     assert got == O.hom_matvec(opk, B, cs, alpha)
 
 
+@pytest.mark.parametrize("nbits,rows,cols", [(3072, 9, 4), (4096, 5, 3)])
+def test_matvec_large_keys(gpu_ctx, nbits, rows, cols):
+    """The 3072- and 4096-bit classes (28-bit digits on 8 lanes, renormalised
+    products) with a ragged wavefront of rows."""
+    sk, opk, _ = _key(gpu_ctx, nbits, seed=10)
+    n2 = opk.n2
+    rng = random.Random(nbits)
+    cs = [rng.randrange(n2) for _ in range(cols)]
+    B = [[rng.getrandbits(40) for _ in range(cols)] for _ in range(rows)]
+    alpha = [rng.randrange(n2) for _ in range(rows)]
+    got, st, _ = _run(gpu_ctx, sk, B, cs, alpha, ebits=40, window=5)
+    assert st == 0
+    assert got == O.hom_matvec(opk, B, cs, alpha)
+
+
 def test_matvec_column_chunks_combine(gpu_ctx):
     """Few rows and many columns: the rows are split over column chunks whose
     partial products are multiplied afterwards."""

@@ -101,8 +101,11 @@ int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
  * batches and runners of encryptions), i.e. how many lanes of a wavefront
  * share one ciphertext.  1024-bit keys run with 2 (own) or 4 lanes,
  * 2048-bit keys with 4 (own) or 8; other sizes have their own tile only.
- * Values: 0 = automatic (the tile pc2_autotune chose for the key's class,
- * else the class's own); 2, 4 or 8 = that many lanes where the class has
+ * Values: 0 = automatic (pc2_encrypt of at most one wavefront per SIMD of
+ * the wider tile, i.e. count <= 4 * CUs * 64 / lanes, takes the wider tile,
+ * which has the shorter latency; larger calls, batches and runners take the
+ * tile pc2_autotune chose for the key's class, else the class's own);
+ * 2, 4 or 8 = that many lanes where the class has
  * such a tile, else its own; PC2_TILE_WIDE = the alternative tile of every
  * class that has one.  Fewer lanes mean more 27/28-bit digits per lane and
  * fewer lane exchanges per digit; more lanes mean fewer registers and more

@@ -454,15 +454,19 @@ int window_for(const pc2_ctx* ctx, int geo, int op) {
   return t ? t : auto_window(geo, op);
 }
 
-// Geometry of an encryption under the key class cls: the alternative tile
-// if PC2_OPT_TILE asks for wide tiles or names its lane count, the class's
-// own tile for any other lane count, else (automatic) the autotuned one,
-// else the class's own.
-int enc_geo(const pc2_ctx* ctx, int cls) {
+// Geometry of an encryption of `count` elements under the key class cls:
+// the alternative tile if PC2_OPT_TILE asks for wide tiles or names its lane
+// count, the class's own tile for any other lane count.  Automatic: a launch
+// that gives every SIMD at most one wavefront of the (wider) alternative tile
+// is latency-bound, and the wider tile finishes it sooner, so it takes that;
+// a larger one takes the autotuned tile, else the class's own.  Batches and
+// runners pass no count (their geometry is fixed per key when groups are cut).
+int enc_geo(const pc2_ctx* ctx, int cls, size_t count = SIZE_MAX) {
   const int alt = pc2k::ALT_GEO[cls];
   if (alt < 0) return cls;
   if (ctx->tile == PC2_TILE_WIDE) return alt;
   if (ctx->tile) return pc2k::CLASS_GEO[alt].nT == ctx->tile ? alt : cls;
+  if (count <= (size_t)ctx->cus * 4 * (size_t)pc2k::elems_per_block(alt)) return alt;
   return ctx->tuned_geo[cls] >= 0 ? ctx->tuned_geo[cls] : cls;
 }
 // the key's constants in geometry geo (its own class or its alternative tile)
@@ -821,7 +825,7 @@ int pc2_encrypt(const pc2_pk* pk, const uint32_t* m, uint32_t m_limbs, const uin
     return status_of(
         pc2k::launch_encrypt_mfma(pk->cls, l, pk->c, m, (int)m_limbs, r, c, count));
   }
-  const int geo = enc_geo(pk->ctx, pk->cls);
+  const int geo = enc_geo(pk->ctx, pk->cls, count);
   int rc = prepare(pk->ctx, geo, pc2k::OP_ENC, count, 0, pk->L, &l, stream);
   if (rc) return rc;
   return status_of(

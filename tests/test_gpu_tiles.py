@@ -145,6 +145,46 @@ def test_tile_option_validation(tctx):
     assert tctx.get_option(pc2.PC2_OPT_TILE) == 0
 
 
+@pytest.mark.parametrize("bits", BITS)
+def test_tile_auto_latency_threshold(tctx, setup, bits):
+    """Automatic tile: a call of at most one wavefront per SIMD of the wider
+    tile (4 * CUs * 64 / lanes elements) runs in the wider tile, one element
+    more in the class's own; both sides of the threshold must give the own
+    tile's ciphertexts."""
+    from paper_2601_14980_amd import pc2
+    k = setup["keys"][BITS.index(bits)]
+    L = k["sk"].L
+    wide = {1024: 4, 2048: 8}[bits]
+    edge = 4 * torch.cuda.get_device_properties(0).multi_processor_count * (64 // wide)
+    count = edge + 1
+    g = torch.Generator().manual_seed(bits)
+    m = torch.randint(0, 2**31, (count, 2), generator=g, dtype=torch.int64).to(torch.int32).cuda()
+    rl = gen.gen_r_limbs(k["n"], count, L, 6)
+    r = pc2.to_device_limbs(rl)
+    ref = torch.full((count, 2 * L), -1, dtype=torch.int32, device="cuda")
+    tctx.set_option(pc2.PC2_OPT_TILE, {1024: 2, 2048: 4}[bits])
+    try:
+        pc2.pc2_encrypt(k["sk"].public, m, r, ref)
+        assert tctx.sync() == 0
+    finally:
+        tctx.set_option(pc2.PC2_OPT_TILE, 0)
+    for n in (edge, count):
+        out = torch.full((n, 2 * L), -1, dtype=torch.int32, device="cuda")
+        pc2.pc2_encrypt(k["sk"].public, m[:n], r[:n], out)
+        assert tctx.sync() == 0
+        assert torch.equal(out, ref[:n]), f"{bits}-bit, {n} elements"
+    mh = m.cpu().numpy().view("uint32").astype(object)
+    for j in (0, edge - 1, edge):
+        mv = int(mh[j, 0]) + (int(mh[j, 1]) << 32)
+        rv = int(ints_from_limbs(rl[j:j + 1])[0])
+        assert _ct(ref, j) == O.encrypt(k["opk"], mv, rv), j
+
+
+def _ct(t, j):
+    from paper_2601_14980_amd import pc2
+    return ints_from_limbs(pc2.from_device_limbs(t[j:j + 1]))[0]
+
+
 def test_autotune_picks_a_tile(tctx, setup):
     from paper_2601_14980_amd import pc2
     for k, lanes in zip(setup["keys"], ((2, 4), (4, 8))):

@@ -271,10 +271,11 @@ SERVE_SEED = 5
 def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
     """Poisson arrivals of encrypt / aggregate / decrypt requests (1/3 each),
     lengths log-uniform in [256, 65536], the 2048-bit key resident, K ~ U{2..8}
-    resident ciphertext vectors per aggregate, admission by a 4 GiB budget.
-    Run at the configured 2000 req/s (overload: latency is queueing) and at
-    0.7x the capacity that run measured."""
-    from paper_2601_14980_amd.serve import GpuExecutor, Request, Scheduler, percentile
+    resident ciphertext vectors per aggregate, admission by a 4 GiB budget,
+    served by libpc2's request server.  Run at the configured 2000 req/s
+    (overload: latency is queueing) and at 0.7x the capacity that run
+    measured."""
+    from paper_2601_14980_amd.serve import Request, percentile, serve_trace
     import random
     L = sk.L
     PL = 65536
@@ -304,33 +305,53 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
             op = ("encrypt", "aggregate", "decrypt")[r.randrange(3)]
             length = int(round(np.exp(r.uniform(np.log(256), np.log(65536)))))
             req = Request(rid=i, op=op, length=length, arrival=t)
+            width = L if op == "decrypt" else 2 * L
+            res = torch.empty((length, width), dtype=torch.int32, device="cuda")
             if op == "encrypt":
-                req.payload = dict(m=mpool2[:length], r=rpool[:length])
+                req.payload = dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=mpool2[:length],
+                                   r=rpool[:length], out=res)
             elif op == "aggregate":
                 req.K = r.randint(2, 8)
-                req.payload = dict(inputs=[cpool[j] for j in r.sample(range(8), req.K)])
+                req.payload = dict(op=pc2.PC2_OP_HOM_SUM, pk=sk.public,
+                                   inputs=[cpool[j] for j in r.sample(range(8), req.K)], out=res)
             else:
-                req.payload = dict(c=cpool[r.randrange(8)][:length])
+                req.payload = dict(op=pc2.PC2_OP_DECRYPT, sk=sk,
+                                   c=cpool[r.randrange(8)][:length], out=res)
             out.append(req)
         return out
 
-    ex = GpuExecutor(ctx, sk, max_groups=1 << 16, max_jobs=1024)
     budget = 4 << 30
 
+    def alone_equal(req) -> bool:
+        job = req.payload
+        ref = torch.empty_like(job["out"])
+        if req.op == "encrypt":
+            pc2.pc2_encrypt(sk.public, job["m"], job["r"], ref)
+        elif req.op == "aggregate":
+            pc2.pc2_hom_sum(sk.public, [c[:req.length] for c in job["inputs"]], ref)
+        else:
+            pc2.pc2_decrypt(sk, job["c"], ref)
+        return bool(torch.equal(ref, job["out"]))
+
     def serve(reqs):
-        sch = Scheduler(ex, hbm_budget=budget, tick_groups=args.serve_tick_groups)
-        span = sch.run_trace(reqs)
+        srv = pc2.Server(ctx, sk, hbm_budget=budget, tick_groups=args.serve_tick_groups,
+                         max_requests=1024)
+        span = serve_trace(srv, reqs)
         torch.cuda.synchronize()
-        lat = [r.latency for r in sch.finished]
-        ed = sum(r.length for r in sch.finished if r.op in ("encrypt", "decrypt"))
-        return dict(requests=len(sch.finished), rejected=len(sch.rejected),
+        st = srv.stats()
+        srv.close()
+        lat = [r.latency for r in reqs]
+        ed = sum(r.length for r in reqs if r.op in ("encrypt", "decrypt"))
+        sample = [reqs[i] for i in (0, len(reqs) // 2, len(reqs) - 1)]
+        return dict(requests=len(reqs),
                     rate_req_per_s=round(len(reqs) / max(reqs[-1].arrival - reqs[0].arrival
                                                          + 1e-9, 1e-9), 1),
                     p50_ms=round(1e3 * percentile(lat, 50), 2),
                     p99_ms=round(1e3 * percentile(lat, 99), 2),
-                    makespan_s=round(span, 3), launches=sch.ticks,
+                    makespan_s=round(span, 3), launches=st["launches"],
                     enc_dec_ops_per_s=round(ed / span, 1),
-                    max_hbm_bytes=sch.max_used)
+                    max_hbm_bytes=st["max_bytes"],
+                    sampled_requests_equal_alone=all(alone_equal(r) for r in sample))
 
     n = args.serve_requests
     hot = serve(make_trace(n, 2000.0, SERVE_SEED))
@@ -338,11 +359,11 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
     sub = serve(make_trace(n, 0.7 * cap, SERVE_SEED + 1))
     if ctx.sync() != 0:
         raise RuntimeError("device reported a data error while serving")
-    ex.close()
     log(f"serving: offered 2000 req/s -> p50 {hot['p50_ms']} ms p99 {hot['p99_ms']} ms; "
         f"at 0.7x capacity ({0.7 * cap:.0f} req/s) p50 {sub['p50_ms']} ms p99 {sub['p99_ms']} ms")
     return {"workload": f"{n} requests per run, Poisson arrivals, encrypt/aggregate/decrypt 1/3 each, "
-                        "lengths log-uniform [256, 65536], 2048-bit key, HBM budget 4 GiB",
+                        "lengths log-uniform [256, 65536], 2048-bit key, HBM budget 4 GiB, "
+                        "libpc2 request server",
             "tick_groups": args.serve_tick_groups,
             "configured_2000_req_s": hot, "sub_saturation_0p7_capacity": sub}
 

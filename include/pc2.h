@@ -138,6 +138,9 @@ int pc2_pk_destroy(pc2_pk *pk);
 int pc2_sk_destroy(pc2_sk *sk);
 /* Bit size and limb count L of a key. */
 int pc2_pk_info(const pc2_pk *pk, uint32_t *nbits, uint32_t *limbs);
+/* The context a key was created in, and that context's HIP device (either
+ * output may be NULL). */
+int pc2_pk_context(const pc2_pk *pk, pc2_ctx **ctx, int *hip_device);
 
 /* ------------------------------------------------------------ data calls */
 
@@ -339,6 +342,72 @@ int pc2_runner_group_size(const pc2_pk *pk, int op, uint32_t *elems);
 int pc2_runner_launch(pc2_runner *runner, const pc2_job *jobs, const size_t *first,
                       const size_t *ngroups, size_t njobs, void *hip_stream);
 int pc2_runner_destroy(pc2_runner *runner);
+
+/* --------------------------------------------------------------- serving
+ *
+ * A request server (continuous batching) for one private key: clients submit
+ * encryptions, aggregations and decryptions of vectors of any length as they
+ * arrive and poll for completion by request id.  A request is admitted when
+ * the bytes of its inputs and output (encrypt: count * (4 m_limbs + 12 L);
+ * hom_sum: count * 8 L (K + 1); decrypt: count * 12 L) fit in the server's
+ * HBM budget beside those already admitted, first come, first served.  Each
+ * operation has its own persistent launcher and stream; whenever a stream is
+ * idle, the next scheduling pass launches up to tick_groups element groups
+ * (pc2_runner_group_size elements each) drawn from every admitted request of
+ * that operation -- an equal slice each, then the rest to the oldest -- so
+ * requests that arrive while others run join the next launch and the three
+ * operations overlap on the device.  Results are identical to the one-call
+ * entry points.
+ *
+ * Every pc2_serve_* call makes one scheduling pass (retire finished
+ * launches, admit, launch on idle streams); nothing advances between calls,
+ * so a client waiting for results keeps calling pc2_serve_poll,
+ * pc2_serve_progress or pc2_serve_completed.  A server is used from one host
+ * thread at a time; data errors latch in the context as for every data call.
+ * A status other than PC2_OK from a pass (PC2_E_DEVICE) leaves the server
+ * unusable: destroy it. */
+typedef struct pc2_server pc2_server;
+
+/* sk: the key every request uses (created in ctx).  hbm_budget: bytes of
+ * admitted requests at once (0 = half the device memory free now).
+ * tick_groups: element groups per launch.  max_requests: requests tracked at
+ * once (submitted and not yet reported done).  Allocates the three
+ * launchers, streams and events. */
+int pc2_server_create(pc2_ctx *ctx, const pc2_sk *sk, size_t hbm_budget, size_t tick_groups,
+                      size_t max_requests, pc2_server **out);
+
+/* Queue one request: a pc2_job (as for pc2_batch_create) with op, the
+ * server's key (pk = pc2_sk_public(sk) for encrypt and hom_sum, sk for
+ * decrypt), device inputs and a device output of count elements, all owned
+ * by the caller and valid until the request is reported done.  The HOST
+ * arrays of a hom_sum job are copied.  *req_id receives the request's id.
+ * PC2_E_INVAL for a bad job or another key; PC2_E_NOMEM if the request could
+ * never fit the budget; PC2_E_BUSY if max_requests are tracked.  count == 0
+ * completes at once. */
+int pc2_serve_submit(pc2_server *srv, const pc2_job *job, uint64_t *req_id);
+
+/* One pass, then *done = 1 if request req_id has finished (its output is
+ * complete on the device); the id is then forgotten.  PC2_E_INVAL for an id
+ * the server does not track. */
+int pc2_serve_poll(pc2_server *srv, uint64_t req_id, int *done);
+
+/* One pass; *pending (may be NULL) = requests waiting or admitted and not
+ * finished. */
+int pc2_serve_progress(pc2_server *srv, size_t *pending);
+
+/* Drain up to cap ids of finished requests, in the order they finished
+ * (requests already reported by pc2_serve_poll are skipped); *n = how many.
+ * The ids are then forgotten.  Makes no pass. */
+int pc2_serve_completed(pc2_server *srv, uint64_t *ids, size_t cap, size_t *n);
+
+/* Launches so far, the largest and the current admitted bytes (any output
+ * may be NULL). */
+int pc2_server_stats(const pc2_server *srv, uint64_t *launches, size_t *max_bytes,
+                     size_t *used_bytes);
+
+/* Waits for the server's launches, then frees it.  Requests not finished are
+ * dropped. */
+int pc2_server_destroy(pc2_server *srv);
 
 /* ------------------------------------------------ ADMM update (FP64 kernels)
  *

@@ -36,6 +36,7 @@ UNITS = {
     "kernels_admm.hip": ["-ffp-contract=off"],
     "kernels_colsplit.hip": ["-ffp-contract=off"],
     "api.cpp": [],
+    "serve.cpp": [],
 }
 
 

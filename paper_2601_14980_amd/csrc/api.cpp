@@ -785,6 +785,13 @@ int pc2_pk_info(const pc2_pk* pk, uint32_t* nbits, uint32_t* limbs) {
   return PC2_OK;
 }
 
+int pc2_pk_context(const pc2_pk* pk, pc2_ctx** ctx, int* hip_device) {
+  if (!pk || !pk->ctx) return PC2_E_INVAL;
+  if (ctx) *ctx = pk->ctx;
+  if (hip_device) *hip_device = pk->ctx->device;
+  return PC2_OK;
+}
+
 // ---------------------------------------------------------------- data
 int pc2_quantize(pc2_ctx* ctx, const pc2_qparams* q, const double* x, uint64_t* m, size_t count,
                  void* stream) {

@@ -1,0 +1,367 @@
+// Request server for continuous batching (pc2_server_*, pc2_serve_*).
+//
+// Requests -- encryptions, aggregations and decryptions of vectors of any
+// length under one key -- arrive one at a time.  A request is admitted when
+// the bytes of its inputs and output fit in the server's HBM budget beside
+// the requests already admitted (first come, first served: a request that
+// does not fit holds back the ones behind it).  An admitted request is cut
+// into element groups (one wavefront's share each).  Each operation has its
+// own persistent launcher (pc2_runner) on its own stream; whenever that
+// stream is idle, the next scheduling pass forms one launch over up to
+// tick_groups groups drawn from every admitted request of the operation: an
+// equal slice each first, so a long request cannot hold back a short one
+// that arrived later, then what is left to the oldest.  Requests that arrive
+// while launches run join the next launch of their operation, and the three
+// operations overlap on the device.  A request is complete when the launch
+// holding its last group has finished.
+//
+// The server drives nothing by itself: every pc2_serve_* call makes one
+// scheduling pass (retire finished launches, admit, launch on idle streams),
+// so a caller that waits for results keeps calling pc2_serve_poll or
+// pc2_serve_progress.  It uses the public runner calls only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <deque>
+#include <memory>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pc2.h"
+
+namespace {
+
+constexpr int NOPS = 3;  // encrypt, hom_sum, decrypt
+constexpr uint32_t K_MAX = 128;
+
+int op_slot(int op) {
+  if (op == PC2_OP_ENCRYPT) return 0;
+  if (op == PC2_OP_HOM_SUM) return 1;
+  if (op == PC2_OP_DECRYPT) return 2;
+  return -1;
+}
+
+enum : int { WAITING = 0, ACTIVE = 1, DONE = 2 };
+
+struct Request {
+  uint64_t id = 0;
+  int slot = 0;
+  int state = WAITING;
+  pc2_job job{};
+  std::vector<const uint32_t*> inputs;  // hom_sum: the caller's pointer array, copied
+  std::vector<size_t> lengths;          // hom_sum: the caller's lengths, copied (may be empty)
+  size_t bytes = 0;                     // inputs + output, for admission
+  size_t groups = 0, next = 0, done = 0;
+};
+
+struct Piece {
+  Request* req;
+  size_t first, n;
+};
+
+}  // namespace
+
+struct pc2_server {
+  pc2_ctx* ctx = nullptr;
+  int device = 0;
+  const pc2_sk* sk = nullptr;
+  const pc2_pk* pk = nullptr;
+  uint32_t L = 0;
+  size_t budget = 0, used = 0, max_used = 0;
+  size_t tick_groups = 0, max_requests = 0;
+  uint32_t group_elems[NOPS] = {};
+  pc2_runner* runner[NOPS] = {};
+  hipStream_t stream[NOPS] = {};
+  hipEvent_t finished[NOPS] = {};
+  bool busy[NOPS] = {};
+  std::vector<Piece> tick[NOPS];
+  std::deque<Request*> waiting;
+  std::deque<Request*> active[NOPS];
+  std::vector<uint64_t> completed;  // finished ids not yet drained by pc2_serve_completed
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+  uint64_t next_id = 1;
+  uint64_t launches = 0;
+  // per-launch argument arrays, reused
+  std::vector<pc2_job> jobs;
+  std::vector<size_t> first, ngroups;
+};
+
+namespace {
+
+size_t request_bytes(const pc2_server* s, const pc2_job& j) {
+  const size_t L = s->L, n = j.count;
+  if (j.op == PC2_OP_ENCRYPT) return n * (4 * (size_t)j.m_limbs + 4 * L + 8 * L);
+  if (j.op == PC2_OP_HOM_SUM) return n * 8 * L * ((size_t)j.K + 1);
+  return n * (8 * L + 4 * L);
+}
+
+void finish(pc2_server* s, Request* r) {
+  r->state = DONE;
+  s->used -= r->bytes;
+  // ids that pc2_serve_poll already reported are dropped here, so the list
+  // holds at most about twice the tracked requests
+  if (s->completed.size() >= 2 * s->max_requests) {
+    auto& c = s->completed;
+    c.erase(std::remove_if(c.begin(), c.end(),
+                           [s](uint64_t id) { return !s->requests.count(id); }),
+            c.end());
+  }
+  s->completed.push_back(r->id);
+}
+
+// The launch of operation `op` finished: count its groups against their requests.
+void retire(pc2_server* s, int op) {
+  for (const Piece& p : s->tick[op]) {
+    Request* r = p.req;
+    r->done += p.n;
+    if (r->done == r->groups) {
+      auto& q = s->active[op];
+      q.erase(std::find(q.begin(), q.end(), r));
+      finish(s, r);
+    }
+  }
+  s->tick[op].clear();
+  s->busy[op] = false;
+}
+
+void admit(pc2_server* s) {
+  while (!s->waiting.empty() && s->used + s->waiting.front()->bytes <= s->budget) {
+    Request* r = s->waiting.front();
+    s->waiting.pop_front();
+    const size_t g = s->group_elems[r->slot];
+    r->groups = (r->job.count + g - 1) / g;
+    r->state = ACTIVE;
+    s->used += r->bytes;
+    s->max_used = std::max(s->max_used, s->used);
+    s->active[r->slot].push_back(r);
+  }
+}
+
+// One launch of operation `op` over the admitted requests' next groups.
+int launch(pc2_server* s, int op) {
+  std::vector<Request*> reqs;
+  for (Request* r : s->active[op])
+    if (r->next < r->groups) reqs.push_back(r);
+  if (reqs.empty()) return PC2_OK;
+  size_t room = s->tick_groups;
+  std::vector<size_t> take(reqs.size(), 0);
+  const size_t share = std::max<size_t>(1, room / reqs.size());
+  for (size_t i = 0; i < reqs.size() && room; ++i) {
+    take[i] = std::min({share, reqs[i]->groups - reqs[i]->next, room});
+    room -= take[i];
+  }
+  for (size_t i = 0; i < reqs.size() && room; ++i) {
+    const size_t t = std::min(reqs[i]->groups - reqs[i]->next - take[i], room);
+    take[i] += t;
+    room -= t;
+  }
+  s->jobs.clear();
+  s->first.clear();
+  s->ngroups.clear();
+  auto& tick = s->tick[op];
+  tick.clear();
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    if (!take[i]) continue;
+    Request* r = reqs[i];
+    s->jobs.push_back(r->job);
+    s->first.push_back(r->next);
+    s->ngroups.push_back(take[i]);
+    tick.push_back({r, r->next, take[i]});
+  }
+  int rc = pc2_runner_launch(s->runner[op], s->jobs.data(), s->first.data(), s->ngroups.data(),
+                             s->jobs.size(), s->stream[op]);
+  if (rc) {
+    tick.clear();
+    return rc;
+  }
+  if (hipEventRecord(s->finished[op], s->stream[op]) != hipSuccess) return PC2_E_DEVICE;
+  for (const Piece& p : tick) p.req->next += p.n;
+  s->busy[op] = true;
+  ++s->launches;
+  return PC2_OK;
+}
+
+// One scheduling pass: retire finished launches, admit, launch where idle.
+int pass(pc2_server* s) {
+  if (hipSetDevice(s->device) != hipSuccess) return PC2_E_DEVICE;
+  for (int op = 0; op < NOPS; ++op) {
+    if (!s->busy[op]) continue;
+    const hipError_t q = hipEventQuery(s->finished[op]);
+    if (q == hipSuccess) retire(s, op);
+    else if (q != hipErrorNotReady) return PC2_E_DEVICE;
+  }
+  admit(s);
+  for (int op = 0; op < NOPS; ++op) {
+    if (s->busy[op]) continue;
+    const int rc = launch(s, op);
+    if (rc) return rc;
+  }
+  return PC2_OK;
+}
+
+// The op and the key always; the arrays only when there is work (count > 0).
+int check_job(const pc2_server* s, const pc2_job& j) {
+  const int slot = op_slot(j.op);
+  if (slot < 0) return PC2_E_INVAL;
+  if (slot == 2 ? j.sk != s->sk : j.pk != s->pk) return PC2_E_INVAL;
+  if (j.count == 0) return PC2_OK;
+  if (!j.out || (slot == 2 && !j.in0)) return PC2_E_INVAL;
+  if (slot == 0 && (!j.in0 || !j.in1 || j.m_limbs < 1 || j.m_limbs > s->L)) return PC2_E_INVAL;
+  if (slot == 1) {
+    if (!j.inputs || j.K < 1 || j.K > K_MAX) return PC2_E_INVAL;
+    for (uint32_t k = 0; k < j.K; ++k)
+      if (!j.inputs[k] || (j.lengths && j.lengths[k] > j.count)) return PC2_E_INVAL;
+  }
+  return PC2_OK;
+}
+
+void destroy(pc2_server* s) {
+  (void)hipSetDevice(s->device);
+  for (int op = 0; op < NOPS; ++op) {
+    if (s->stream[op]) (void)hipStreamSynchronize(s->stream[op]);
+    if (s->runner[op]) (void)pc2_runner_destroy(s->runner[op]);
+    if (s->finished[op]) (void)hipEventDestroy(s->finished[op]);
+    if (s->stream[op]) (void)hipStreamDestroy(s->stream[op]);
+  }
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pc2_server_create(pc2_ctx* ctx, const pc2_sk* sk, size_t hbm_budget, size_t tick_groups,
+                      size_t max_requests, pc2_server** out) {
+  if (!ctx || !sk || !out || tick_groups == 0 || max_requests == 0) return PC2_E_INVAL;
+  *out = nullptr;
+  const pc2_pk* pk = pc2_sk_public(sk);
+  uint32_t nbits = 0, limbs = 0;
+  pc2_ctx* key_ctx = nullptr;
+  int device = 0;
+  if (!pk || pc2_pk_info(pk, &nbits, &limbs) != PC2_OK ||
+      pc2_pk_context(pk, &key_ctx, &device) != PC2_OK || key_ctx != ctx)
+    return PC2_E_INVAL;
+  if (hipSetDevice(device) != hipSuccess) return PC2_E_DEVICE;
+  if (hbm_budget == 0) {  // half of the device memory free now
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return PC2_E_DEVICE;
+    hbm_budget = free_b / 2;
+  }
+  pc2_server* s = new (std::nothrow) pc2_server();
+  if (!s) return PC2_E_NOMEM;
+  s->ctx = ctx;
+  s->device = device;
+  s->sk = sk;
+  s->pk = pk;
+  s->L = limbs;
+  s->budget = hbm_budget;
+  s->tick_groups = tick_groups;
+  s->max_requests = max_requests;
+  static const int ops[NOPS] = {PC2_OP_ENCRYPT, PC2_OP_HOM_SUM, PC2_OP_DECRYPT};
+  int rc = PC2_OK;
+  for (int op = 0; op < NOPS && !rc; ++op) {
+    rc = pc2_runner_group_size(pk, ops[op], &s->group_elems[op]);
+    if (!rc && s->group_elems[op] == 0) rc = PC2_E_UNSUPPORTED;
+    if (!rc) rc = pc2_runner_create(ctx, ops[op], nbits, max_requests, tick_groups, &s->runner[op]);
+    if (!rc && (hipStreamCreateWithFlags(&s->stream[op], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s->finished[op], hipEventDisableTiming) != hipSuccess))
+      rc = PC2_E_DEVICE;
+  }
+  if (rc) {
+    destroy(s);
+    return rc;
+  }
+  s->jobs.reserve(max_requests);
+  s->first.reserve(max_requests);
+  s->ngroups.reserve(max_requests);
+  *out = s;
+  return PC2_OK;
+}
+
+int pc2_serve_submit(pc2_server* s, const pc2_job* job, uint64_t* req_id) {
+  if (!s || !job || !req_id) return PC2_E_INVAL;
+  int rc = check_job(s, *job);
+  if (rc) return rc;
+  if (s->requests.size() >= s->max_requests) return PC2_E_BUSY;
+  auto r = std::unique_ptr<Request>(new (std::nothrow) Request());
+  if (!r) return PC2_E_NOMEM;
+  r->id = s->next_id++;
+  r->slot = op_slot(job->op);
+  r->job = *job;
+  if (job->op == PC2_OP_HOM_SUM && job->count > 0) {
+    r->inputs.assign(job->inputs, job->inputs + job->K);
+    r->job.inputs = r->inputs.data();
+    if (job->lengths) {
+      r->lengths.assign(job->lengths, job->lengths + job->K);
+      r->job.lengths = r->lengths.data();
+    }
+  }
+  r->bytes = request_bytes(s, r->job);
+  if (r->bytes > s->budget) return PC2_E_NOMEM;  // could never be admitted
+  Request* raw = r.get();
+  s->requests.emplace(raw->id, std::move(r));
+  *req_id = raw->id;
+  if (raw->job.count == 0) {  // nothing to compute
+    raw->state = ACTIVE;
+    s->used += raw->bytes;
+    finish(s, raw);
+    return PC2_OK;
+  }
+  s->waiting.push_back(raw);
+  return pass(s);
+}
+
+int pc2_serve_poll(pc2_server* s, uint64_t req_id, int* done) {
+  if (!s || !done) return PC2_E_INVAL;
+  auto it = s->requests.find(req_id);
+  if (it == s->requests.end()) return PC2_E_INVAL;
+  const int rc = pass(s);
+  if (rc) return rc;
+  *done = it->second->state == DONE;
+  if (*done) s->requests.erase(it);
+  return PC2_OK;
+}
+
+int pc2_serve_progress(pc2_server* s, size_t* pending) {
+  if (!s) return PC2_E_INVAL;
+  const int rc = pass(s);
+  if (rc) return rc;
+  if (pending) {
+    size_t n = s->waiting.size();
+    for (int op = 0; op < NOPS; ++op) n += s->active[op].size();
+    *pending = n;
+  }
+  return PC2_OK;
+}
+
+int pc2_serve_completed(pc2_server* s, uint64_t* ids, size_t cap, size_t* n) {
+  if (!s || !n || (cap && !ids)) return PC2_E_INVAL;
+  size_t i = 0, k = 0;
+  for (; i < s->completed.size() && k < cap; ++i) {
+    auto it = s->requests.find(s->completed[i]);
+    if (it == s->requests.end()) continue;  // already reported by pc2_serve_poll
+    ids[k++] = s->completed[i];
+    s->requests.erase(it);
+  }
+  s->completed.erase(s->completed.begin(), s->completed.begin() + i);
+  *n = k;
+  return PC2_OK;
+}
+
+int pc2_server_stats(const pc2_server* s, uint64_t* launches, size_t* max_bytes,
+                     size_t* used_bytes) {
+  if (!s) return PC2_E_INVAL;
+  if (launches) *launches = s->launches;
+  if (max_bytes) *max_bytes = s->max_used;
+  if (used_bytes) *used_bytes = s->used;
+  return PC2_OK;
+}
+
+int pc2_server_destroy(pc2_server* s) {
+  if (!s) return PC2_E_INVAL;
+  destroy(s);
+  return PC2_OK;
+}
+
+}  // extern "C"

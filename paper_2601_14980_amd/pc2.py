@@ -51,6 +51,8 @@ EXPORTS = [
     "pc2_matvec_destroy", "pc2_colsplit_create", "pc2_colsplit_iterate", "pc2_colsplit_destroy",
     "pc2_batch_create", "pc2_batch_run", "pc2_batch_destroy", "pc2_autotune",
     "pc2_runner_create", "pc2_runner_group_size", "pc2_runner_launch", "pc2_runner_destroy",
+    "pc2_pk_context", "pc2_server_create", "pc2_serve_submit", "pc2_serve_poll",
+    "pc2_serve_progress", "pc2_serve_completed", "pc2_server_stats", "pc2_server_destroy",
     "pc2_admm_create", "pc2_admm_local", "pc2_admm_consensus", "pc2_admm_destroy",
 ]
 
@@ -93,6 +95,7 @@ def _load() -> ctypes.CDLL:
         "pc2_pk_destroy": (c_int, [P]),
         "pc2_sk_destroy": (c_int, [P]),
         "pc2_pk_info": (c_int, [P, POINTER(c_uint32), POINTER(c_uint32)]),
+        "pc2_pk_context": (c_int, [P, POINTER(P), POINTER(c_int)]),
         "pc2_quantize": (c_int, [P, POINTER(pc2_qparams), P, P, c_size_t, P]),
         "pc2_dequantize": (c_int, [P, POINTER(pc2_qparams), P, c_uint32, c_uint64, P,
                                    c_size_t, P]),
@@ -122,6 +125,13 @@ def _load() -> ctypes.CDLL:
         "pc2_runner_launch": (c_int, [P, POINTER(pc2_job), POINTER(c_size_t), POINTER(c_size_t),
                                       c_size_t, P]),
         "pc2_runner_destroy": (c_int, [P]),
+        "pc2_server_create": (c_int, [P, P, c_size_t, c_size_t, c_size_t, POINTER(P)]),
+        "pc2_serve_submit": (c_int, [P, POINTER(pc2_job), POINTER(c_uint64)]),
+        "pc2_serve_poll": (c_int, [P, c_uint64, POINTER(c_int)]),
+        "pc2_serve_progress": (c_int, [P, POINTER(c_size_t)]),
+        "pc2_serve_completed": (c_int, [P, POINTER(c_uint64), c_size_t, POINTER(c_size_t)]),
+        "pc2_server_stats": (c_int, [P, POINTER(c_uint64), POINTER(c_size_t), POINTER(c_size_t)]),
+        "pc2_server_destroy": (c_int, [P]),
         "pc2_admm_create": (c_int, [P, P, P, c_uint32, c_uint32, c_uint32, c_double, P,
                                     POINTER(P)]),
         "pc2_admm_local": (c_int, [P, P, P, P, P, P]),
@@ -516,6 +526,71 @@ class Runner:
         if self.handle:
             lib.pc2_runner_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server for continuous batching under one key (pc2_server).
+
+    submit() takes a job dict as for Batch (op, pk / sk, m, r, c, inputs,
+    lengths, out); its tensors are held here until the request is reported
+    done by poll() or completed()."""
+
+    def __init__(self, ctx: Context, sk: SecretKey, hbm_budget: int = 0,
+                 tick_groups: int = 2048, max_requests: int = 1024):
+        h = c_void_p()
+        _check(lib.pc2_server_create(ctx.handle, sk.handle, hbm_budget, tick_groups,
+                                     max_requests, byref(h)), "pc2_server_create")
+        self.handle = h
+        self.ctx = ctx
+        self._held: dict[int, tuple] = {}
+        self._ids = (c_uint64 * max_requests)()
+
+    def submit(self, job: dict) -> int:
+        keep: list = []
+        arr = _make_jobs([job], keep)
+        rid = c_uint64()
+        _check(lib.pc2_serve_submit(self.handle, arr, byref(rid)), "pc2_serve_submit")
+        self._held[rid.value] = (job, keep)
+        return rid.value
+
+    def poll(self, rid: int) -> bool:
+        done = c_int()
+        _check(lib.pc2_serve_poll(self.handle, rid, byref(done)), "pc2_serve_poll")
+        if done.value:
+            self._held.pop(rid, None)
+        return bool(done.value)
+
+    def progress(self) -> int:
+        pending = c_size_t()
+        _check(lib.pc2_serve_progress(self.handle, byref(pending)), "pc2_serve_progress")
+        return pending.value
+
+    def completed(self) -> list[int]:
+        n = c_size_t()
+        _check(lib.pc2_serve_completed(self.handle, self._ids, len(self._ids), byref(n)),
+               "pc2_serve_completed")
+        ids = list(self._ids[:n.value])
+        for rid in ids:
+            self._held.pop(rid, None)
+        return ids
+
+    def stats(self) -> dict:
+        launches, mx, used = c_uint64(), c_size_t(), c_size_t()
+        _check(lib.pc2_server_stats(self.handle, byref(launches), byref(mx), byref(used)),
+               "pc2_server_stats")
+        return dict(launches=launches.value, max_bytes=mx.value, used_bytes=used.value)
+
+    def close(self) -> None:
+        if self.handle:
+            lib.pc2_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
 
     def __del__(self):
         try:

@@ -11,10 +11,13 @@ run join the next launch, long requests do not block short ones, and the
 three operations run concurrently on three streams.  A request completes when its last group has finished;
 its latency is completion time minus arrival time.
 
-The scheduling logic is independent of the device: `Scheduler` drives an
-executor with five methods (`bytes_for`, `admit`, `group_size`, `launch`,
-`poll`, `release`), so it is tested on the CPU with a simulated executor and
-runs on the GPU with `GpuExecutor`.
+On the device these rules run natively: libpc2's request server
+(pc2_server_*, pc2_serve_*) implements the same admission and launch
+formation in C++ over its persistent runners, and `serve_trace` feeds it a
+timed trace.  `Scheduler` states the same rules over an abstract executor
+with six methods (`bytes_for`, `admit`, `group_size`, `launch`, `poll`,
+`release`), so that they can be exercised on the CPU with a simulated
+executor.
 """
 from __future__ import annotations
 
@@ -182,77 +185,30 @@ def percentile(values: list[float], q: float) -> float:
     return v[k]
 
 
-# ------------------------------------------------------------ GPU executor
-class GpuExecutor:
-    """Runs scheduler ticks with pc2_runner_launch on one stream per op.
-
-    Request payloads (device tensors, int32 limb rows):
-      encrypt:   {"m": [L, m_limbs], "r": [L, Lk]}        -> result [L, 2Lk]
-      aggregate: {"inputs": [K tensors [>= L, 2Lk]]}      -> result [L, 2Lk]
-      decrypt:   {"c": [L, 2Lk]}                          -> result [L, Lk]
-    """
-
-    def __init__(self, ctx, sk, max_groups: int = 1 << 15, max_jobs: int = 512):
-        import torch
-
-        from . import pc2
-        self.pc2, self.torch = pc2, torch
-        self.ctx, self.sk = ctx, sk
-        self.L = sk.L
-        self.streams = {op: torch.cuda.Stream() for op in OPS}
-        codes = {"encrypt": pc2.PC2_OP_ENCRYPT, "aggregate": pc2.PC2_OP_HOM_SUM,
-                 "decrypt": pc2.PC2_OP_DECRYPT}
-        self.codes = codes
-        self.runners = {op: pc2.Runner(ctx, codes[op], sk.nbits, max_jobs, max_groups)
-                        for op in OPS}
-        self.gsize = {op: pc2.runner_group_size(sk.public, codes[op]) for op in OPS}
-
-    def group_size(self, req: Request) -> int:
-        return self.gsize[req.op]
-
-    def bytes_for(self, req: Request) -> int:
-        L, Lk = req.length, self.L
-        if req.op == "encrypt":
-            return L * (8 + 4 * Lk + 8 * Lk)
-        if req.op == "aggregate":
-            return L * 8 * Lk * (req.K + 1)
-        return L * (8 * Lk + 4 * Lk)
-
-    def admit(self, req: Request) -> None:
-        torch = self.torch
-        L, Lk = req.length, self.L
-        width = Lk if req.op == "decrypt" else 2 * Lk
-        req.result = torch.empty((L, width), dtype=torch.int32, device="cuda")
-
-    def _job(self, req: Request):
-        pc2 = self.pc2
-        p = req.payload
-        if req.op == "encrypt":
-            return dict(op=pc2.PC2_OP_ENCRYPT, pk=self.sk.public, m=p["m"], r=p["r"],
-                        out=req.result)
-        if req.op == "aggregate":
-            return dict(op=pc2.PC2_OP_HOM_SUM, pk=self.sk.public, inputs=p["inputs"],
-                        lengths=None, out=req.result)
-        return dict(op=pc2.PC2_OP_DECRYPT, sk=self.sk, c=p["c"], out=req.result)
-
-    def launch(self, op: str, pieces: list):
-        torch = self.torch
-        st = self.streams[op]
-        jobs = [self._job(req) for req, _, _ in pieces]
-        first = [f for _, f, _ in pieces]
-        ngroups = [n for _, _, n in pieces]
-        with torch.cuda.stream(st):
-            self.runners[op].launch(jobs, first, ngroups)
-            ev = torch.cuda.Event()
-            ev.record(st)
-        return ev
-
-    def poll(self, handle) -> bool:
-        return handle.query()
-
-    def release(self, req: Request) -> None:
-        pass  # results stay with the request; inputs belong to the caller
-
-    def close(self) -> None:
-        for r in self.runners.values():
-            r.close()
+# ------------------------------------------------------ native server driver
+def serve_trace(server, requests: list[Request], clock: Callable[[], float] = time.perf_counter,
+                t0: Optional[float] = None) -> float:
+    """Feed requests to a libpc2 request server (pc2.Server) at their arrival
+    times (seconds after t0, default now; they become absolute) and record
+    when each is seen complete.  Each request's payload is its pc2 job dict
+    (op, key, device inputs and output).  Returns the makespan in seconds."""
+    start = clock() if t0 is None else t0
+    for r in requests:
+        r.arrival += start
+    order = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    live: dict[int, Request] = {}
+    i = 0
+    while i < len(order) or live:
+        now = clock()
+        while i < len(order) and order[i].arrival <= now:
+            r = order[i]
+            live[server.submit(r.payload)] = r
+            r.admitted = now
+            i += 1
+        server.progress()
+        ids = server.completed()
+        if ids:
+            now = clock()
+            for rid in ids:
+                live.pop(rid).completed = now
+    return clock() - start

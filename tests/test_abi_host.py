@@ -66,7 +66,19 @@ def test_null_arguments_rejected(pc2):
     assert lib.pc2_pk_destroy(None) == INVAL
     assert lib.pc2_sk_destroy(None) == INVAL
     assert lib.pc2_pk_info(None, None, None) == INVAL
+    assert lib.pc2_pk_context(None, None, None) == INVAL
     assert lib.pc2_sk_public(None) is None
+    h = ctypes.c_void_p()
+    assert lib.pc2_server_create(None, None, 0, 8, 8, ctypes.byref(h)) == INVAL
+    rid = ctypes.c_uint64()
+    done = ctypes.c_int()
+    n = ctypes.c_size_t()
+    assert lib.pc2_serve_submit(None, None, ctypes.byref(rid)) == INVAL
+    assert lib.pc2_serve_poll(None, 1, ctypes.byref(done)) == INVAL
+    assert lib.pc2_serve_progress(None, None) == INVAL
+    assert lib.pc2_serve_completed(None, None, 0, ctypes.byref(n)) == INVAL
+    assert lib.pc2_server_stats(None, None, None, None) == INVAL
+    assert lib.pc2_server_destroy(None) == INVAL
 
 
 def test_context_without_gpu(pc2):

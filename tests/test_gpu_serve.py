@@ -1,7 +1,8 @@
-"""Serving loop on the GPU: requests of mixed type and length run through the
-continuous-batching scheduler (persistent runner launches on three streams)
+"""Request server on the GPU (pc2_server_*, pc2_serve_*): requests of mixed
+type and length arrive over time, run through continuous batching
+(persistent runner launches on three streams, admission by an HBM budget),
 and each result must equal, bit for bit, the same request run alone through
-the one-call entry points, and sampled elements must equal the oracle."""
+the one-call entry points; sampled elements must equal the oracle."""
 from __future__ import annotations
 
 import random
@@ -18,77 +19,161 @@ pytestmark = pytest.mark.gpu
 NBITS = 1024
 
 
-def test_mixed_requests_equal_alone(gpu_ctx):
+@pytest.fixture(scope="module")
+def keyset(gpu_ctx):
     from paper_2601_14980_amd import pc2
-    from paper_2601_14980_amd.serve import GpuExecutor, Request, Scheduler, percentile
-
     p, q = gen.primes_for(5, NBITS)
     n = p * q
     opk, osk = O.derive_keys(p, q)
     sk = pc2.SecretKey(gpu_ctx, NBITS, p, q)
-    L = sk.L
     rng = random.Random(9)
-    # resident ciphertext pool for aggregate / decrypt requests
     POOL, PLEN = 6, 700
     pool_m = [[rng.getrandbits(30) for _ in range(PLEN)] for _ in range(POOL)]
     pool_c = []
     for k in range(POOL):
-        c = torch.zeros((PLEN, 2 * L), dtype=torch.int32, device="cuda")
+        c = torch.zeros((PLEN, 2 * sk.L), dtype=torch.int32, device="cuda")
         pc2.pc2_encrypt(sk.public, pc2.to_device_limbs(to_limbs(pool_m[k], 2)),
-                        pc2.to_device_limbs(to_limbs(gen.gen_r(n, PLEN, 5, extra=k), L)), c)
+                        pc2.to_device_limbs(to_limbs(gen.gen_r(n, PLEN, 5, extra=k), sk.L)), c)
         pool_c.append(c)
     assert gpu_ctx.sync() == 0
+    return dict(sk=sk, n=n, opk=opk, osk=osk, pool_m=pool_m, pool_c=pool_c, PLEN=PLEN)
 
-    reqs = []
-    t = 0.0
-    for i in range(18):
+
+def _requests(pc2, ks, count, seed, rate):
+    from paper_2601_14980_amd.serve import Request
+    sk, n, L = ks["sk"], ks["n"], ks["sk"].L
+    rng = random.Random(seed)
+    reqs, t = [], 0.0
+    for i in range(count):
         op = ("encrypt", "aggregate", "decrypt")[i % 3]
-        length = rng.randint(20, PLEN)
-        t += rng.expovariate(4000.0)
+        length = rng.randint(20, ks["PLEN"])
+        t += rng.expovariate(rate)
         req = Request(rid=i, op=op, length=length, arrival=t)
         if op == "encrypt":
             ms = [rng.getrandbits(30) for _ in range(length)]
             rs = gen.gen_r(n, length, 6, extra=i)
-            req.payload = dict(m=pc2.to_device_limbs(to_limbs(ms, 2)),
-                               r=pc2.to_device_limbs(to_limbs(rs, L)), ms=ms, rs=rs)
+            out = torch.full((length, 2 * L), -1, dtype=torch.int32, device="cuda")
+            req.payload = dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public,
+                               m=pc2.to_device_limbs(to_limbs(ms, 2)),
+                               r=pc2.to_device_limbs(to_limbs(rs, L)), out=out)
+            req.result = dict(ms=ms, rs=rs)
         elif op == "aggregate":
             K = rng.randint(2, 5)
-            idx = rng.sample(range(POOL), K)
+            idx = rng.sample(range(len(ks["pool_c"])), K)
+            out = torch.full((length, 2 * L), -1, dtype=torch.int32, device="cuda")
             req.K = K
-            req.payload = dict(inputs=[pool_c[j] for j in idx], idx=idx)
+            req.payload = dict(op=pc2.PC2_OP_HOM_SUM, pk=sk.public,
+                               inputs=[ks["pool_c"][j] for j in idx], out=out)
+            req.result = dict(idx=idx)
         else:
-            j = rng.randrange(POOL)
-            req.payload = dict(c=pool_c[j][:length], idx=j)
+            j = rng.randrange(len(ks["pool_c"]))
+            out = torch.full((length, L), -1, dtype=torch.int32, device="cuda")
+            req.payload = dict(op=pc2.PC2_OP_DECRYPT, sk=sk, c=ks["pool_c"][j][:length], out=out)
+            req.result = dict(idx=j)
         reqs.append(req)
+    return reqs
 
-    ex = GpuExecutor(gpu_ctx, sk, max_groups=4096, max_jobs=64)
-    sch = Scheduler(ex, hbm_budget=1 << 30, tick_groups=24)
-    sch.run_trace(reqs)
+
+def _check_alone(pc2, gpu_ctx, ks, req):
+    job = req.payload
+    got = job["out"]
+    alone = torch.zeros_like(got)
+    if req.op == "encrypt":
+        pc2.pc2_encrypt(ks["sk"].public, job["m"], job["r"], alone)
+    elif req.op == "aggregate":
+        pc2.pc2_hom_sum(ks["sk"].public, [c[:req.length].contiguous() for c in job["inputs"]],
+                        alone)
+    else:
+        pc2.pc2_decrypt(ks["sk"], job["c"].contiguous(), alone)
+    assert gpu_ctx.sync() == 0
+    assert torch.equal(got, alone), f"request {req.rid} ({req.op}) differs from alone"
+    vals = ints_from_limbs(pc2.from_device_limbs(got))
+    j = req.length - 1
+    if req.op == "encrypt":
+        assert vals[j] == O.encrypt(ks["opk"], req.result["ms"][j], req.result["rs"][j])
+    elif req.op == "aggregate":
+        assert O.decrypt(ks["osk"], vals[j]) == sum(ks["pool_m"][k][j] for k in req.result["idx"])
+    else:
+        assert vals[j] == ks["pool_m"][req.result["idx"]][j]
+
+
+def test_mixed_requests_equal_alone(gpu_ctx, keyset):
+    from paper_2601_14980_amd import pc2
+    from paper_2601_14980_amd.serve import percentile, serve_trace
+    reqs = _requests(pc2, keyset, 18, 9, 4000.0)
+    budget = 2 << 20                    # holds a few requests at a time
+    srv = pc2.Server(gpu_ctx, keyset["sk"], hbm_budget=budget, tick_groups=24, max_requests=64)
+    serve_trace(srv, reqs)
     torch.cuda.synchronize()
     assert gpu_ctx.sync() == 0
-    assert len(sch.finished) == len(reqs)
-    assert sch.ticks > 3
+    st = srv.stats()
+    assert all(r.completed is not None for r in reqs)
+    assert st["launches"] > 3
+    assert 0 < st["max_bytes"] <= budget and st["used_bytes"] == 0
     lat = [r.latency for r in reqs]
     assert percentile(lat, 50) <= percentile(lat, 99)
-
     for req in reqs:
-        got = req.result
-        alone = torch.zeros_like(got)
-        if req.op == "encrypt":
-            pc2.pc2_encrypt(sk.public, req.payload["m"], req.payload["r"], alone)
-        elif req.op == "aggregate":
-            pc2.pc2_hom_sum(sk.public, [c[:req.length].contiguous()
-                                        for c in req.payload["inputs"]], alone)
-        else:
-            pc2.pc2_decrypt(sk, req.payload["c"].contiguous(), alone)
-        assert gpu_ctx.sync() == 0
-        assert torch.equal(got, alone), f"request {req.rid} ({req.op}) differs from alone"
-        vals = ints_from_limbs(pc2.from_device_limbs(got))
-        j = req.length - 1
-        if req.op == "encrypt":
-            assert vals[j] == O.encrypt(opk, req.payload["ms"][j], req.payload["rs"][j])
-        elif req.op == "aggregate":
-            assert O.decrypt(osk, vals[j]) == sum(pool_m[k][j] for k in req.payload["idx"])
-        else:
-            assert vals[j] == pool_m[req.payload["idx"]][j]
-    ex.close()
+        _check_alone(pc2, gpu_ctx, keyset, req)
+    srv.close()
+
+
+def test_poll_one_request_and_drain(gpu_ctx, keyset):
+    """poll() waits on one id; completed() drains the rest in finishing order,
+    skipping the ids poll already reported."""
+    from paper_2601_14980_amd import pc2
+    reqs = _requests(pc2, keyset, 9, 21, 1e9)
+    srv = pc2.Server(gpu_ctx, keyset["sk"], hbm_budget=1 << 30, tick_groups=4096,
+                     max_requests=16)
+    ids = [srv.submit(r.payload) for r in reqs]
+    while not srv.poll(ids[4]):
+        pass
+    seen = []
+    while len(seen) < len(ids) - 1:
+        srv.progress()
+        seen += srv.completed()
+    assert sorted(seen) == sorted(i for i in ids if i != ids[4])
+    assert srv.progress() == 0 and srv.completed() == []
+    assert gpu_ctx.sync() == 0
+    for req in reqs:
+        _check_alone(pc2, gpu_ctx, keyset, req)
+    srv.close()
+
+
+def test_server_argument_errors(gpu_ctx, keyset):
+    from paper_2601_14980_amd import pc2
+    sk = keyset["sk"]
+    L = sk.L
+    p2, q2 = gen.primes_for(6, NBITS)
+    other = pc2.SecretKey(gpu_ctx, NBITS, p2, q2)
+    srv = pc2.Server(gpu_ctx, sk, hbm_budget=1 << 20, tick_groups=8, max_requests=2)
+    m = torch.zeros((4, 2), dtype=torch.int32, device="cuda")
+    r = torch.ones((4, L), dtype=torch.int32, device="cuda")
+    out = torch.zeros((4, 2 * L), dtype=torch.int32, device="cuda")
+    with pytest.raises(pc2.PC2Error) as e:      # another key
+        srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=other.public, m=m, r=r, out=out))
+    assert e.value.status == pc2.PC2_E_INVAL
+    big = torch.zeros((4096, 2 * L), dtype=torch.int32, device="cuda")
+    with pytest.raises(pc2.PC2Error) as e:      # 4096 x 392 B > 1 MiB: never admissible
+        srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=big[:, :2].contiguous(),
+                        r=big[:, :L].contiguous(), out=big))
+    assert e.value.status == pc2.PC2_E_NOMEM
+    empty = torch.zeros((0, 2 * L), dtype=torch.int32, device="cuda")
+    z = srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m[:0], r=r[:0], out=empty))
+    assert srv.poll(z)                          # nothing to compute: done at once
+    with pytest.raises(pc2.PC2Error) as e:      # forgotten once reported
+        srv.poll(z)
+    assert e.value.status == pc2.PC2_E_INVAL
+    a = srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m, r=r, out=out))
+    out2 = torch.zeros_like(out)
+    b = srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m, r=r, out=out2))
+    with pytest.raises(pc2.PC2Error) as e:      # max_requests tracked
+        srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m, r=r,
+                        out=torch.zeros_like(out)))
+    assert e.value.status == pc2.PC2_E_BUSY
+    for rid in (a, b):
+        while not srv.poll(rid):
+            pass
+    assert gpu_ctx.sync() == 0
+    assert torch.equal(out, out2)
+    srv.close()
+    other.close()

@@ -18,7 +18,8 @@
  *             ([count][limbs]), owned and freed by the caller.  They are
  *             enqueued on the given HIP stream (NULL = the null stream) and
  *             return before the work finishes.  Outputs may alias an input
- *             of identical shape exactly; partial overlap is not allowed.
+ *             of identical size exactly (same address, same bytes); any
+ *             other overlap of an output with an input is PC2_E_INVAL.
  * Keys.       Key material is passed once, as HOST arrays, to the key
  *             constructors; the library derives and uploads every constant.
  *             g = n + 1 is implied (the paper admits any g in Z*_{n^2}).

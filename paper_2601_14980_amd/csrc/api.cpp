@@ -535,6 +535,14 @@ int prepare(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, pc2k::La
 int status_of(hipError_t e) { return e == hipSuccess ? PC2_OK : PC2_E_DEVICE; }
 
 
+
+// Two device arrays [a, a + na) and [b, b + nb) overlap without being the
+// same array of the same size (the only aliasing the data calls accept).
+bool partial_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  if (x + na <= y || y + nb <= x) return false;
+  return !(x == y && na == nb);
+}
 }  // namespace
 
 // ================================================================ ABI
@@ -798,6 +806,7 @@ int pc2_quantize(pc2_ctx* ctx, const pc2_qparams* q, const double* x, uint64_t* 
   if (!ctx || !q) return PC2_E_INVAL;
   if (count == 0) return PC2_OK;
   if (!x || !m) return PC2_E_INVAL;
+  if (partial_overlap(x, 8 * count, m, 8 * count)) return PC2_E_INVAL;
   if (q->log2_scale < -1074 || q->log2_scale > 1023) return PC2_E_INVAL;
   pc2k::Launch l{};
   l.grid = (int)std::min<size_t>((count + 255) / 256, (size_t)ctx->cus * 8);
@@ -811,6 +820,7 @@ int pc2_dequantize(pc2_ctx* ctx, const pc2_qparams* q, const uint32_t* m, uint32
   if (!ctx || !q) return PC2_E_INVAL;
   if (count == 0) return PC2_OK;
   if (!x || !m || m_limbs < 1 || m_limbs > 4096) return PC2_E_INVAL;
+  if (partial_overlap(m, 4 * (size_t)m_limbs * count, x, 8 * count)) return PC2_E_INVAL;
   if (q->log2_scale < -1074 || q->log2_scale > 1023) return PC2_E_INVAL;
   pc2k::Launch l{};
   l.grid = (int)std::min<size_t>((count + 255) / 256, (size_t)ctx->cus * 8);
@@ -825,6 +835,10 @@ int pc2_encrypt(const pc2_pk* pk, const uint32_t* m, uint32_t m_limbs, const uin
   if (!pk || !pk->ctx) return PC2_E_INVAL;
   if (count == 0) return PC2_OK;
   if (!m || !r || !c || m_limbs < 1 || (int)m_limbs > pk->L) return PC2_E_INVAL;
+  const size_t cb = 8 * (size_t)pk->L * count;
+  if (partial_overlap(c, cb, m, 4 * (size_t)m_limbs * count) ||
+      partial_overlap(c, cb, r, 4 * (size_t)pk->L * count))
+    return PC2_E_INVAL;
   pc2k::Launch l{};
   if (pk->ctx->modmul == PC2_MODMUL_MFMA) {
     int rc = prepare(pk->ctx, pk->cls, pc2k::OP_ENC_MFMA, count, 0, pk->L, &l, stream);
@@ -843,6 +857,8 @@ int pc2_decrypt(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count, 
   if (!sk || !sk->ctx) return PC2_E_INVAL;
   if (count == 0) return PC2_OK;
   if (!c || !m) return PC2_E_INVAL;
+  if (partial_overlap(c, 8 * (size_t)sk->pk.L * count, m, 4 * (size_t)sk->pk.L * count))
+    return PC2_E_INVAL;
   // the two CRT halves of up to DEC_CHUNK elements are staged between the
   // per-prime phase and the recombination
   const int Ls = sk->c.h[0].Ls;
@@ -866,6 +882,12 @@ int pc2_encrypt_sk(const pc2_sk* sk, const uint32_t* m, uint32_t m_limbs, const 
   if (!sk || !sk->ctx) return PC2_E_INVAL;
   if (count == 0) return PC2_OK;
   if (!m || !r || !c || m_limbs < 1 || (int)m_limbs > sk->pk.L) return PC2_E_INVAL;
+  {
+    const size_t cb = 8 * (size_t)sk->pk.L * count;
+    if (partial_overlap(c, cb, m, 4 * (size_t)m_limbs * count) ||
+        partial_overlap(c, cb, r, 4 * (size_t)sk->pk.L * count))
+      return PC2_E_INVAL;
+  }
   if (!sk->crt_ok) return PC2_E_UNSUPPORTED;
   // the two halves of up to DEC_CHUNK elements are staged before the recombination
   const int nl2 = sk->c.h[0].s2.nl, L = sk->pk.L, cls = sk->pk.cls;
@@ -889,8 +911,9 @@ int pc2_hom_sum(const pc2_pk* pk, const uint32_t* const* c_k, uint32_t K, uint32
   if (count == 0) return PC2_OK;
   if (!c_k || !out || K < 1 || K > (uint32_t)pc2k::RK_MAX) return PC2_E_INVAL;
   pc2k::PtrList lst{};
+  const size_t cb = 8 * (size_t)pk->L * count;
   for (uint32_t k = 0; k < K; ++k) {
-    if (!c_k[k]) return PC2_E_INVAL;
+    if (!c_k[k] || partial_overlap(out, cb, c_k[k], cb)) return PC2_E_INVAL;
     lst.p[k] = c_k[k];
   }
   pc2_ctx* ctx = pk->ctx;
@@ -918,6 +941,11 @@ int pc2_hom_scalar_mul(const pc2_pk* pk, const uint32_t* c, const uint64_t* k, u
   if (!pk || !pk->ctx) return PC2_E_INVAL;
   if (count == 0) return PC2_OK;
   if (!c || !k || !out) return PC2_E_INVAL;
+  {
+    const size_t cb = 8 * (size_t)pk->L * count;
+    if (partial_overlap(out, cb, c, cb) || partial_overlap(out, cb, k, 8 * count))
+      return PC2_E_INVAL;
+  }
   pc2k::Launch l{};
   int rc = prepare(pk->ctx, pk->cls, pc2k::OP_SMUL, count, 0, pk->L, &l, stream);
   if (rc) return rc;
@@ -935,6 +963,11 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
   pc2k::PtrList ms{}, rs{};
   for (uint32_t k = 0; k < K; ++k) {
     if (!m_k[k] || !r_k[k]) return PC2_E_INVAL;
+    if (partial_overlap(m_out, 4 * (size_t)sk->pk.L * count, m_k[k],
+                        4 * (size_t)m_limbs * count) ||
+        partial_overlap(m_out, 4 * (size_t)sk->pk.L * count, r_k[k],
+                        4 * (size_t)sk->pk.L * count))
+      return PC2_E_INVAL;
     ms.p[k] = m_k[k];
     rs.p[k] = r_k[k];
   }

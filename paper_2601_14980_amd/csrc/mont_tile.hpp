@@ -57,7 +57,9 @@ struct Geo {
 // Tiles are aligned groups of T lanes inside a DPP row of 16.  quad_perm
 // controls select a source lane inside each quad; row_shl:1 / row_shr:1 move
 // values one lane down / up inside the row (the tile-boundary lanes receive a
-// neighbour tile's value and are masked by the callers).
+// neighbour tile's value and are masked by the callers).  A lane whose source
+// is outside the row reads zero (bound control), which also lets the
+// compiler fold a move into the instruction that consumes it.
 enum : int {
   DPP_QUAD_0000 = 0x00,
   DPP_ROW_SHL1 = 0x101,
@@ -66,7 +68,7 @@ enum : int {
 };
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
@@ -164,13 +166,18 @@ __device__ __forceinline__ void mont_mul(uint32_t (&out)[G::K], const uint32_t (
   // the previous lane's top digit (in lane 0 they are zero by the choice of
   // m and leave the number) and its high part stays in this lane's digit 0,
   // so only 32 bits cross lanes.
+  // The digit mask sits in a register so that each lane move below fuses
+  // with its masking into one DPP-form v_and_b32 (a DPP operand pair takes
+  // no literal); the moves fill with zero where a source lane is absent.
+  uint32_t vmask = G::MASK;
+  asm volatile("" : "+v"(vmask));
   auto step = [&](uint32_t bi) {
     uint64_t x0 = mad64(a[0], bi, acc[0]);
-    uint32_t m = tile_bcast0<T>(((uint32_t)x0 * nprime) & G::MASK);
+    uint32_t m = tile_bcast0<T>((uint32_t)x0 * nprime) & vmask;
     x0 = mad64(m, N[0], x0);
 #pragma unroll
     for (int j = 1; j < K; ++j) acc[j - 1] = mad64(m, N[j], mad64(a[j], bi, acc[j]));
-    const uint32_t lo = tile_from_next32<T>((uint32_t)x0 & G::MASK);
+    const uint32_t lo = tile_from_next32<T>((uint32_t)x0) & vmask;
     acc[K - 1] = top ? 0ull : (uint64_t)lo;
     acc[0] += x0 >> D;
   };

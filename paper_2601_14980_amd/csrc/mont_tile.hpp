@@ -161,11 +161,13 @@ __device__ __forceinline__ void mont_mul(uint32_t (&out)[G::K], const uint32_t (
   uint64_t acc[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) acc[j] = 0;
-  const bool top = (tl == T - 1);
   // One step: the columns shift down one digit.  Digit 0's low D bits move to
-  // the previous lane's top digit (in lane 0 they are zero by the choice of
-  // m and leave the number) and its high part stays in this lane's digit 0,
-  // so only 32 bits cross lanes.
+  // the previous lane's top digit and its high part stays in this lane's
+  // digit 0, so only 32 bits cross lanes.  In lane 0 of every tile those low
+  // bits are zero by the choice of m (they leave the number), and that zero
+  // is what the top lane of the tile below reads, so the top digit needs no
+  // masking (every tile of a wavefront runs the same step on its own
+  // operands; the last lane of a row reads zero by bound control).
   // The digit mask sits in a register so that each lane move below fuses
   // with its masking into one DPP-form v_and_b32 (a DPP operand pair takes
   // no literal); the moves fill with zero where a source lane is absent.
@@ -177,8 +179,7 @@ __device__ __forceinline__ void mont_mul(uint32_t (&out)[G::K], const uint32_t (
     x0 = mad64(m, N[0], x0);
 #pragma unroll
     for (int j = 1; j < K; ++j) acc[j - 1] = mad64(m, N[j], mad64(a[j], bi, acc[j]));
-    const uint32_t lo = tile_from_next32<T>((uint32_t)x0) & vmask;
-    acc[K - 1] = top ? 0ull : (uint64_t)lo;
+    acc[K - 1] = (uint64_t)(tile_from_next32<T>((uint32_t)x0) & vmask);
     acc[0] += x0 >> D;
   };
   int i = 0;

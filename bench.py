@@ -687,8 +687,8 @@ def main() -> int:
                          "(reference for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the hot path on a single MI355X "
+              "and has no multi-GPU path; use --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -56,7 +56,7 @@ enum {
   PC2_E_RANGE = -2,       /* latched device data error (see Errors above) */
   PC2_E_NOMEM = -3,       /* device or host allocation failed */
   PC2_E_DEVICE = -4,      /* HIP runtime error or no usable device */
-  PC2_E_UNSUPPORTED = -5, /* key size or option this build does not support */
+  PC2_E_UNSUPPORTED = -5, /* key size or option the library does not support */
   PC2_E_BUSY = -6         /* resource limit reached (serving admission) */
 };
 

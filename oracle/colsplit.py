@@ -15,8 +15,8 @@ Enc(Gamma_1(B_k A_k^T y)) once and Enc(Gamma_2(z_k)), Enc(Gamma_2(-v_k)) every
 iteration; the node returns alpha_k (+) Gamma_2(rho B_k) (x) (z_k (+) -v_k)
 (eq. (itq2)); the master decrypts it and inverts the quantization.
 
-Quantizers (the affine, power-of-two reading of Sec. III-A used throughout
-this build, on the common interval [-8, 8)):
+Quantizers (the affine, power-of-two reading of Sec. III-A used throughout,
+on the common interval [-8, 8)):
 
     Gamma_2(u) = rint(u 2^k) + o,        o  = 2^(k+3)
     Gamma_1(u) = rint(u 2^(2k)) + o1,    o1 = 2^(2k+3)

@@ -27,7 +27,7 @@ passage of the paper it writes out:
                          pin that the split route reaches the plain result; the
                          parity tests compare against ``decrypt``.
 
-Choice of g: the paper allows any g in Z*_{n^2}; this build fixes g = n + 1, so
+Choice of g: the paper allows any g in Z*_{n^2}; this implementation fixes g = n + 1, so
 no g is ever passed around.
 """
 from __future__ import annotations

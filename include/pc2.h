@@ -365,8 +365,11 @@ int pc2_runner_destroy(pc2_runner *runner);
  * so a client waiting for results keeps calling pc2_serve_poll,
  * pc2_serve_progress or pc2_serve_completed.  A server is used from one host
  * thread at a time; data errors latch in the context as for every data call.
- * A status other than PC2_OK from a pass (PC2_E_DEVICE) leaves the server
- * unusable: destroy it. */
+ * Changing the key's encryption tile (PC2_OPT_TILE, pc2_autotune) while
+ * requests of an operation are admitted makes the next pass return
+ * PC2_E_UNSUPPORTED (their element groups were cut for the old tile) until
+ * the tile is restored; with none admitted the new tile is used.
+ * PC2_E_DEVICE from a pass leaves the server unusable: destroy it. */
 typedef struct pc2_server pc2_server;
 
 /* sk: the key every request uses (created in ctx).  hbm_budget: bytes of

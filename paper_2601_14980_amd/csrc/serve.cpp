@@ -182,6 +182,22 @@ int launch(pc2_server* s, int op) {
   return PC2_OK;
 }
 
+// Requests are cut into groups of the size the key's current encryption
+// tile gives; a tile change (PC2_OPT_TILE, pc2_autotune) while requests of an
+// operation are admitted would make the launcher read their group ranges in
+// other units, so it is refused; with none admitted the new size is taken.
+int refresh_group_sizes(pc2_server* s) {
+  static const int ops[NOPS] = {PC2_OP_ENCRYPT, PC2_OP_HOM_SUM, PC2_OP_DECRYPT};
+  for (int op = 0; op < NOPS; ++op) {
+    uint32_t g = 0;
+    if (pc2_runner_group_size(s->pk, ops[op], &g) != PC2_OK || g == 0) return PC2_E_UNSUPPORTED;
+    if (g == s->group_elems[op]) continue;
+    if (!s->active[op].empty()) return PC2_E_UNSUPPORTED;
+    s->group_elems[op] = g;
+  }
+  return PC2_OK;
+}
+
 // One scheduling pass: retire finished launches, admit, launch where idle.
 int pass(pc2_server* s) {
   if (hipSetDevice(s->device) != hipSuccess) return PC2_E_DEVICE;
@@ -191,10 +207,12 @@ int pass(pc2_server* s) {
     if (q == hipSuccess) retire(s, op);
     else if (q != hipErrorNotReady) return PC2_E_DEVICE;
   }
+  int rc = refresh_group_sizes(s);
+  if (rc) return rc;
   admit(s);
   for (int op = 0; op < NOPS; ++op) {
     if (s->busy[op]) continue;
-    const int rc = launch(s, op);
+    rc = launch(s, op);
     if (rc) return rc;
   }
   return PC2_OK;

@@ -177,3 +177,34 @@ def test_server_argument_errors(gpu_ctx, keyset):
     assert torch.equal(out, out2)
     srv.close()
     other.close()
+
+
+def test_tile_change_while_admitted_is_refused(gpu_ctx, keyset):
+    """Groups are cut for the key's tile at admission: changing the tile while
+    a request still has groups to launch is refused until it is restored."""
+    from paper_2601_14980_amd import pc2
+    sk, L, n = keyset["sk"], keyset["sk"].L, keyset["n"]
+    count = 200
+    rng = random.Random(33)
+    ms = [rng.getrandbits(30) for _ in range(count)]
+    m = pc2.to_device_limbs(to_limbs(ms, 2))
+    r = pc2.to_device_limbs(to_limbs(gen.gen_r(n, count, 8), L))
+    out = torch.full((count, 2 * L), -1, dtype=torch.int32, device="cuda")
+    srv = pc2.Server(gpu_ctx, sk, hbm_budget=1 << 30, tick_groups=2, max_requests=4)
+    rid = srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m, r=r, out=out))
+    other = 4 if pc2.runner_group_size(sk.public, pc2.PC2_OP_ENCRYPT) == 32 else 2
+    try:
+        gpu_ctx.set_option(pc2.PC2_OPT_TILE, other)  # 1024-bit keys: 2 or 4 lanes
+        with pytest.raises(pc2.PC2Error) as e:
+            srv.poll(rid)
+        assert e.value.status == pc2.PC2_E_UNSUPPORTED
+    finally:
+        gpu_ctx.set_option(pc2.PC2_OPT_TILE, 0)
+    while not srv.poll(rid):
+        pass
+    assert gpu_ctx.sync() == 0
+    alone = torch.zeros_like(out)
+    pc2.pc2_encrypt(sk.public, m, r, alone)
+    assert gpu_ctx.sync() == 0
+    assert torch.equal(out, alone)
+    srv.close()

@@ -7,7 +7,9 @@ checked through the exact identity Dec(prod_k Enc(m_k)) = sum_k m_k.
 * 16 nodes of log-uniform lengths in [1024, 65536] under alternating
   1024/2048-bit keys: one persistent batch launch per phase.
 * 3072-bit key, 32 x 16384 quantized values (one lasso iteration's
-  crypto): encryption of 524288, 32-way aggregation, decryption of 16384."""
+  crypto): encryption of 524288, 32-way aggregation, decryption of 16384.
+* The request server as the benchmark runs it (2048-bit key, launches of 2048
+  groups, 4 GiB budget) on requests of up to 65536 elements."""
 from __future__ import annotations
 
 import numpy as np
@@ -135,3 +137,69 @@ def test_full_size_batches(gpu_ctx):
         assert got == O.encrypt(nd["k"]["opk"], mv, r), f"node {i}, element {j}"
     for b in (enc, agg, dec):
         b.close()
+
+
+def test_full_size_serving(gpu_ctx):
+    """The request server in the benchmark's configuration (2048-bit key,
+    launches of 2048 groups, a 4 GiB budget) on requests of up to 65536
+    elements of each operation: every result equals the same request run
+    alone; sampled elements equal the oracle."""
+    from paper_2601_14980_amd import pc2
+    from paper_2601_14980_amd.serve import Request, serve_trace
+    seed, PL = 6, 65536
+    p, q = gen.primes_for(seed, 2048)
+    n = p * q
+    opk, osk = O.derive_keys(p, q)
+    sk = pc2.SecretKey(gpu_ctx, 2048, p, q)
+    L = sk.L
+    qp = gen.Q_PLAIN
+    m = torch.empty(PL, dtype=torch.int64, device="cuda")
+    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset,
+                     torch.from_numpy(gen.normal_vectors(seed, [PL])[0]).cuda(), m)
+    m2 = m.view(torch.int32).reshape(PL, 2)
+    rl = gen.gen_r_limbs(n, PL, L, seed)
+    r = pc2.to_device_limbs(rl)
+    pool = [torch.empty((PL, 2 * L), dtype=torch.int32, device="cuda") for _ in range(3)]
+    pc2.pc2_encrypt(sk.public, m2, r, pool[0])
+    for k in (1, 2):
+        pc2.pc2_hom_scalar_mul(sk.public, pool[0],
+                               torch.full((PL,), k + 1, dtype=torch.int64, device="cuda"), pool[k])
+    assert gpu_ctx.sync() == 0
+    specs = [("encrypt", PL), ("aggregate", PL), ("decrypt", PL),
+             ("encrypt", 300), ("aggregate", 4097), ("decrypt", 1000)]
+    reqs = []
+    for i, (op, ln) in enumerate(specs):
+        req = Request(rid=i, op=op, length=ln, arrival=0.002 * i)
+        width = L if op == "decrypt" else 2 * L
+        out = torch.full((ln, width), -1, dtype=torch.int32, device="cuda")
+        if op == "encrypt":
+            req.payload = dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m2[:ln], r=r[:ln], out=out)
+        elif op == "aggregate":
+            req.payload = dict(op=pc2.PC2_OP_HOM_SUM, pk=sk.public, inputs=pool, out=out)
+        else:
+            req.payload = dict(op=pc2.PC2_OP_DECRYPT, sk=sk, c=pool[1][:ln], out=out)
+        reqs.append(req)
+    srv = pc2.Server(gpu_ctx, sk, hbm_budget=4 << 30, tick_groups=2048, max_requests=64)
+    serve_trace(srv, reqs)
+    assert gpu_ctx.sync() == 0
+    srv.close()
+    mh = m.cpu().numpy().view(np.uint64)
+    for req in reqs:
+        job, ln = req.payload, req.length
+        alone = torch.empty_like(job["out"])
+        if req.op == "encrypt":
+            pc2.pc2_encrypt(sk.public, job["m"], job["r"], alone)
+        elif req.op == "aggregate":
+            pc2.pc2_hom_sum(sk.public, [c[:ln] for c in pool], alone)
+        else:
+            pc2.pc2_decrypt(sk, job["c"], alone)
+        assert gpu_ctx.sync() == 0
+        assert torch.equal(job["out"], alone), f"request {req.rid} ({req.op}, {ln})"
+        j = ln - 1
+        got = ints_from_limbs(pc2.from_device_limbs(job["out"][j:j + 1]))[0]
+        if req.op == "encrypt":
+            assert got == O.encrypt(opk, int(mh[j]), int(ints_from_limbs(rl[j:j + 1])[0]))
+        elif req.op == "aggregate":
+            assert O.decrypt(osk, got) == 6 * int(mh[j])   # (1 + 2 + 3) m_j
+        else:
+            assert got == 2 * int(mh[j])

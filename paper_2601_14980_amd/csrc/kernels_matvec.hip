@@ -135,9 +135,12 @@ __global__ __launch_bounds__(64, 2) void k_mv_apply(PkConst pk, const uint64_t* 
         const uint32_t d = (uint32_t)((e >> (w * t)) & dmask);
         if (__ballot(d != 0) == 0) continue;  // wave-uniform: no tile has work here
         const uint32_t* b = d ? tj + ((size_t)t * per + d - 1) * G::CH : pk.n2.R1;
+        // the running value goes to LDS and the table entry into its
+        // registers (one vector load per four digits, all in flight at once)
         lds_sync();
-        lds_from_chunk<G>(lds, b, tl);
+        to_lds<G>(lds, acc, tl);
         lds_sync();
+        load_chunk<G>(acc, b, tl);
         mont_mul<G>(acc, acc, lds, N, np, tl);
       }
     }

@@ -91,6 +91,17 @@ __device__ __forceinline__ uint32_t tile_bcast0(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)q, (int)q, DPP_ROW_SHR4, 0xF, 0xA, false);
   }
 }
+// tile_bcast0(v) & mask, written so that the mask fuses with the first lane
+// move (the bitwise and commutes with moving lanes)
+template <int T>
+__device__ __forceinline__ uint32_t tile_bcast0_masked(uint32_t v, uint32_t mask) {
+  if constexpr (T == 8) {
+    uint32_t q = dpp32<DPP_QUAD_0000>(v) & mask;
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)q, (int)q, DPP_ROW_SHR4, 0xF, 0xA, false);
+  } else {
+    return tile_bcast0<T>(v) & mask;
+  }
+}
 // value of tile lane t+1 (meaningless in the top lane of the tile)
 template <int T>
 __device__ __forceinline__ uint32_t tile_from_next32(uint32_t v) {
@@ -175,7 +186,7 @@ __device__ __forceinline__ void mont_mul(uint32_t (&out)[G::K], const uint32_t (
   asm volatile("" : "+v"(vmask));
   auto step = [&](uint32_t bi) {
     uint64_t x0 = mad64(a[0], bi, acc[0]);
-    uint32_t m = tile_bcast0<T>((uint32_t)x0 * nprime) & vmask;
+    uint32_t m = tile_bcast0_masked<T>((uint32_t)x0 * nprime, vmask);
     x0 = mad64(m, N[0], x0);
 #pragma unroll
     for (int j = 1; j < K; ++j) acc[j - 1] = mad64(m, N[j], mad64(a[j], bi, acc[j]));

@@ -266,6 +266,8 @@ def run_batching(pc2, gen, ctx, torch, np, args, reps: int = 3) -> dict:
 
 # -------------------------------------------------------- serving (config 5)
 SERVE_SEED = 5
+# requests admitted longer ago than this go first under the shortest-first policy
+SERVE_MAX_AGE = 1.0
 
 
 def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
@@ -333,9 +335,10 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
             pc2.pc2_decrypt(sk, job["c"], ref)
         return bool(torch.equal(ref, job["out"]))
 
-    def serve(reqs):
+    def serve(reqs, policy=pc2.PC2_SERVE_FAIR):
         srv = pc2.Server(ctx, sk, hbm_budget=budget, tick_groups=args.serve_tick_groups,
                          max_requests=1024)
+        srv.set_policy(policy, SERVE_MAX_AGE)
         span = serve_trace(srv, reqs)
         torch.cuda.synchronize()
         st = srv.stats()
@@ -354,18 +357,23 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
                     sampled_requests_equal_alone=all(alone_equal(r) for r in sample))
 
     n = args.serve_requests
-    hot = serve(make_trace(n, 2000.0, SERVE_SEED))
+    hot = serve(make_trace(n, 2000.0, SERVE_SEED), pc2.PC2_SERVE_SHORTEST)
     cap = hot["requests"] / hot["makespan_s"]
-    sub = serve(make_trace(n, 0.7 * cap, SERVE_SEED + 1))
+    sub = serve(make_trace(n, 0.7 * cap, SERVE_SEED + 1), pc2.PC2_SERVE_SHORTEST)
+    hot_f = serve(make_trace(n, 2000.0, SERVE_SEED), pc2.PC2_SERVE_FAIR)
+    sub_f = serve(make_trace(n, 0.7 * cap, SERVE_SEED + 1), pc2.PC2_SERVE_FAIR)
     if ctx.sync() != 0:
         raise RuntimeError("device reported a data error while serving")
-    log(f"serving: offered 2000 req/s -> p50 {hot['p50_ms']} ms p99 {hot['p99_ms']} ms; "
-        f"at 0.7x capacity ({0.7 * cap:.0f} req/s) p50 {sub['p50_ms']} ms p99 {sub['p99_ms']} ms")
+    for name, h, u in (("shortest first", hot, sub), ("fair share", hot_f, sub_f)):
+        log(f"serving ({name}): offered 2000 req/s -> p50 {h['p50_ms']} ms p99 {h['p99_ms']} ms; "
+            f"at 0.7x capacity ({0.7 * cap:.0f} req/s) p50 {u['p50_ms']} ms p99 {u['p99_ms']} ms")
     return {"workload": f"{n} requests per run, Poisson arrivals, encrypt/aggregate/decrypt 1/3 each, "
                         "lengths log-uniform [256, 65536], 2048-bit key, HBM budget 4 GiB, "
                         "libpc2 request server",
             "tick_groups": args.serve_tick_groups,
-            "configured_2000_req_s": hot, "sub_saturation_0p7_capacity": sub}
+            "policy": f"shortest remaining first, requests older than {SERVE_MAX_AGE} s first",
+            "configured_2000_req_s": hot, "sub_saturation_0p7_capacity": sub,
+            "fair_share": {"configured_2000_req_s": hot_f, "sub_saturation_0p7_capacity": sub_f}}
 
 
 # ------------------------------------------------------------- ADMM (config 4)

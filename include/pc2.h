@@ -354,11 +354,11 @@ int pc2_runner_destroy(pc2_runner *runner);
  * HBM budget beside those already admitted, first come, first served.  Each
  * operation has its own persistent launcher and stream; whenever a stream is
  * idle, the next scheduling pass launches up to tick_groups element groups
- * (pc2_runner_group_size elements each) drawn from every admitted request of
- * that operation -- an equal slice each, then the rest to the oldest -- so
- * requests that arrive while others run join the next launch and the three
- * operations overlap on the device.  Results are identical to the one-call
- * entry points.
+ * (pc2_runner_group_size elements each) drawn from the admitted requests of
+ * that operation in the order of the launch policy (pc2_server_set_policy),
+ * so requests that arrive while others run join the next launch and the
+ * three operations overlap on the device.  Results are identical to the
+ * one-call entry points.
  *
  * Every pc2_serve_* call makes one scheduling pass (retire finished
  * launches, admit, launch on idle streams); nothing advances between calls,
@@ -403,6 +403,17 @@ int pc2_serve_progress(pc2_server *srv, size_t *pending);
  * (requests already reported by pc2_serve_poll are skipped); *n = how many.
  * The ids are then forgotten.  Makes no pass. */
 int pc2_serve_completed(pc2_server *srv, uint64_t *ids, size_t cap, size_t *n);
+
+/* Launch policy.  PC2_SERVE_SHORTEST (the default, with max_age_s = 1):
+ * requests take the launch in increasing order of the groups they have left
+ * (shortest remaining first, the order that minimises mean latency), except
+ * that requests admitted more than max_age_s seconds ago go first, oldest
+ * first, which bounds how long a long request can be passed over.
+ * PC2_SERVE_FAIR: every admitted request of the operation gets an equal
+ * slice of the launch, what is left goes to the oldest.  Applies from the
+ * next launch. */
+enum { PC2_SERVE_FAIR = 0, PC2_SERVE_SHORTEST = 1 };
+int pc2_server_set_policy(pc2_server *srv, int policy, double max_age_s);
 
 /* Launches so far, the largest and the current admitted bytes (any output
  * may be NULL). */

@@ -8,9 +8,14 @@
 // into element groups (one wavefront's share each).  Each operation has its
 // own persistent launcher (pc2_runner) on its own stream; whenever that
 // stream is idle, the next scheduling pass forms one launch over up to
-// tick_groups groups drawn from every admitted request of the operation: an
-// equal slice each first, so a long request cannot hold back a short one
-// that arrived later, then what is left to the oldest.  Requests that arrive
+// tick_groups groups drawn from the admitted requests of the operation.
+// Two launch policies: shortest remaining first (the default: requests in
+// increasing order of the groups they have left, each taking all it can,
+// which minimises mean latency; a request admitted longer ago than a set age
+// goes first, oldest first, so that long requests are not starved) and fair
+// share (an equal slice each first, so a long request cannot hold back a
+// short one that arrived later, then what is left to the oldest).  Requests
+// that arrive
 // while launches run join the next launch of their operation, and the three
 // operations overlap on the device.  A request is complete when the launch
 // holding its last group has finished.
@@ -22,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <deque>
 #include <memory>
 #include <new>
@@ -53,7 +59,13 @@ struct Request {
   std::vector<size_t> lengths;          // hom_sum: the caller's lengths, copied (may be empty)
   size_t bytes = 0;                     // inputs + output, for admission
   size_t groups = 0, next = 0, done = 0;
+  double admitted = 0;                  // host clock, seconds
 };
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
 
 struct Piece {
   Request* req;
@@ -70,6 +82,8 @@ struct pc2_server {
   uint32_t L = 0;
   size_t budget = 0, used = 0, max_used = 0;
   size_t tick_groups = 0, max_requests = 0;
+  int policy = PC2_SERVE_SHORTEST;
+  double max_age = 1.0;  // seconds, shortest-first policy
   uint32_t group_elems[NOPS] = {};
   pc2_runner* runner[NOPS] = {};
   hipStream_t stream[NOPS] = {};
@@ -132,6 +146,7 @@ void admit(pc2_server* s) {
     const size_t g = s->group_elems[r->slot];
     r->groups = (r->job.count + g - 1) / g;
     r->state = ACTIVE;
+    r->admitted = now_s();
     s->used += r->bytes;
     s->max_used = std::max(s->max_used, s->used);
     s->active[r->slot].push_back(r);
@@ -146,10 +161,21 @@ int launch(pc2_server* s, int op) {
   if (reqs.empty()) return PC2_OK;
   size_t room = s->tick_groups;
   std::vector<size_t> take(reqs.size(), 0);
-  const size_t share = std::max<size_t>(1, room / reqs.size());
-  for (size_t i = 0; i < reqs.size() && room; ++i) {
-    take[i] = std::min({share, reqs[i]->groups - reqs[i]->next, room});
-    room -= take[i];
+  if (s->policy == PC2_SERVE_SHORTEST) {
+    // aged requests first (oldest first), then the rest by groups left
+    const double t = now_s();
+    std::stable_sort(reqs.begin(), reqs.end(), [&](const Request* a, const Request* b) {
+      const bool oa = t - a->admitted > s->max_age, ob = t - b->admitted > s->max_age;
+      if (oa != ob) return oa;
+      if (oa) return a->admitted < b->admitted;
+      return a->groups - a->next < b->groups - b->next;
+    });
+  } else {
+    const size_t share = std::max<size_t>(1, room / reqs.size());
+    for (size_t i = 0; i < reqs.size() && room; ++i) {
+      take[i] = std::min({share, reqs[i]->groups - reqs[i]->next, room});
+      room -= take[i];
+    }
   }
   for (size_t i = 0; i < reqs.size() && room; ++i) {
     const size_t t = std::min(reqs[i]->groups - reqs[i]->next - take[i], room);
@@ -364,6 +390,14 @@ int pc2_serve_completed(pc2_server* s, uint64_t* ids, size_t cap, size_t* n) {
   }
   s->completed.erase(s->completed.begin(), s->completed.begin() + i);
   *n = k;
+  return PC2_OK;
+}
+
+int pc2_server_set_policy(pc2_server* s, int policy, double max_age_s) {
+  if (!s || (policy != PC2_SERVE_FAIR && policy != PC2_SERVE_SHORTEST) || !(max_age_s >= 0))
+    return PC2_E_INVAL;
+  s->policy = policy;
+  s->max_age = max_age_s;
   return PC2_OK;
 }
 

@@ -39,6 +39,8 @@ PC2_MODMUL_MFMA = 1
 PC2_OP_ENCRYPT = 1
 PC2_OP_HOM_SUM = 2
 PC2_OP_DECRYPT = 3
+PC2_SERVE_FAIR = 0
+PC2_SERVE_SHORTEST = 1
 
 EXPORTS = [
     "pc2_ctx_create", "pc2_ctx_destroy", "pc2_ctx_sync", "pc2_ctx_take_error",
@@ -53,6 +55,7 @@ EXPORTS = [
     "pc2_runner_create", "pc2_runner_group_size", "pc2_runner_launch", "pc2_runner_destroy",
     "pc2_pk_context", "pc2_server_create", "pc2_serve_submit", "pc2_serve_poll",
     "pc2_serve_progress", "pc2_serve_completed", "pc2_server_stats", "pc2_server_destroy",
+    "pc2_server_set_policy",
     "pc2_admm_create", "pc2_admm_local", "pc2_admm_consensus", "pc2_admm_destroy",
 ]
 
@@ -131,6 +134,7 @@ def _load() -> ctypes.CDLL:
         "pc2_serve_progress": (c_int, [P, POINTER(c_size_t)]),
         "pc2_serve_completed": (c_int, [P, POINTER(c_uint64), c_size_t, POINTER(c_size_t)]),
         "pc2_server_stats": (c_int, [P, POINTER(c_uint64), POINTER(c_size_t), POINTER(c_size_t)]),
+        "pc2_server_set_policy": (c_int, [P, c_int, c_double]),
         "pc2_server_destroy": (c_int, [P]),
         "pc2_admm_create": (c_int, [P, P, P, c_uint32, c_uint32, c_uint32, c_double, P,
                                     POINTER(P)]),
@@ -579,6 +583,9 @@ class Server:
         for rid in ids:
             self._held.pop(rid, None)
         return ids
+
+    def set_policy(self, policy: int, max_age_s: float = 1.0) -> None:
+        _check(lib.pc2_server_set_policy(self.handle, policy, max_age_s), "pc2_server_set_policy")
 
     def stats(self) -> dict:
         launches, mx, used = c_uint64(), c_size_t(), c_size_t()

@@ -5,11 +5,13 @@ time.  A request is admitted when its device memory fits in the HBM budget
 (first come, first served); an admitted request is cut into element groups
 (one wavefront's share each).  Whenever the GPU stream of an operation is
 idle, the scheduler launches ONE persistent kernel over up to `tick_groups`
-groups shared among every admitted request of that operation (an equal
-slice each, leftovers to the oldest) -- so requests that arrive while others
-run join the next launch, long requests do not block short ones, and the
-three operations run concurrently on three streams.  A request completes when its last group has finished;
-its latency is completion time minus arrival time.
+groups drawn from the admitted requests of that operation -- shortest
+remaining first, except that requests admitted more than `max_age` seconds
+ago go first (or, with policy "fair", an equal slice each, leftovers to the
+oldest) -- so requests that arrive while others run join the next launch,
+long requests do not block short ones, and the three operations run
+concurrently on three streams.  A request completes when its last group has
+finished; its latency is completion time minus arrival time.
 
 On the device these rules run natively: libpc2's request server
 (pc2_server_*, pc2_serve_*) implements the same admission and launch
@@ -61,10 +63,20 @@ class Tick:
 
 
 class Scheduler:
+    """policy "shortest" (default): requests take a launch in increasing
+    order of the groups they have left, except that those admitted more than
+    max_age seconds ago go first, oldest first; "fair": each admitted request
+    of an operation gets an equal slice of a launch, leftovers to the oldest."""
+
     def __init__(self, executor, hbm_budget: int, tick_groups: int,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, policy: str = "shortest",
+                 max_age: float = 1.0):
         if hbm_budget <= 0 or tick_groups <= 0:
             raise ValueError("budget and tick size must be positive")
+        if policy not in ("fair", "shortest") or not max_age >= 0:
+            raise ValueError("policy is 'fair' or 'shortest', max_age >= 0")
+        self.policy = policy
+        self.max_age = max_age
         self.ex = executor
         self.budget = hbm_budget
         self.tick_groups = tick_groups
@@ -98,21 +110,28 @@ class Scheduler:
 
     # ------------------------------------------------------------- batching
     def _form_tick(self, op: str) -> list:
-        """Share the launch among all admitted requests of this op: each gets
-        an equal slice first (so a long request cannot starve a short one
-        that arrived later), then leftover room goes to the oldest."""
+        """Fair: share the launch among all admitted requests of this op, an
+        equal slice first (so a long request cannot starve a short one that
+        arrived later), then leftover room to the oldest.  Shortest: aged
+        requests (oldest first), then the rest by groups left, each taking
+        all it can."""
         reqs = [r for r in self.active[op] if r.next_group < r.groups]
         if not reqs:
             return []
         room = self.tick_groups
         take = {r.rid: 0 for r in reqs}
-        share = max(1, room // len(reqs))
-        for r in reqs:
-            if room == 0:
-                break
-            t = min(share, r.groups - r.next_group, room)
-            take[r.rid] = t
-            room -= t
+        if self.policy == "shortest":
+            now = self.clock()
+            aged = lambda r: now - r.admitted > self.max_age
+            reqs.sort(key=lambda r: (0, r.admitted) if aged(r) else (1, r.groups - r.next_group))
+        else:
+            share = max(1, room // len(reqs))
+            for r in reqs:
+                if room == 0:
+                    break
+                t = min(share, r.groups - r.next_group, room)
+                take[r.rid] = t
+                room -= t
         for r in reqs:
             if room == 0:
                 break

@@ -208,3 +208,27 @@ def test_tile_change_while_admitted_is_refused(gpu_ctx, keyset):
     assert gpu_ctx.sync() == 0
     assert torch.equal(out, alone)
     srv.close()
+
+
+@pytest.mark.parametrize("policy", ["shortest_aging", "fair"])
+def test_policies_equal_alone(gpu_ctx, keyset, policy):
+    """The default is shortest remaining first; here with an age limit short
+    enough that aged requests lead most launches, and the fair-share policy."""
+    from paper_2601_14980_amd import pc2
+    from paper_2601_14980_amd.serve import serve_trace
+    reqs = _requests(pc2, keyset, 15, 17, 4000.0)
+    srv = pc2.Server(gpu_ctx, keyset["sk"], hbm_budget=2 << 20, tick_groups=24, max_requests=64)
+    for bad in ((7, 1.0), (pc2.PC2_SERVE_SHORTEST, -1.0)):
+        with pytest.raises(pc2.PC2Error):
+            srv.set_policy(*bad)
+    if policy == "fair":
+        srv.set_policy(pc2.PC2_SERVE_FAIR, 1.0)
+    else:
+        srv.set_policy(pc2.PC2_SERVE_SHORTEST, 0.001)
+    serve_trace(srv, reqs)
+    torch.cuda.synchronize()
+    assert gpu_ctx.sync() == 0
+    assert all(r.completed is not None for r in reqs)
+    for req in reqs:
+        _check_alone(pc2, gpu_ctx, keyset, req)
+    srv.close()

@@ -58,10 +58,10 @@ class FakeExecutor:
         del self.live[req.rid]
 
 
-def run(requests, budget=10**9, tick=64, dt=1e-4):
+def run(requests, budget=10**9, tick=64, dt=1e-4, **kw):
     clock = Clock()
     ex = FakeExecutor(clock, budget)
-    sch = Scheduler(ex, budget, tick, clock=clock)
+    sch = Scheduler(ex, budget, tick, clock=clock, **kw)
 
     def idle():
         clock.t += dt
@@ -133,3 +133,45 @@ def test_percentile_nearest_rank():
 def test_bad_arguments():
     with pytest.raises(ValueError):
         Scheduler(FakeExecutor(Clock(), 1), 0, 4)
+    with pytest.raises(ValueError):
+        Scheduler(FakeExecutor(Clock(), 1), 10, 4, policy="lifo")
+    with pytest.raises(ValueError):
+        Scheduler(FakeExecutor(Clock(), 1), 10, 4, policy="shortest", max_age=-1.0)
+
+
+@pytest.mark.parametrize("policy", ["fair", "shortest"])
+def test_every_group_once_under_each_policy(policy):
+    reqs = trace(120, seed=4)
+    sch, ex, _ = run(reqs, policy=policy, max_age=0.05)
+    assert len(sch.finished) == len(reqs)
+    for r in reqs:
+        assert sorted(ex.coverage[r.rid]) == list(range(-(-r.length // FakeExecutor.GROUP)))
+
+
+def test_shortest_first_orders_by_groups_left():
+    """A launch goes to the requests with the fewest groups left, each taking
+    all it can; under fair share every request gets a slice."""
+    reqs = [Request(rid=0, op="encrypt", length=16 * 100, arrival=0.0),
+            Request(rid=1, op="encrypt", length=16 * 6, arrival=0.0),
+            Request(rid=2, op="encrypt", length=16 * 2, arrival=0.0)]
+    sch, ex, _ = run(reqs, tick=4, policy="shortest", max_age=10.0)
+    assert ex.ticks[0] == ("encrypt", [(2, 0, 2), (1, 0, 2)])
+    assert ex.ticks[1] == ("encrypt", [(1, 2, 4)])
+    assert reqs[2].completed < reqs[1].completed < reqs[0].completed
+    reqs = [Request(rid=r.rid, op=r.op, length=r.length, arrival=0.0) for r in reqs]
+    sch, ex, _ = run(reqs, tick=4, policy="fair")
+    assert {rid for rid, _, _ in ex.ticks[0][1]} == {0, 1, 2}
+
+
+def test_shortest_first_ages_long_requests():
+    """Once past max_age a request goes first, whatever its size."""
+    long = Request(rid=0, op="encrypt", length=16 * 40, arrival=0.0)
+    shorts = [Request(rid=1 + i, op="encrypt", length=16 * 4, arrival=0.001 * i)
+              for i in range(60)]
+    sch, ex, _ = run([long] + shorts, tick=4, policy="shortest", max_age=0.02)
+    first_long = next(i for i, (_, p) in enumerate(ex.ticks) if any(r == 0 for r, _, _ in p))
+    assert ex.ticks[first_long][1][0][0] == 0      # the aged request leads its launch
+    assert long.completed < max(r.completed for r in shorts)
+    sch, ex, _ = run([Request(rid=r.rid, op=r.op, length=r.length, arrival=r.arrival)
+                      for r in [long] + shorts], tick=4, policy="shortest", max_age=100.0)
+    assert sch.finished[-1].rid == 0               # never aged: served last

@@ -351,7 +351,8 @@ int pc2_runner_destroy(pc2_runner *runner);
  * arrive and poll for completion by request id.  A request is admitted when
  * the bytes of its inputs and output (encrypt: count * (4 m_limbs + 12 L);
  * hom_sum: count * 8 L (K + 1); decrypt: count * 12 L) fit in the server's
- * HBM budget beside those already admitted, first come, first served.  Each
+ * HBM budget beside those already admitted (in arrival order; see the launch
+ * policy for what happens to requests behind one that does not fit).  Each
  * operation has its own persistent launcher and stream; whenever a stream is
  * idle, the next scheduling pass launches up to tick_groups element groups
  * (pc2_runner_group_size elements each) drawn from the admitted requests of
@@ -404,14 +405,17 @@ int pc2_serve_progress(pc2_server *srv, size_t *pending);
  * The ids are then forgotten.  Makes no pass. */
 int pc2_serve_completed(pc2_server *srv, uint64_t *ids, size_t cap, size_t *n);
 
-/* Launch policy.  PC2_SERVE_SHORTEST (the default, with max_age_s = 1):
- * requests take the launch in increasing order of the groups they have left
- * (shortest remaining first, the order that minimises mean latency), except
- * that requests admitted more than max_age_s seconds ago go first, oldest
- * first, which bounds how long a long request can be passed over.
- * PC2_SERVE_FAIR: every admitted request of the operation gets an equal
- * slice of the launch, what is left goes to the oldest.  Applies from the
- * next launch. */
+/* Launch and admission policy.  PC2_SERVE_SHORTEST (the default, with
+ * max_age_s = 1): requests take the launch in increasing order of the groups
+ * they have left (shortest remaining first, the order that minimises mean
+ * latency), except that requests admitted more than max_age_s seconds ago go
+ * first, oldest first, which bounds how long a long request can be passed
+ * over; every waiting request that fits the budget is admitted, except that
+ * one submitted more than max_age_s ago which does not fit holds back those
+ * behind it.  PC2_SERVE_FAIR: every admitted request of the operation gets an
+ * equal slice of the launch, what is left goes to the oldest; admission is
+ * first come, first served (a request that does not fit holds back those
+ * behind it).  Applies from the next scheduling pass. */
 enum { PC2_SERVE_FAIR = 0, PC2_SERVE_SHORTEST = 1 };
 int pc2_server_set_policy(pc2_server *srv, int policy, double max_age_s);
 

@@ -3,8 +3,8 @@
 // Requests -- encryptions, aggregations and decryptions of vectors of any
 // length under one key -- arrive one at a time.  A request is admitted when
 // the bytes of its inputs and output fit in the server's HBM budget beside
-// the requests already admitted (first come, first served: a request that
-// does not fit holds back the ones behind it).  An admitted request is cut
+// the requests already admitted (see admit() for the order).  An admitted
+// request is cut
 // into element groups (one wavefront's share each).  Each operation has its
 // own persistent launcher (pc2_runner) on its own stream; whenever that
 // stream is idle, the next scheduling pass forms one launch over up to
@@ -59,7 +59,7 @@ struct Request {
   std::vector<size_t> lengths;          // hom_sum: the caller's lengths, copied (may be empty)
   size_t bytes = 0;                     // inputs + output, for admission
   size_t groups = 0, next = 0, done = 0;
-  double admitted = 0;                  // host clock, seconds
+  double submitted = 0, admitted = 0;   // host clock, seconds
 };
 
 double now_s() {
@@ -139,14 +139,26 @@ void retire(pc2_server* s, int op) {
   s->busy[op] = false;
 }
 
+// Fair share admits first come, first served: a request that does not fit
+// holds back those behind it.  Shortest first admits every waiting request
+// that fits, in arrival order, except that one submitted more than the age
+// limit ago which does not fit holds back those behind it (so the memory it
+// waits for is not taken by later requests).
 void admit(pc2_server* s) {
-  while (!s->waiting.empty() && s->used + s->waiting.front()->bytes <= s->budget) {
-    Request* r = s->waiting.front();
-    s->waiting.pop_front();
+  const bool first_fit = s->policy == PC2_SERVE_SHORTEST;
+  const double t = now_s();
+  for (auto it = s->waiting.begin(); it != s->waiting.end();) {
+    Request* r = *it;
+    if (s->used + r->bytes > s->budget) {
+      if (!first_fit || t - r->submitted > s->max_age) break;
+      ++it;
+      continue;
+    }
+    it = s->waiting.erase(it);
     const size_t g = s->group_elems[r->slot];
     r->groups = (r->job.count + g - 1) / g;
     r->state = ACTIVE;
-    r->admitted = now_s();
+    r->admitted = t;
     s->used += r->bytes;
     s->max_used = std::max(s->max_used, s->used);
     s->active[r->slot].push_back(r);
@@ -352,6 +364,7 @@ int pc2_serve_submit(pc2_server* s, const pc2_job* job, uint64_t* req_id) {
     finish(s, raw);
     return PC2_OK;
   }
+  raw->submitted = now_s();
   s->waiting.push_back(raw);
   return pass(s);
 }

@@ -2,7 +2,9 @@
 
 Requests (encrypt / aggregate / decrypt vectors of any length) arrive over
 time.  A request is admitted when its device memory fits in the HBM budget
-(first come, first served); an admitted request is cut into element groups
+(in arrival order; under the shortest-first policy later requests that fit
+may pass one that does not, until it has waited `max_age`); an admitted
+request is cut into element groups
 (one wavefront's share each).  Whenever the GPU stream of an operation is
 idle, the scheduler launches ONE persistent kernel over up to `tick_groups`
 groups drawn from the admitted requests of that operation -- shortest
@@ -99,14 +101,29 @@ class Scheduler:
         self.waiting.append(req)
 
     def _admit(self, now: float) -> None:
-        while self.waiting and self.used + self.waiting[0].nbytes <= self.budget:
+        """Fair: first come, first served (a request that does not fit holds
+        back those behind it).  Shortest: every waiting request that fits, in
+        arrival order, except that one waiting longer than max_age which does
+        not fit holds back those behind it."""
+        first_fit = self.policy == "shortest"
+        keep: deque[Request] = deque()
+        while self.waiting:
             req = self.waiting.popleft()
+            if self.used + req.nbytes > self.budget:
+                if not first_fit or now - req.arrival > self.max_age:
+                    keep.append(req)
+                    keep.extend(self.waiting)
+                    self.waiting.clear()
+                    break
+                keep.append(req)
+                continue
             self.ex.admit(req)
             req.admitted = now
             req.groups = -(-req.length // self.ex.group_size(req))
             self.used += req.nbytes
             self.max_used = max(self.max_used, self.used)
             self.active[req.op].append(req)
+        self.waiting = keep
 
     # ------------------------------------------------------------- batching
     def _form_tick(self, op: str) -> list:

@@ -96,7 +96,7 @@ def test_budget_and_fifo_admission():
     reqs = trace(80, seed=2)
     budget = 400_000
     big = [r for r in reqs if r.length * 100 > budget]
-    sch, ex, _ = run(reqs, budget=budget)
+    sch, ex, _ = run(reqs, budget=budget, policy="fair")
     assert sch.max_used <= budget
     assert {r.rid for r in sch.rejected} == {r.rid for r in big}
     admitted = sorted((r for r in reqs if r.admitted is not None), key=lambda r: r.admitted)
@@ -175,3 +175,26 @@ def test_shortest_first_ages_long_requests():
     sch, ex, _ = run([Request(rid=r.rid, op=r.op, length=r.length, arrival=r.arrival)
                       for r in [long] + shorts], tick=4, policy="shortest", max_age=100.0)
     assert sch.finished[-1].rid == 0               # never aged: served last
+
+
+def test_first_fit_admission_with_aging():
+    """Shortest first: small requests that fit pass a large one waiting for
+    memory, until it has waited max_age; then it holds them back, and the
+    budget is never exceeded."""
+    budget = 16 * 100 * 100 + 10_000             # one 100-group request and three small
+    reqs = [Request(rid=0, op="encrypt", length=16 * 100, arrival=0.0),
+            Request(rid=1, op="encrypt", length=16 * 100, arrival=0.0001)]
+    reqs += [Request(rid=2 + i, op="encrypt", length=16 * 2, arrival=0.0002 + 0.001 * i)
+             for i in range(40)]
+    sch, ex, _ = run(reqs, budget=budget, tick=8, policy="shortest", max_age=0.02)
+    assert sch.max_used <= budget
+    assert len(sch.finished) == len(reqs)
+    big2 = reqs[1]
+    passed = [r for r in reqs[2:] if r.admitted < big2.admitted]
+    late = [r for r in reqs[2:] if r.arrival > big2.arrival + 0.02 + 0.005]
+    assert passed                                 # small requests went ahead
+    assert all(r.admitted >= big2.admitted for r in late)   # not after it aged
+    sch, ex, _ = run([Request(rid=r.rid, op=r.op, length=r.length, arrival=r.arrival)
+                      for r in reqs], budget=budget, tick=8, policy="fair")
+    order = [r.rid for r in sorted(sch.finished, key=lambda r: (r.admitted, r.rid))]
+    assert order == sorted(order)                 # first come, first served

@@ -18,6 +18,7 @@ same data and reported beside it.  One JSON line is printed.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import multiprocessing as mp
 import os
@@ -199,13 +200,19 @@ def run_batching(pc2, gen, ctx, torch, np, args, reps: int = 3) -> dict:
                      lengths=[nd["L"] for nd in g["mem"]], out=g["agg"]) for g in groups]
     dec_jobs = [dict(op=pc2.PC2_OP_DECRYPT, sk=g["sk"], c=g["agg"], out=g["dec"]) for g in groups]
     batches = [pc2.Batch(ctx, j) for j in (enc_jobs, sum_jobs, dec_jobs)]
-    side = torch.cuda.Stream()
+    # a HIP stream of default priority made directly: torch.cuda.Stream()
+    # would create torch's whole stream pool, after which HIP can map the
+    # serving leg's three streams onto shared hardware queues
+    hip = ctypes.CDLL("libamdhip64.so")
+    side = ctypes.c_void_p()
+    if hip.hipStreamCreateWithFlags(ctypes.byref(side), ctypes.c_uint(1)) != 0:
+        raise RuntimeError("hipStreamCreateWithFlags failed")
 
     def batched():
-        with torch.cuda.stream(side):
-            for b in batches:
-                b.run()
-        side.synchronize()
+        for b in batches:
+            b.run(side.value)
+        if hip.hipStreamSynchronize(side) != 0:
+            raise RuntimeError("hipStreamSynchronize failed")
 
     def plain():
         for nd in nodes:
@@ -253,6 +260,7 @@ def run_batching(pc2, gen, ctx, torch, np, args, reps: int = 3) -> dict:
         exact &= bool(np.all(dec[:, 2:] == 0)) and bool(np.all(got == want))
     for b in batches:
         b.close()
+    hip.hipStreamDestroy(side)
     mb, mp = float(np.median(tb)), float(np.median(tp))
     log(f"batching: batched {mb * 1e3:.1f} ms, plain {mp * 1e3:.1f} ms per phase set")
     return {"workload": "16 nodes, lengths log-uniform [1024, 65536] (sum %d), keys 1024/2048-bit "

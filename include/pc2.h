@@ -358,8 +358,11 @@ int pc2_runner_destroy(pc2_runner *runner);
  * (pc2_runner_group_size elements each) drawn from the admitted requests of
  * that operation in the order of the launch policy (pc2_server_set_policy),
  * so requests that arrive while others run join the next launch and the
- * three operations overlap on the device.  Results are identical to the
- * one-call entry points.
+ * three operations overlap on the device.  (They overlap when HIP gives the
+ * three streams hardware queues of their own; in a process that has created
+ * many streams before -- torch's stream pool holds dozens -- they can share
+ * queues, and launches of different operations then run one after the
+ * other.)  Results are identical to the one-call entry points.
  *
  * Every pc2_serve_* call makes one scheduling pass (retire finished
  * launches, admit, launch on idle streams); nothing advances between calls,

@@ -146,7 +146,6 @@ std::vector<uint32_t> to_chunk(const Limbs& v, int D, int K, int T) {
   return out;
 }
 
-bool fits_digits(const Limbs& v, int D, int S) { return pc2h::bitlen(v) <= D * S; }
 
 // Montgomery constants of odd N in geometry (D, K, T), appended to buf.
 struct ModOffsets {
@@ -1013,7 +1012,6 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
   else return PC2_E_INVAL;
   // validate and collect classes
   int ca = -1, cb = -1, Ls = 0;
-  size_t ptr_words = 0;
   for (size_t i = 0; i < njobs; ++i) {
     const pc2_job& j = jobs[i];
     if (j.op != op_abi) return PC2_E_INVAL;
@@ -1028,7 +1026,6 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
       if (!j.inputs || j.K < 1 || j.K > (uint32_t)pc2k::RK_MAX) return PC2_E_INVAL;
       for (uint32_t k = 0; k < j.K; ++k)
         if (!j.inputs[k] || (j.lengths && j.lengths[k] > j.count)) return PC2_E_INVAL;
-      ptr_words += 2 * (size_t)j.K;
     }
     if (op == pc2k::OP_DEC) Ls = std::max(Ls, j.sk->c.h[0].Ls);
     const int g = job_geo(ctx, pk, op);
@@ -1416,7 +1413,7 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     else return PC2_E_UNSUPPORTED;
   }
   if (nitems == 0) return PC2_OK;
-  if (nitems > r->max_groups) return PC2_E_BUSY;
+  if (nitems > r->max_groups || nptrs > r->max_ptrs) return PC2_E_BUSY;
   if (cb < 0) cb = ca;
   const int pair = pc2k::batch_pair(ca, cb);
   if (pair < 0) return PC2_E_UNSUPPORTED;

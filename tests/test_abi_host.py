@@ -78,6 +78,7 @@ def test_null_arguments_rejected(pc2):
     assert lib.pc2_serve_progress(None, None) == INVAL
     assert lib.pc2_serve_completed(None, None, 0, ctypes.byref(n)) == INVAL
     assert lib.pc2_server_stats(None, None, None, None) == INVAL
+    assert lib.pc2_server_set_policy(None, pc2.PC2_SERVE_SHORTEST, 1.0) == INVAL
     assert lib.pc2_server_destroy(None) == INVAL
 
 

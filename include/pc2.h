@@ -289,7 +289,9 @@ int pc2_colsplit_destroy(pc2_colsplit *cs);
 
 /* ------------------------------------------------------ batched launches */
 
-/* One job of a batch.  A batch runs one phase of many edge nodes' work --
+/* One job of a batch.  (Its output may be one of its inputs exactly, as for
+ * the data calls; any other overlap is PC2_E_INVAL.)  A batch runs one phase
+ * of many edge nodes' work --
  * all their encryptions, all their aggregations or all their decryptions --
  * in ONE persistent launch, whatever the vector lengths, under keys of up to
  * two size classes (supported mixes: one class of 256, 1024, 2048, 3072 or

@@ -542,6 +542,22 @@ bool partial_overlap(const void* a, size_t na, const void* b, size_t nb) {
   if (x + na <= y || y + nb <= x) return false;
   return !(x == y && na == nb);
 }
+
+// A job's output against its inputs under the same rule (L: limbs of n).
+bool job_overlaps(const pc2_job& j, int L) {
+  const size_t n = j.count;
+  if (j.op == PC2_OP_ENCRYPT) {
+    const size_t cb = 8 * (size_t)L * n;
+    return partial_overlap(j.out, cb, j.in0, 4 * (size_t)j.m_limbs * n) ||
+           partial_overlap(j.out, cb, j.in1, 4 * (size_t)L * n);
+  }
+  if (j.op == PC2_OP_DECRYPT) return partial_overlap(j.out, 4 * (size_t)L * n, j.in0, 8 * (size_t)L * n);
+  for (uint32_t k = 0; k < j.K; ++k) {  // input k holds lengths[k] rows (ragged) or count
+    const size_t rows = j.lengths ? j.lengths[k] : n;
+    if (partial_overlap(j.out, 8 * (size_t)L * n, j.inputs[k], 8 * (size_t)L * rows)) return true;
+  }
+  return false;
+}
 }  // namespace
 
 // ================================================================ ABI
@@ -1027,6 +1043,7 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
       for (uint32_t k = 0; k < j.K; ++k)
         if (!j.inputs[k] || (j.lengths && j.lengths[k] > j.count)) return PC2_E_INVAL;
     }
+    if (job_overlaps(j, pk->L)) return PC2_E_INVAL;
     if (op == pc2k::OP_DEC) Ls = std::max(Ls, j.sk->c.h[0].Ls);
     const int g = job_geo(ctx, pk, op);
     if (ca < 0 || ca == g) ca = g;
@@ -1407,6 +1424,7 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
         if (!j.inputs[k] || (j.lengths && j.lengths[k] > j.count)) return PC2_E_INVAL;
       nptrs += 2 * (size_t)j.K;
     }
+    if (job_overlaps(j, pk->L)) return PC2_E_INVAL;
     nitems += ngroups[i];
     if (ca < 0 || ca == g) ca = g;
     else if (cb < 0 || cb == g) cb = g;

@@ -256,6 +256,14 @@ int pass(pc2_server* s) {
   return PC2_OK;
 }
 
+// Two device arrays overlap without being the same array of the same size
+// (the only aliasing the library accepts between an output and an input).
+bool partial_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  if (x + na <= y || y + nb <= x) return false;
+  return !(x == y && na == nb);
+}
+
 // The op and the key always; the arrays only when there is work (count > 0).
 int check_job(const pc2_server* s, const pc2_job& j) {
   const int slot = op_slot(j.op);
@@ -269,6 +277,16 @@ int check_job(const pc2_server* s, const pc2_job& j) {
     for (uint32_t k = 0; k < j.K; ++k)
       if (!j.inputs[k] || (j.lengths && j.lengths[k] > j.count)) return PC2_E_INVAL;
   }
+  const size_t n = j.count, L = s->L;
+  if (slot == 0 && (partial_overlap(j.out, 8 * L * n, j.in0, 4 * (size_t)j.m_limbs * n) ||
+                    partial_overlap(j.out, 8 * L * n, j.in1, 4 * L * n)))
+    return PC2_E_INVAL;
+  if (slot == 2 && partial_overlap(j.out, 4 * L * n, j.in0, 8 * L * n)) return PC2_E_INVAL;
+  if (slot == 1)
+    for (uint32_t k = 0; k < j.K; ++k) {  // input k holds lengths[k] rows (ragged) or count
+      const size_t rows = j.lengths ? j.lengths[k] : n;
+      if (partial_overlap(j.out, 8 * L * n, j.inputs[k], 8 * L * rows)) return PC2_E_INVAL;
+    }
   return PC2_OK;
 }
 

@@ -106,3 +106,25 @@ def test_partial_overlap_refused(gpu_ctx, setup):
             call()
         assert e.value.status == pc2.PC2_E_INVAL, f"case {i}"
     assert gpu_ctx.sync() == 0
+
+
+def test_batch_jobs_follow_the_aliasing_rule(gpu_ctx, setup):
+    """Batches: an aggregation into one of its inputs gives the out-of-place
+    result; an output over another job array is refused at planning."""
+    from paper_2601_14980_amd import pc2
+    sk, L, cs = setup["sk"], setup["L"], setup["cs"]
+    ref = torch.empty_like(cs[0])
+    pc2.pc2_hom_sum(sk.public, [cs[0], cs[1]], ref)
+    inplace = cs[0].clone()
+    b = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_HOM_SUM, pk=sk.public, inputs=[inplace, cs[1]],
+                                 out=inplace)])
+    b.run(0)
+    assert gpu_ctx.sync() == 0
+    assert torch.equal(inplace, ref)
+    b.close()
+    n = 64
+    flat = torch.zeros(n * 2 * L, dtype=torch.int32, device="cuda")
+    with pytest.raises(pc2.PC2Error) as e:     # plaintexts over the first half of c
+        pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_DECRYPT, sk=sk, c=flat.view(n, 2 * L),
+                                 out=flat[:n * L].view(n, L))])
+    assert e.value.status == pc2.PC2_E_INVAL

@@ -157,6 +157,11 @@ def test_server_argument_errors(gpu_ctx, keyset):
         srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=big[:, :2].contiguous(),
                         r=big[:, :L].contiguous(), out=big))
     assert e.value.status == pc2.PC2_E_NOMEM
+    flat = torch.zeros(8 * L * 2, dtype=torch.int32, device="cuda")
+    with pytest.raises(pc2.PC2Error) as e:      # output over its randomness, one row apart
+        srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m,
+                        r=flat[:4 * L].view(4, L), out=flat[L:L + 8 * L].view(4, 2 * L)))
+    assert e.value.status == pc2.PC2_E_INVAL
     empty = torch.zeros((0, 2 * L), dtype=torch.int32, device="cuda")
     z = srv.submit(dict(op=pc2.PC2_OP_ENCRYPT, pk=sk.public, m=m[:0], r=r[:0], out=empty))
     assert srv.poll(z)                          # nothing to compute: done at once

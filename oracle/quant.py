@@ -11,7 +11,12 @@ the offset o = -z_min s an integer.  Then Gamma_2 takes the affine form
     Gamma_2(x) = rint(x * 2^k) + o,
 
 where rint rounds half to even (the paper writes only "rounding") and x * 2^k
-is exact in float64, so there is exactly one rounding.
+is exact in float64, so there is exactly one rounding.  Gamma_2 maps the
+interval onto {0, ..., Delta}; with z_min = -o / 2^k and z_max = (Delta - o) / 2^k
+an input outside [z_min, z_max) is an error (Theorem 1 assumes every
+quantized value lies in the common interval), never clamped.  The top of the
+interval is open, so that adjacent intervals of the same scale do not share
+a point; rounding can still reach Delta itself from just below z_max.
 
 Inverse quantization (Sec. III-C, inverse-quantization formula): a decrypted
 integer M that is the sum of W quantized addends (W = K for a K-way
@@ -27,20 +32,27 @@ not generalise to N > 1.
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 from typing import Sequence
 
 U64 = 1 << 64
 
 
-def quantize(x: float, log2_scale: int, offset: int) -> int:
-    """Gamma_2 in affine form: rint(x 2^k) + o, required to lie in [0, 2^64)."""
+def quantize(x: float, log2_scale: int, offset: int, delta: int) -> int:
+    """Gamma_2 in affine form: rint(x 2^k) + o for x in the common interval
+    [-o / 2^k, (Delta - o) / 2^k), so that the result lies in {0, ..., Delta}.
+
+    0 <= o <= Delta < 2^64 is required of the parameters."""
+    if not (0 <= offset <= delta < U64):
+        raise ValueError("quantizer needs 0 <= offset <= delta < 2^64")
     if not math.isfinite(x):
         raise ValueError("non-finite input")
-    v = round(math.ldexp(x, log2_scale))  # Python rounds floats half to even
-    m = v + offset
-    if not (0 <= m < U64):
-        raise ValueError("quantized value outside [0, 2^64)")
-    return m
+    t = math.ldexp(x, log2_scale)  # exact: a power-of-two scale
+    # -o <= t < Delta - o, compared exactly as rationals (t is a binary fraction)
+    if not (-offset <= Fraction(t) < delta - offset):
+        raise ValueError("input outside the quantizer's common interval")
+    v = round(t)  # Python rounds floats half to even
+    return v + offset
 
 
 def dequantize(M: int, log2_scale: int, offset: int, weight: int) -> float:
@@ -49,8 +61,8 @@ def dequantize(M: int, log2_scale: int, offset: int, weight: int) -> float:
     return math.ldexp(float(d), -log2_scale)
 
 
-def quantize_vec(xs: Sequence[float], log2_scale: int, offset: int) -> list[int]:
-    return [quantize(float(x), log2_scale, offset) for x in xs]
+def quantize_vec(xs: Sequence[float], log2_scale: int, offset: int, delta: int) -> list[int]:
+    return [quantize(float(x), log2_scale, offset, delta) for x in xs]
 
 
 def dequantize_vec(Ms: Sequence[int], log2_scale: int, offset: int,

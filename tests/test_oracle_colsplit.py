@@ -101,6 +101,36 @@ def test_inverse_quantization_expands_to_centered_sums():
             assert x[i] == math.ldexp(float(direct), -2 * k)
 
 
+def test_fixed_order_loop_equals_plain_definition():
+    """The oracle's float64 loop (summation in a fixed order, Gauss-Jordan
+    without row exchanges, x_k = alpha_k + rho B_k (z_k - v_k) with alpha_k =
+    B_k A_k^T y) against the iteration written from its definition with
+    LAPACK's solver and numpy's products: x_k = solve(A_k^T A_k + rho I,
+    A_k^T y + rho (z_k - v_k)), z = t - clip(t, -lambda/rho, lambda/rho) for
+    t = v + x (the soft threshold), v = t - z.  50 iterations, 1e-12 relative
+    at every one of them."""
+    M, N, K, rho, lam = 150, 120, 3, 1.0, 0.02
+    A, y = _data(M, N, 8)
+    cs = C.ColumnSplitLasso(A, y, K, rho, 40)
+    Nk = N // K
+    z, v = np.zeros(N), np.zeros(N)
+    zp, vp = np.zeros(N), np.zeros(N)
+    for _ in range(50):
+        x, z, v = cs.iterate(z, v, lam, quantized=False)
+        xp = np.concatenate([
+            np.linalg.solve(A[:, k * Nk:(k + 1) * Nk].T @ A[:, k * Nk:(k + 1) * Nk]
+                            + rho * np.eye(Nk),
+                            A[:, k * Nk:(k + 1) * Nk].T @ y
+                            + rho * (zp[k * Nk:(k + 1) * Nk] - vp[k * Nk:(k + 1) * Nk]))
+            for k in range(K)])
+        t = vp + xp
+        zp = t - np.clip(t, -lam / rho, lam / rho)
+        vp = t - zp
+        for got, want in ((x, xp), (z, zp), (v, vp)):
+            assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    assert np.count_nonzero(z) not in (0, N)  # the threshold is active on both sides
+
+
 def test_quantizer_range():
     with pytest.raises(ValueError):
         C.gamma2(np.array([8.0]), 10)

@@ -21,7 +21,22 @@ PINS_QUANT = [
     pins.test_quantize_error_bound_and_aggregate,
     pins.test_quantize_ties_round_half_even,
     pins.test_quantize_range,
+    pins.test_quantize_common_interval,
     pins.test_dequantize_rounding_above_2_53,
+]
+
+
+def _agg_identities_64():
+    import random as _r
+    from workload import gen as _g
+    p, q = _g.primes_for(7, 64)
+    pk, sk = O.derive_keys(p, q)
+    pins._aggregate_identities(pk, sk, _r.Random(5))
+
+
+PINS_AGG = [
+    lambda: pins.test_hom_sum_bruteforce_tiny(3, 5, 3),
+    _agg_identities_64,
 ]
 
 
@@ -29,7 +44,8 @@ def _caught(checks) -> bool:
     for chk in checks:
         try:
             chk()
-        except (AssertionError, ValueError, ArithmeticError, ZeroDivisionError, LookupError):
+        except (AssertionError, ValueError, ArithmeticError, ZeroDivisionError, LookupError,
+                pytest.fail.Exception):  # a pytest.raises block that did not raise
             return True
     return False
 
@@ -136,14 +152,41 @@ def test_crypto_mutants_caught(monkeypatch, name, target, mutant):
     assert _caught(PINS_CRYPTO), f"mutant '{name}' survived the pins"
 
 
-def _q_floor(x, k, o):
+def _q_floor(x, k, o, dl):
     v = math.floor(math.ldexp(x, k))  # mistake: floor instead of round-half-even
     return v + o
 
 
-def _q_half_up(x, k, o):
+def _q_half_up(x, k, o, dl):
     v = math.floor(math.ldexp(x, k) + 0.5)  # mistake: ties away from even
     return v + o
+
+
+def _q_checks_result(x, k, o, dl):
+    if not math.isfinite(x):
+        raise ValueError("non-finite input")
+    m = round(math.ldexp(x, k)) + o
+    if not (0 <= m <= dl):            # mistake: the rounded result is checked, not x
+        raise ValueError("out of range")
+    return m
+
+
+def _q_closed_top(x, k, o, dl):
+    if not math.isfinite(x):
+        raise ValueError("non-finite input")
+    t = math.ldexp(x, k)
+    if not (-o <= t <= dl - o):       # mistake: z_max itself accepted
+        raise ValueError("out of range")
+    return round(t) + o
+
+
+def _q_no_interval(x, k, o, dl):
+    if not math.isfinite(x):
+        raise ValueError("non-finite input")
+    m = round(math.ldexp(x, k)) + o   # mistake: only [0, 2^64) is enforced
+    if not (0 <= m < 1 << 64):
+        raise ValueError("out of range")
+    return m
 
 
 def _dq_no_weight(M, k, o, W):
@@ -158,12 +201,85 @@ def _dq_truncating(M, k, o, W):
 @pytest.mark.parametrize("name,target,mutant", [
     ("floor", "quantize", _q_floor),
     ("half up", "quantize", _q_half_up),
+    ("result checked, not x", "quantize", _q_checks_result),
+    ("closed top", "quantize", _q_closed_top),
+    ("no interval", "quantize", _q_no_interval),
     ("no weight", "dequantize", _dq_no_weight),
     ("truncating", "dequantize", _dq_truncating),
 ])
 def test_quant_mutants_caught(monkeypatch, name, target, mutant):
     monkeypatch.setattr(Q, target, mutant)
     assert _caught(PINS_QUANT), f"mutant '{name}' survived the pins"
+
+
+# ------------------------------------------------------- K-way aggregation
+def _sum_no_reduction(pk, cs):
+    acc = 1
+    for c in cs:
+        acc = acc * c                  # mistake: the product is never reduced mod n^2
+    return acc
+
+
+def _sum_starts_at_zero(pk, cs):
+    acc = 0                            # mistake: empty product taken as 0
+    for c in cs:
+        acc = (acc * c) % pk.n2
+    return acc
+
+
+def _sum_skips_first(pk, cs):
+    acc = 1
+    for c in list(cs)[1:]:             # mistake: the first addend is skipped
+        acc = (acc * c) % pk.n2
+    return acc
+
+
+def _sum_skips_last(pk, cs):
+    acc = 1
+    for c in list(cs)[:-1] or list(cs):  # mistake: the last addend is skipped (K > 1)
+        acc = (acc * c) % pk.n2
+    return acc
+
+
+def _sum_mod_n(pk, cs):
+    acc = 1
+    for c in cs:
+        acc = (acc * c) % pk.n         # mistake: reduced mod n instead of n^2
+    return acc
+
+
+def _sum_vec_first_element(pk, cvs):
+    return [O.hom_sum(pk, (cv[0] for cv in cvs)) for _ in range(len(cvs[0]))]  # mistake: index
+
+
+def _sum_vec_transposed(pk, cvs):
+    K, J = len(cvs), len(cvs[0])       # mistake: element j combines row j of every vector
+    return [O.hom_sum(pk, (cvs[min(j, K - 1)][k] for k in range(J))) for j in range(J)]
+
+
+def _esd_first_only(sk, ms, rs):
+    pk = sk.public                     # mistake: only the first contribution is decrypted
+    return O.decrypt(sk, O.encrypt(pk, ms[0], rs[0]))
+
+
+def _esd_plain_sum(sk, ms, rs):
+    return sum(ms)                     # mistake: no reduction mod n
+
+
+@pytest.mark.parametrize("name,target,mutant", [
+    ("sum without reduction", "hom_sum", _sum_no_reduction),
+    ("sum starts at 0", "hom_sum", _sum_starts_at_zero),
+    ("sum skips the first addend", "hom_sum", _sum_skips_first),
+    ("sum skips the last addend", "hom_sum", _sum_skips_last),
+    ("sum mod n", "hom_sum", _sum_mod_n),
+    ("vector sum indexes element 0", "hom_sum_vec", _sum_vec_first_element),
+    ("vector sum transposed", "hom_sum_vec", _sum_vec_transposed),
+    ("fused keeps one contribution", "enc_sum_dec", _esd_first_only),
+    ("fused sum not reduced", "enc_sum_dec", _esd_plain_sum),
+])
+def test_aggregation_mutants_caught(monkeypatch, name, target, mutant):
+    monkeypatch.setattr(O, target, mutant)
+    assert _caught(PINS_AGG), f"mutant '{name}' survived the pins"
 
 
 # ------------------------------------------------- column-split ADMM oracle

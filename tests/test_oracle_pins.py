@@ -8,12 +8,18 @@
 * CPython's built-in three-argument pow and sympy's primality/inverse
 * the CRT route reaching the plain decryption
 * Euler/Carmichael: (r^n)^lambda = 1 (mod n^2)
-* the quantizer's exact error bound and exact aggregate dequantization
+* the quantizer's exact error bound and exact aggregate dequantization, and
+  its common interval checked on the input, not on the rounded result
+* the K-way aggregation (Definition 1 applied K - 1 times) and the fused
+  encrypt -> aggregate -> decrypt: brute force over every K-tuple of tiny
+  keys, and the exact identity prod_k Enc(a_k, r_k) = Enc(sum a_k, prod r_k)
+  at every key size
 * the ciphertext mat-vec decrypting to the integer mat-vec, and its special
   cases (identity and zero matrices, one column against built-in pow)
 """
 from __future__ import annotations
 
+import itertools
 import math
 import random
 from pathlib import Path
@@ -184,10 +190,10 @@ def test_invariants_and_edges(key):
 # ------------------------------------------------------------ quantization
 def test_quantize_error_bound_and_aggregate():
     rng = np.random.default_rng(1)
-    k, o = 20, 1 << 23
+    k, o, dl = 20, 1 << 23, 1 << 24
     s = 2.0 ** k
     xs = rng.standard_normal((8, 500))
-    qs = [Q.quantize_vec(x, k, o) for x in xs]
+    qs = [Q.quantize_vec(x, k, o, dl) for x in xs]
     for x, qv in zip(xs, qs):
         for xi, mi in zip(x, qv):
             assert abs(xi - Q.dequantize(mi, k, o, 1)) <= 0.5 / s
@@ -202,25 +208,102 @@ def test_quantize_error_bound_and_aggregate():
 def test_quantize_ties_round_half_even():
     k, o = 1, 100
     # x * 2 = 0.5, 1.5, 2.5, -0.5, -1.5 -> 0, 2, 2, -0, -2
-    assert [Q.quantize(x, k, o) for x in (0.25, 0.75, 1.25, -0.25, -0.75)] == \
+    assert [Q.quantize(x, k, o, 200) for x in (0.25, 0.75, 1.25, -0.25, -0.75)] == \
         [100, 102, 102, 100, 98]
 
 
 def test_quantize_range():
+    top = (1 << 64) - 1
     with pytest.raises(ValueError):
-        Q.quantize(float("nan"), 10, 0)
+        Q.quantize(float("nan"), 10, 0, top)
     with pytest.raises(ValueError):
-        Q.quantize(-1.0, 10, 5)
+        Q.quantize(float("inf"), 10, 0, top)
     with pytest.raises(ValueError):
-        Q.quantize(2.0 ** 60, 10, 0)
-    assert Q.quantize(-1.0, 10, 1024) == 0
-    assert Q.quantize(0.0, 0, (1 << 64) - 1) == (1 << 64) - 1
+        Q.quantize(-1.0, 10, 5, top)
+    with pytest.raises(ValueError):
+        Q.quantize(2.0 ** 60, 10, 0, top)
+    with pytest.raises(ValueError):
+        Q.quantize(0.0, 0, 9, 8)  # offset above delta
+    assert Q.quantize(-1.0, 10, 1024, 2048) == 0
+    assert Q.quantize(0.0, 0, top - 1, top) == top - 1
+
+
+def test_quantize_common_interval():
+    """Sec. III-A maps [z_min, z_max] onto {0, ..., Delta}; with s = 2, o = 4,
+    Delta = 8 the interval is [-2, 2): its ends, values that round back into
+    it, and the largest value below z_max, which rounds to Delta itself."""
+    k, o, dl = 1, 4, 8
+    assert Q.quantize(-2.0, k, o, dl) == 0                  # z_min is in
+    assert Q.quantize(1.75, k, o, dl) == 8                  # 3.5 rounds (to even) to 4: Delta
+    assert Q.quantize(1.25, k, o, dl) == 6                  # 2.5 -> 2
+    assert Q.quantize(math.nextafter(2.0, 0.0), k, o, dl) == 8
+    for x in (2.0, 2.25, -2.25, math.nextafter(-2.0, -3.0), 1e300, -1e300):
+        with pytest.raises(ValueError):                     # -2.25 would round to m = 0
+            Q.quantize(x, k, o, dl)
+    # the benchmark's quantizer: [-8, 8) at scale 2^20
+    q = gen.Q_PLAIN
+    assert Q.quantize(-8.0, q.log2_scale, q.offset, q.delta) == 0
+    assert Q.quantize(math.nextafter(8.0, 0.0), q.log2_scale, q.offset, q.delta) == q.delta
+    with pytest.raises(ValueError):
+        Q.quantize(8.0, q.log2_scale, q.offset, q.delta)
 
 
 def test_dequantize_rounding_above_2_53():
     # float(int) rounds to nearest even: 2^53 + 1 -> 2^53, 2^53 + 3 -> 2^53 + 4
     assert Q.dequantize((1 << 53) + 1, 0, 0, 1) == float(1 << 53)
     assert Q.dequantize((1 << 53) + 3, 0, 0, 1) == float((1 << 53) + 4)
+
+
+# ------------------------------------------------------- K-way aggregation
+def _units(n):
+    return [r for r in range(1, n) if math.gcd(r, n) == 1]
+
+
+@pytest.mark.parametrize("p,q,kmax", [(3, 5, 3), (5, 7, 3), (7, 11, 2)])
+def test_hom_sum_bruteforce_tiny(p, q, kmax):
+    """Every K-tuple of plaintexts (K = 1..kmax) under tiny keys: the K-way
+    aggregate is exactly Enc(sum m_k mod n, prod r_k mod n) (since
+    (x + j n)^n = x^n mod n^2), it decrypts to the sum mod n, and the fused
+    encrypt -> aggregate -> decrypt returns that sum."""
+    pk, sk = O.derive_keys(p, q)
+    n = p * q
+    units = _units(n)
+    rng = random.Random(n * 31)
+    for K in range(1, kmax + 1):
+        for ms in itertools.product(range(n), repeat=K):
+            rs = [rng.choice(units) for _ in ms]
+            cs = [O.encrypt(pk, m, r) for m, r in zip(ms, rs)]
+            agg = O.hom_sum(pk, cs)
+            assert agg == O.encrypt(pk, sum(ms) % n, math.prod(rs) % n)
+            assert O.decrypt(sk, agg) == sum(ms) % n
+            assert O.enc_sum_dec(sk, ms, rs) == sum(ms) % n
+
+
+def _aggregate_identities(pk, sk, rng):
+    n = pk.n
+    for K in (1, 2, 5):
+        a = [rng.randrange(n) for _ in range(K)]
+        r = gen.gen_r(n, K, 12, extra=K + pk.nbits)
+        cs = [O.encrypt(pk, ai, ri) for ai, ri in zip(a, r)]
+        assert O.hom_sum(pk, cs) == O.encrypt(pk, sum(a) % n, math.prod(r) % n)
+    # element-wise over K vectors of length 3: element j combines only column j
+    K, J = 3, 3
+    a = [[rng.randrange(n) for _ in range(J)] for _ in range(K)]
+    r = [gen.gen_r(n, J, 13, extra=k + pk.nbits) for k in range(K)]
+    cvs = [O.encrypt_vec(pk, a[k], r[k]) for k in range(K)]
+    got = O.hom_sum_vec(pk, cvs)
+    assert got == [O.encrypt(pk, sum(a[k][j] for k in range(K)) % n,
+                             math.prod(r[k][j] for k in range(K)) % n) for j in range(J)]
+    # the fused form: plaintexts that wrap past n, and the largest plaintexts
+    ms = [n - 1, n - 2, 1, rng.randrange(n)]
+    rs = gen.gen_r(n, 4, 14, extra=pk.nbits)
+    assert O.enc_sum_dec(sk, ms, rs) == sum(ms) % n
+    assert O.enc_sum_dec(sk, [n - 1], [n - 1]) == n - 1
+
+
+def test_aggregate_identities(key):
+    _, _, pk, sk = key
+    _aggregate_identities(pk, sk, random.Random(pk.nbits + 77))
 
 
 # ------------------------------------------------------ ciphertext mat-vec

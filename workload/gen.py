@@ -99,15 +99,17 @@ def gen_r_limbs(n: int, count: int, nlimbs: int, config: int, extra: int = 0) ->
 
 @dataclass(frozen=True)
 class QParams:
-    """Affine quantizer m = rint(x 2^log2_scale) + offset."""
+    """Affine quantizer m = rint(x 2^log2_scale) + offset on the common
+    interval [-offset, delta - offset) / 2^log2_scale, onto {0, ..., delta}."""
     log2_scale: int
     offset: int
+    delta: int
 
 
 # Quantizer settings per workload (common interval, power-of-two scale).
-Q_TINY = QParams(16, 1 << 19)       # [-8, 8] -> [0, 2^20)
-Q_PLAIN = QParams(20, 1 << 23)      # [-8, 8) -> [0, 2^24)
-Q_ADMM = QParams(44, 1 << 51)       # [-128, 128) -> [0, 2^52)
+Q_TINY = QParams(16, 1 << 19, 1 << 20)      # [-8, 8) -> {0, ..., 2^20}
+Q_PLAIN = QParams(20, 1 << 23, 1 << 24)     # [-8, 8) -> {0, ..., 2^24}
+Q_ADMM = QParams(44, 1 << 51, 1 << 52)      # [-128, 128) -> {0, ..., 2^52}
 
 
 def uniform_vectors(config: int, k: int, length: int, lo: float = -1.0, hi: float = 1.0):

@@ -181,7 +181,7 @@ def run_batching(pc2, gen, ctx, torch, np, args, reps: int = 3) -> dict:
         sk = keys[i % 2]
         x = torch.from_numpy(xs[i]).cuda()
         m = torch.empty(L, dtype=torch.int64, device="cuda")
-        pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, x, m)
+        pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, qp.delta, x, m)
         r = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, L, sk.L, BATCH_SEED, extra=i))
         c = torch.empty((L, 2 * sk.L), dtype=torch.int32, device="cuda")
         nodes.append(dict(sk=sk, L=L, m=m.view(torch.int32).reshape(L, 2), r=r, c=c))
@@ -293,7 +293,7 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
     xq = torch.from_numpy(rng.standard_normal(PL)).cuda()
     qp = gen.Q_PLAIN
     mpool = torch.empty(PL, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, xq, mpool)
+    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, qp.delta, xq, mpool)
     mpool2 = mpool.view(torch.int32).reshape(PL, 2)
     rpool = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, PL, L, SERVE_SEED))
     cpool = []
@@ -470,7 +470,7 @@ def run_key4096(pc2, gen, ctx, torch, np, args) -> dict:
     qp = gen.Q_PLAIN
     x = torch.from_numpy(rng.standard_normal(count)).cuda()
     mq = torch.empty(count, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, x, mq)
+    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, qp.delta, x, mq)
     m2 = mq.view(torch.int32).reshape(count, 2)
     r = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, count, L, KEY4096_SEED))
     c = torch.empty((count, 2 * L), dtype=torch.int32, device="cuda")
@@ -527,7 +527,7 @@ def run_matvec(pc2, gen, ctx, sk, torch, np, args) -> dict:
     qp = gen.Q_PLAIN
     x = torch.from_numpy(rng.standard_normal(2 * D)).cuda()
     mq = torch.empty(2 * D, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, x, mq)
+    pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, qp.delta, x, mq)
     r = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, 2 * D, L, MATVEC_SEED))
     enc = torch.empty((2 * D, 2 * L), dtype=torch.int32, device="cuda")
     pc2.pc2_encrypt(sk.public, mq.view(torch.int32).reshape(2 * D, 2), r, enc)
@@ -615,7 +615,8 @@ def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
     Ad = torch.from_numpy(A).cuda()
     yd = torch.from_numpy(y).cuda()
     del A
-    drv = EncryptedConsensusLasso(ctx, sk, Ad, yd, K, 1.0, lam, qa.log2_scale, qa.offset, r_pool)
+    drv = EncryptedConsensusLasso(ctx, sk, Ad, yd, K, 1.0, lam, qa.log2_scale, qa.offset,
+                                  qa.delta, r_pool)
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     out = {"workload": "lasso A 4096x16384 ~ N(0,1/4096), 32 nodes x 128 rows, x* 1% sparse, "
@@ -632,7 +633,7 @@ def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             drv.local(z, u)
-            pc2.pc2_quantize(ctx, qa.log2_scale, qa.offset, drv.xu.reshape(-1), drv.m)
+            pc2.pc2_quantize(ctx, qa.log2_scale, qa.offset, qa.delta, drv.xu.reshape(-1), drv.m)
             ev[0].record(stream)
             pc2.pc2_encrypt(sk.public, drv.m.view(torch.int32).reshape(K * N, 2), drv.r, drv.c)
             ev[1].record(stream)
@@ -757,7 +758,7 @@ def main() -> int:
     dec_ms: list[float] = []
 
     def step_batched(record: bool) -> None:
-        pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, x_all, m_all)
+        pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, qp.delta, x_all, m_all)
         ev[0].record(stream)
         pc2.pc2_encrypt(pk, m2_all, r_all, c_all)
         ev[1].record(stream)
@@ -774,7 +775,7 @@ def main() -> int:
     def step_plain() -> None:
         for k in range(NODES):
             sl = slice(k * LENGTH, (k + 1) * LENGTH)
-            pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, x_all[sl], m_all[sl])
+            pc2.pc2_quantize(ctx, qp.log2_scale, qp.offset, qp.delta, x_all[sl], m_all[sl])
             ctx.sync()
         for k in range(NODES):
             sl = slice(k * LENGTH, (k + 1) * LENGTH)

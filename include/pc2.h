@@ -65,10 +65,14 @@ typedef struct pc2_pk pc2_pk;
 typedef struct pc2_sk pc2_sk;
 
 /* Affine quantizer (Sec. III-A, Gamma_2 with a common interval and a
- * power-of-two scale): m = rint(x * 2^log2_scale) + offset. */
+ * power-of-two scale): m = rint(x * 2^log2_scale) + offset on the common
+ * interval [z_min, z_max) = [-offset, delta - offset) / 2^log2_scale (the
+ * interval Theorem 1 assumes every quantized value lies in), onto
+ * {0, ..., delta}; 0 <= offset <= delta.  Only pc2_quantize reads delta. */
 typedef struct {
   int32_t log2_scale;
   uint64_t offset;
+  uint64_t delta;
 } pc2_qparams;
 
 /* ------------------------------------------------------------- context */
@@ -147,8 +151,9 @@ int pc2_pk_context(const pc2_pk *pk, pc2_ctx **ctx, int *hip_device);
 
 /* Quantize (Sec. III-A, Gamma_2 in affine form): m[i] = rint(x[i] * 2^k) + o,
  * rint = round half to even.  x: double[count]; m: uint64[count] (equal to
- * two uint32 limbs per element).  Non-finite x or a result outside
- * [0, 2^64) -> m = 0 and PC2_E_RANGE latched. */
+ * two uint32 limbs per element).  Non-finite x or x outside the common
+ * interval [-o, delta - o) / 2^k (compared exactly) -> m = 0 and PC2_E_RANGE
+ * latched; there is no clamping.  offset > delta is PC2_E_INVAL. */
 int pc2_quantize(pc2_ctx *ctx, const pc2_qparams *q, const double *x, uint64_t *m,
                  size_t count, void *stream);
 

@@ -33,11 +33,11 @@ def _f64(t: torch.Tensor, what: str) -> int:
 
 class EncryptedConsensusLasso:
     def __init__(self, ctx: pc2.Context, sk: pc2.SecretKey, A: torch.Tensor, y: torch.Tensor,
-                 K: int, rho: float, lam: float, log2_scale: int, offset: int,
+                 K: int, rho: float, lam: float, log2_scale: int, offset: int, delta: int,
                  r_pool: torch.Tensor):
         M, N = A.shape
         self.ctx, self.sk, self.K, self.N = ctx, sk, K, N
-        self.rho, self.lam, self.k, self.o = rho, lam, log2_scale, offset
+        self.rho, self.lam, self.k, self.o, self.delta = rho, lam, log2_scale, offset, delta
         self.A, self.y = A, y
         h = c_void_p()
         pc2._check(_lib.pc2_admm_create(ctx.handle, _f64(A, "A"), _f64(y, "y"), M, N, K, rho,
@@ -75,7 +75,7 @@ class EncryptedConsensusLasso:
     def aggregate(self) -> None:
         """total = sum_k x_k + u_k through quantize -> encrypt -> product -> decrypt."""
         K, N = self.K, self.N
-        pc2.pc2_quantize(self.ctx, self.k, self.o, self.xu.reshape(-1), self.m)
+        pc2.pc2_quantize(self.ctx, self.k, self.o, self.delta, self.xu.reshape(-1), self.m)
         pc2.pc2_encrypt(self.sk.public, self.m.view(torch.int32).reshape(K * N, 2), self.r, self.c)
         pc2.pc2_hom_sum(self.sk.public, self.parts, self.agg)
         pc2.pc2_decrypt(self.sk, self.agg, self.msum)

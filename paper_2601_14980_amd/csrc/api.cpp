@@ -822,12 +822,12 @@ int pc2_quantize(pc2_ctx* ctx, const pc2_qparams* q, const double* x, uint64_t* 
   if (count == 0) return PC2_OK;
   if (!x || !m) return PC2_E_INVAL;
   if (partial_overlap(x, 8 * count, m, 8 * count)) return PC2_E_INVAL;
-  if (q->log2_scale < -1074 || q->log2_scale > 1023) return PC2_E_INVAL;
+  if (q->log2_scale < -1074 || q->log2_scale > 1023 || q->offset > q->delta) return PC2_E_INVAL;
   pc2k::Launch l{};
   l.grid = (int)std::min<size_t>((count + 255) / 256, (size_t)ctx->cus * 8);
   l.err = ctx->err;
   l.stream = stream;
-  return status_of(pc2k::launch_quantize(l, q->log2_scale, q->offset, x, m, count));
+  return status_of(pc2k::launch_quantize(l, q->log2_scale, q->offset, q->delta, x, m, count));
 }
 
 int pc2_dequantize(pc2_ctx* ctx, const pc2_qparams* q, const uint32_t* m, uint32_t m_limbs,

@@ -10,28 +10,25 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_quantize(int log2_scale, uint64_t offset,
+// x must lie in the common interval [-o, delta - o) / 2^k.  t = x 2^k is
+// exact, and for the integer bounds -o <= t < hi (hi = delta - o) holds
+// exactly when it holds for floor(t); then rint(t) <= floor(t) + 1 <= hi, so
+// m = o + rint(t) lies in {0, ..., delta}.
+__global__ __launch_bounds__(256) void k_quantize(int log2_scale, uint64_t offset, uint64_t hi,
                                                   const double* __restrict__ x,
                                                   uint64_t* __restrict__ m, size_t count,
                                                   int* err) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   bool bad = false;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-    double v = rint(ldexp(x[i], log2_scale));  // one rounding, half to even
+    const double t = ldexp(x[i], log2_scale);
+    const double f = floor(t);
+    const double v = rint(t);  // one rounding, half to even
+    bool ok = fabs(f) < 18446744073709551616.0;  // false for NaN and infinities
+    if (ok) ok = f >= 0.0 ? (uint64_t)f < hi : (uint64_t)(-f) <= offset;
     uint64_t out = 0;
-    // v is integer-valued; the result offset + v must lie in [0, 2^64)
-    bool ok = fabs(v) < 18446744073709551616.0;  // false for NaN and infinities
-    if (ok) {
-      if (v >= 0.0) {
-        out = offset + (uint64_t)v;
-        ok = out >= offset;  // no wrap past 2^64
-      } else {
-        uint64_t mag = (uint64_t)(-v);
-        ok = offset >= mag;
-        out = offset - mag;
-      }
-    }
-    m[i] = ok ? out : 0u;
+    if (ok) out = v >= 0.0 ? offset + (uint64_t)v : offset - (uint64_t)(-v);
+    m[i] = out;
     bad |= !ok;
   }
   if (bad) atomicOr(err, pc2k::ERR_RANGE);
@@ -64,10 +61,10 @@ __global__ __launch_bounds__(256) void k_dequantize(int log2_scale, uint64_t off
 
 namespace pc2k {
 
-hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, const double* x,
-                           uint64_t* m, size_t count) {
+hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, uint64_t delta,
+                           const double* x, uint64_t* m, size_t count) {
   hipLaunchKernelGGL(k_quantize, dim3(l.grid), dim3(256), 0, (hipStream_t)l.stream, log2_scale,
-                     offset, x, m, count, l.err);
+                     offset, delta - offset, x, m, count, l.err);
   return hipGetLastError();
 }
 

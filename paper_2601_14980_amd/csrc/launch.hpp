@@ -97,8 +97,8 @@ hipError_t admm_local(const double* A, const double* Lchol, const double* aty, c
 hipError_t admm_consensus(const double* sum, const double* x, int N, int K, double kappa,
                           double* z, double* u, void* stream);
 
-hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, const double* x,
-                           uint64_t* m, size_t count);
+hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, uint64_t delta,
+                           const double* x, uint64_t* m, size_t count);
 hipError_t launch_dequantize(const Launch& l, int log2_scale, uint64_t offset, const uint32_t* m,
                              int m_limbs, uint64_t weight, double* x, size_t count);
 

@@ -67,7 +67,7 @@ class PC2Error(RuntimeError):
 
 
 class pc2_qparams(ctypes.Structure):
-    _fields_ = [("log2_scale", c_int32), ("offset", c_uint64)]
+    _fields_ = [("log2_scale", c_int32), ("offset", c_uint64), ("delta", c_uint64)]
 
 
 class pc2_job(ctypes.Structure):
@@ -281,12 +281,13 @@ def _rows(t: torch.Tensor, width: int, what: str) -> int:
     return t.shape[0]
 
 
-def pc2_quantize(ctx: Context, log2_scale: int, offset: int, x: torch.Tensor,
+def pc2_quantize(ctx: Context, log2_scale: int, offset: int, delta: int, x: torch.Tensor,
                  m: torch.Tensor, stream=None) -> None:
-    """m (int64 bit patterns of uint64) <- rint(x 2^k) + offset."""
+    """m (int64 bit patterns of uint64) <- rint(x 2^k) + offset for x in the
+    common interval [-offset, delta - offset) / 2^k."""
     if x.shape != m.shape or x.dim() != 1:
         raise ValueError("x and m must be 1-D tensors of equal length")
-    q = pc2_qparams(log2_scale, offset)
+    q = pc2_qparams(log2_scale, offset, delta)
     _check(lib.pc2_quantize(ctx.handle, byref(q), _dev_ptr(x, torch.float64, "x"),
                             _dev_ptr(m, torch.int64, "m"), x.numel(), _stream(stream)),
            "pc2_quantize")
@@ -298,7 +299,7 @@ def pc2_dequantize(ctx: Context, log2_scale: int, offset: int, m: torch.Tensor, 
     count = m.shape[0]
     if m.dim() != 2 or x.shape != (count,):
         raise ValueError("m must be [count, m_limbs] and x [count]")
-    q = pc2_qparams(log2_scale, offset)
+    q = pc2_qparams(log2_scale, offset, offset)  # delta is not read by dequantize
     _check(lib.pc2_dequantize(ctx.handle, byref(q), _dev_ptr(m, torch.int32, "m"), m.shape[1],
                               weight, _dev_ptr(x, torch.float64, "x"), count, _stream(stream)),
            "pc2_dequantize")

@@ -49,7 +49,7 @@ def test_strerror(pc2):
 def test_null_arguments_rejected(pc2):
     lib = pc2.lib
     INVAL = pc2.PC2_E_INVAL
-    q = pc2.pc2_qparams(20, 1 << 23)
+    q = pc2.pc2_qparams(20, 1 << 23, 1 << 24)
     assert lib.pc2_ctx_create(0, None) == INVAL
     assert lib.pc2_ctx_destroy(None) == INVAL
     assert lib.pc2_ctx_sync(None, None) == INVAL

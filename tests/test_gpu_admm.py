@@ -27,12 +27,12 @@ def test_encrypted_admm_matches_oracle(gpu_ctx, M, N, K, iters):
     y = A @ xs + 1e-3 * rng.standard_normal(M)
     rho = 1.0
     lam = 0.1 * float(np.max(np.abs(A.T @ y)))
-    k, o = gen.Q_ADMM.log2_scale, gen.Q_ADMM.offset
+    k, o, dl = gen.Q_ADMM.log2_scale, gen.Q_ADMM.offset, gen.Q_ADMM.delta
     p, q = gen.primes_for(4, 256)
     sk = pc2.SecretKey(gpu_ctx, 256, p, q)
     r_pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, K * N, sk.L, 4))
     drv = EncryptedConsensusLasso(gpu_ctx, sk, torch.from_numpy(A).cuda(),
-                                  torch.from_numpy(y).cuda(), K, rho, lam, k, o, r_pool)
+                                  torch.from_numpy(y).cuda(), K, rho, lam, k, o, dl, r_pool)
     ora = ConsensusLasso(A, y, K, rho, lam)
     z = torch.zeros(N, dtype=torch.float64, device="cuda")
     u = torch.zeros((K, N), dtype=torch.float64, device="cuda")

@@ -66,9 +66,9 @@ def test_quantize_dequantize_in_place(gpu_ctx):
     qp = gen.Q_PLAIN
     x = torch.from_numpy(np.random.default_rng(3).standard_normal(COUNT)).cuda()
     ref = torch.empty(COUNT, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, x, ref)
+    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, qp.delta, x, ref)
     buf = x.clone()
-    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, buf, buf.view(torch.int64))
+    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, qp.delta, buf, buf.view(torch.int64))
     assert gpu_ctx.sync() == 0
     assert torch.equal(buf.view(torch.int64), ref)
     back = torch.empty(COUNT, dtype=torch.float64, device="cuda")

@@ -46,7 +46,7 @@ def test_full_size_encrypt_aggregate_decrypt(gpu_ctx, nbits, nodes, length, seed
     rs = np.concatenate([gen.gen_r_limbs(n, length, L, seed, extra=k) for k in range(nodes)])
     total = nodes * length
     m = torch.empty(total, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, torch.from_numpy(np.concatenate(xs)).cuda(),
+    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, qp.delta, torch.from_numpy(np.concatenate(xs)).cuda(),
                      m)
     c = torch.empty((total, 2 * L), dtype=torch.int32, device="cuda")
     pc2.pc2_encrypt(sk.public, m.view(torch.int32).reshape(total, 2), pc2.to_device_limbs(rs), c)
@@ -63,7 +63,7 @@ def test_full_size_encrypt_aggregate_decrypt(gpu_ctx, nbits, nodes, length, seed
     rng = np.random.default_rng(nbits)
     for node, j in zip(rng.integers(0, nodes, 3), rng.integers(0, length, 3)):
         e = int(node) * length + int(j)
-        mv = Q.quantize(float(xs[node][j]), qp.log2_scale, qp.offset)
+        mv = Q.quantize(float(xs[node][j]), qp.log2_scale, qp.offset, qp.delta)
         assert int(mq[node, j]) == mv
         r = int(ints_from_limbs(rs[e:e + 1])[0])
         want = O.encrypt(opk, mv, r)
@@ -96,7 +96,7 @@ def test_full_size_batches(gpu_ctx):
     for i, Ln in enumerate(lengths):
         k = keys[i % 2]
         m = torch.empty(Ln, dtype=torch.int64, device="cuda")
-        pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, torch.from_numpy(xs[i]).cuda(), m)
+        pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, qp.delta, torch.from_numpy(xs[i]).cuda(), m)
         rl = gen.gen_r_limbs(k["n"], Ln, k["sk"].L, seed, extra=i)
         nodes.append(dict(k=k, L=Ln, m=m, rl=rl, r=pc2.to_device_limbs(rl),
                           c=torch.empty((Ln, 2 * k["sk"].L), dtype=torch.int32, device="cuda")))
@@ -154,7 +154,7 @@ def test_full_size_serving(gpu_ctx):
     L = sk.L
     qp = gen.Q_PLAIN
     m = torch.empty(PL, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset,
+    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, qp.delta,
                      torch.from_numpy(gen.normal_vectors(seed, [PL])[0]).cuda(), m)
     m2 = m.view(torch.int32).reshape(PL, 2)
     rl = gen.gen_r_limbs(n, PL, L, seed)

@@ -181,13 +181,13 @@ def test_quantize_dequantize(gpu_ctx):
     rng = np.random.default_rng(5)
     x = rng.standard_normal(10000)
     x[:8] = [0.5 / 2**20, 1.5 / 2**20, -0.5 / 2**20, -2.5 / 2**20, 7.999, -8.0, 0.0, -0.0]
-    k, o = 20, 1 << 23
+    k, o, dl = 20, 1 << 23, 1 << 24
     xt = torch.from_numpy(x).cuda()
     mt = torch.zeros(x.shape, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(gpu_ctx, k, o, xt, mt)
+    pc2.pc2_quantize(gpu_ctx, k, o, dl, xt, mt)
     assert gpu_ctx.sync() == 0
     m = mt.cpu().numpy().view(np.uint64)
-    assert [int(v) for v in m] == Q.quantize_vec(x, k, o)
+    assert [int(v) for v in m] == Q.quantize_vec(x, k, o, dl)
     # dequantize sums of W addends
     W = 8
     Ms = [int(v) * W + 12345 for v in m[:1000]]
@@ -202,10 +202,25 @@ def test_quantize_dequantize(gpu_ctx):
 
 def test_quantize_range_errors(gpu_ctx):
     from paper_2601_14980_amd import pc2
-    x = np.array([1.0, np.nan, np.inf, -20.0, 1e30])
+    k, o, dl = 20, 1 << 23, 1 << 24  # the common interval [-8, 8)
+    inside = [1.0, -8.0, np.nextafter(8.0, 0.0), -8.0 + 2.0 ** -21, 7.5 + 2.0 ** -21]
+    outside = [np.nan, np.inf, -np.inf, -20.0, 1e30, 8.0, np.nextafter(-8.0, -9.0),
+               -8.0 - 2.0 ** -21]  # the last rounds to -8 * 2^20, i.e. m = 0, yet lies below z_min
+    x = np.array(inside + outside)
     xt = torch.from_numpy(x).cuda()
     mt = torch.zeros(x.shape, dtype=torch.int64, device="cuda")
-    pc2.pc2_quantize(gpu_ctx, 20, 1 << 23, xt, mt)
+    pc2.pc2_quantize(gpu_ctx, k, o, dl, xt, mt)
     assert gpu_ctx.sync() == -2
     m = [int(v) for v in mt.cpu().numpy().view(np.uint64)]
-    assert m == [Q.quantize(1.0, 20, 1 << 23), 0, 0, 0, 0]
+    want = Q.quantize_vec(inside, k, o, dl)
+    assert want[1:3] == [0, dl]
+    assert m == want + [0] * len(outside)
+    for x_bad in outside:
+        with pytest.raises(ValueError):
+            Q.quantize(float(x_bad), k, o, dl)
+    # a full-interval call with no error latches nothing
+    pc2.pc2_quantize(gpu_ctx, k, o, dl, torch.from_numpy(np.array(inside)).cuda(), mt[:5])
+    assert gpu_ctx.sync() == 0
+    # offset above delta is an argument error, reported at once
+    with pytest.raises(pc2.PC2Error):
+        pc2.pc2_quantize(gpu_ctx, k, dl + 1, dl, xt, mt)

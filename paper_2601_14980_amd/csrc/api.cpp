@@ -19,8 +19,11 @@ struct pc2_ctx {
   int device = 0;
   int cus = 0;
   int* err = nullptr;          // device word, latched error bits
-  uint32_t* scratch = nullptr; // per-tile tables
-  size_t scratch_bytes = 0;
+  uint32_t* scratch = nullptr; // per-tile tables and per-call staging
+  size_t scratch_bytes = 0;    // sized by the key constructors and pc2_ctx_reserve
+  hipEvent_t done = nullptr;   // recorded after the last call that used the scratch
+  void* done_stream = nullptr; // ... on this stream
+  bool done_valid = false;
   int window = 0;              // 0 = automatic
   int modmul = PC2_MODMUL_VALU;
   int tile = 0;                // PC2_OPT_TILE: 0 automatic, 1 wide, else lanes per ciphertext
@@ -491,13 +494,13 @@ int occupancy(pc2_ctx* ctx, int geo, int op) {
   return o;
 }
 
-// grid + scratch for a Paillier launch over `count` elements in geometry
-// geo (the key class, except for an encryption in an alternative tile).  The scratch
-// holds aux_words of per-call staging first (Launch::aux, at the same place
-// for every launch that asks for the same amount), then the tables.
-int prepare(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, pc2k::Launch* l,
-            void* stream, size_t aux_words = 0) {
-  const int w = window_for(ctx, geo, op);
+// Grid and table slot of a Paillier launch over `count` elements in geometry
+// geo (the key class, except for an encryption in an alternative tile) with
+// window w; returns the bytes of scratch the launch needs.  The scratch holds
+// aux_words of per-call staging first (Launch::aux, at the same place for
+// every launch that asks for the same amount), then the tables.
+size_t plan_launch(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, int w,
+                   pc2k::Launch* l, void* stream, size_t aux_words) {
   const size_t epb = op == pc2k::OP_ENC_MFMA ? 1 : (size_t)pc2k::elems_per_block(geo);
   const size_t groups = (count + epb - 1) / epb;
   const size_t cap = (size_t)ctx->cus * occupancy(ctx, geo, op);
@@ -516,18 +519,98 @@ int prepare(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, pc2k::La
   words = (words + 3) & ~(size_t)3;
   l->slot_words = words;
   const size_t aux = (aux_words + 63) & ~(size_t)63;
-  const size_t need = (aux + (size_t)l->grid * tiles * words) * 4;
-  if (need > ctx->scratch_bytes) {
-    // growing the scratch: wait for in-flight work that may use the old one
-    if (hipDeviceSynchronize() != hipSuccess) return PC2_E_DEVICE;
-    if (ctx->scratch) (void)hipFree(ctx->scratch);
-    ctx->scratch = nullptr;
-    ctx->scratch_bytes = 0;
-    if (hipMalloc(&ctx->scratch, need) != hipSuccess) return PC2_E_NOMEM;
-    ctx->scratch_bytes = need;
-  }
+  return (aux + (size_t)l->grid * tiles * words) * 4;
+}
+
+// A data call's launch in the context's scratch.  Data calls never allocate:
+// the key constructors sized the scratch for every call of their key class
+// (class_scratch_need), so a launch that does not fit is PC2_E_NOMEM.
+int prepare(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, pc2k::Launch* l,
+            void* stream, size_t aux_words = 0) {
+  const size_t need = plan_launch(ctx, geo, op, count, Ls, L, window_for(ctx, geo, op), l,
+                                  stream, aux_words);
+  if (need > ctx->scratch_bytes || !ctx->scratch) return PC2_E_NOMEM;
+  const size_t aux = (aux_words + 63) & ~(size_t)63;
   l->aux = aux_words ? ctx->scratch : nullptr;
   l->scratch = ctx->scratch + aux;
+  return PC2_OK;
+}
+
+// Largest scratch any data call under a key of class cls can need: every
+// operation and encryption tile, the widest window an option can select,
+// a device-filling grid and the largest per-call staging (DEC_CHUNK
+// elements).  L: limbs of n; Ls, nl2: limbs of the larger prime and of its
+// square.  Also caches every occupancy the calls will look up, so that no
+// data call queries the runtime for it (e.g. under graph capture).
+size_t class_scratch_need(pc2_ctx* ctx, int cls, int L, int Ls, int nl2) {
+  const size_t big = (size_t)1 << 40;  // enough elements to fill the device
+  const size_t ch = pc2k::DEC_CHUNK;
+  const int w = pc2k::SCHED_WMAX;
+  pc2k::Launch l{};
+  size_t need = 0;
+  auto take = [&](int geo, int op, size_t aux) {
+    need = std::max(need, plan_launch(ctx, geo, op, big, Ls, L, w, &l, nullptr, aux));
+  };
+  take(cls, pc2k::OP_ENC, 0);
+  if (pc2k::ALT_GEO[cls] >= 0) take(pc2k::ALT_GEO[cls], pc2k::OP_ENC, 0);
+  take(cls, pc2k::OP_SMUL, 0);
+  take(cls, pc2k::OP_ENC_MFMA, 0);
+  take(cls, pc2k::OP_DEC, ch * 2 * (size_t)(Ls + 1));
+  const size_t fused_aux = ch * 2 * (size_t)L + ch * 2 * (size_t)(Ls + 1);
+  take(cls, pc2k::OP_DEC, fused_aux);
+  take(cls, pc2k::OP_FUSED, fused_aux);
+  take(cls, pc2k::OP_ENC_CRT, ch * 2 * (size_t)(nl2 + 1));
+  (void)occupancy(ctx, cls, pc2k::OP_SUM);
+  return need;
+}
+
+// Grow the context's scratch to `need` bytes.  Only the key constructors and
+// pc2_ctx_reserve call this (never a data call): it waits for the device,
+// since work in flight may still use the old buffer.
+int grow_scratch(pc2_ctx* ctx, size_t need) {
+  if (need <= ctx->scratch_bytes && ctx->scratch) return PC2_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  if (hipDeviceSynchronize() != hipSuccess) return PC2_E_DEVICE;
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  ctx->scratch = nullptr;
+  ctx->scratch_bytes = 0;
+  ctx->done_valid = false;
+  if (hipMalloc(&ctx->scratch, need) != hipSuccess) return PC2_E_NOMEM;
+  ctx->scratch_bytes = need;
+  return PC2_OK;
+}
+
+// Bounds on a private key's prime sizes in class cls: a prime s must satisfy
+// 4 s^2 < R of the class's s^2 digit geometry.
+void class_prime_limbs(int cls, int* Ls, int* nl2) {
+  const pc2k::ClassGeo g = pc2k::CLASS_GEO[cls];
+  const int p2bits = g.pD * g.pK * g.pT - 2;
+  *nl2 = (p2bits + 31) / 32;
+  *Ls = (p2bits / 2 + 31) / 32;
+}
+
+bool capturing(void* stream) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing((hipStream_t)stream, &st) == hipSuccess &&
+         st != hipStreamCaptureStatusNone;
+}
+
+// Calls that use the context's scratch run one after another whatever their
+// streams: a call on a stream other than the previous call's first makes its
+// stream wait for that call's completion event (on the device; the host does
+// not block), and records the event after its own launches.  Under graph
+// capture neither happens: the caller orders a graph's replays against other
+// calls on the context.
+int scratch_begin(pc2_ctx* ctx, void* stream) {
+  if (!ctx->done_valid || ctx->done_stream == stream || capturing(stream)) return PC2_OK;
+  return hipStreamWaitEvent((hipStream_t)stream, ctx->done, 0) == hipSuccess ? PC2_OK
+                                                                            : PC2_E_DEVICE;
+}
+int scratch_end(pc2_ctx* ctx, void* stream, int rc) {
+  if (rc || capturing(stream)) return rc;
+  if (hipEventRecord(ctx->done, (hipStream_t)stream) != hipSuccess) return PC2_E_DEVICE;
+  ctx->done_stream = stream;
+  ctx->done_valid = true;
   return PC2_OK;
 }
 
@@ -594,7 +677,8 @@ int pc2_ctx_create(int hip_device, pc2_ctx** out) {
     delete c;
     return PC2_E_NOMEM;
   }
-  if (hipMemset(c->err, 0, sizeof(int)) != hipSuccess) {
+  if (hipMemset(c->err, 0, sizeof(int)) != hipSuccess ||
+      hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess) {
     (void)hipFree(c->err);
     delete c;
     return PC2_E_DEVICE;
@@ -609,6 +693,7 @@ int pc2_ctx_destroy(pc2_ctx* ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   if (ctx->err) (void)hipFree(ctx->err);
+  if (ctx->done) (void)hipEventDestroy(ctx->done);
   delete ctx;
   return PC2_OK;
 }
@@ -632,20 +717,11 @@ int pc2_ctx_sync(pc2_ctx* ctx, void* hip_stream) {
 int pc2_ctx_reserve(pc2_ctx* ctx, uint32_t max_nbits) {
   if (!ctx) return PC2_E_INVAL;
   const int cls = pc2k::class_for_bits((int)max_nbits);
-  if (cls < 0) return PC2_E_UNSUPPORTED;
-  const int L = (int)((max_nbits + 31) / 32);
-  const int Ls = (L + 1) / 2 + 1;
-  pc2k::Launch l{};
-  const size_t big = (size_t)1 << 40;  // enough elements to fill the device
-  for (int op : {pc2k::OP_ENC, pc2k::OP_DEC, pc2k::OP_SMUL, pc2k::OP_FUSED}) {
-    int rc = prepare(ctx, cls, op, big, Ls, L, &l, nullptr);
-    if (rc) return rc;
-  }
-  if (pc2k::ALT_GEO[cls] >= 0) {
-    int rc = prepare(ctx, pc2k::ALT_GEO[cls], pc2k::OP_ENC, big, Ls, L, &l, nullptr);
-    if (rc) return rc;
-  }
-  return PC2_OK;
+  if (max_nbits < 2 || cls < 0) return PC2_E_UNSUPPORTED;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  int Ls = 0, nl2 = 0;
+  class_prime_limbs(cls, &Ls, &nl2);
+  return grow_scratch(ctx, class_scratch_need(ctx, cls, (int)((max_nbits + 31) / 32), Ls, nl2));
 }
 
 int pc2_ctx_set_option(pc2_ctx* ctx, int option, int64_t value) {
@@ -706,6 +782,12 @@ int pc2_pk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* n_limbs, pc2_pk*
   pk->cls = cls;
   pk->c = pk_const((const uint32_t*)pk->dev, o, L, nb);
   if (pc2k::ALT_GEO[cls] >= 0) pk->alt = pk_const_alt((const uint32_t*)pk->dev, o, pk->c);
+  rc = pc2_ctx_reserve(ctx, nbits);  // every later data call under this key fits
+  if (rc) {
+    (void)hipFree(pk->dev);
+    delete pk;
+    return rc;
+  }
   *out = pk;
   return PC2_OK;
 }
@@ -776,6 +858,12 @@ int pc2_sk_create(pc2_ctx* ctx, uint32_t nbits, const uint32_t* p_limbs, const u
   sk->crt_ok = crt_ok;
   Limbs pm1 = pc2h::sub(p, Limbs{1}), qm1 = pc2h::sub(q, Limbs{1});
   sk->c.ebits = std::max(pc2h::bitlen(pm1), pc2h::bitlen(qm1));
+  rc = pc2_ctx_reserve(ctx, nbits);  // every later data call under this key fits
+  if (rc) {
+    (void)hipFree(sk->dev);
+    delete sk;
+    return rc;
+  }
   *out = sk;
   return PC2_OK;
 }
@@ -854,18 +942,21 @@ int pc2_encrypt(const pc2_pk* pk, const uint32_t* m, uint32_t m_limbs, const uin
   if (partial_overlap(c, cb, m, 4 * (size_t)m_limbs * count) ||
       partial_overlap(c, cb, r, 4 * (size_t)pk->L * count))
     return PC2_E_INVAL;
+  pc2_ctx* ctx = pk->ctx;
   pc2k::Launch l{};
-  if (pk->ctx->modmul == PC2_MODMUL_MFMA) {
-    int rc = prepare(pk->ctx, pk->cls, pc2k::OP_ENC_MFMA, count, 0, pk->L, &l, stream);
+  if (ctx->modmul == PC2_MODMUL_MFMA) {
+    int rc = prepare(ctx, pk->cls, pc2k::OP_ENC_MFMA, count, 0, pk->L, &l, stream);
+    if (!rc) rc = scratch_begin(ctx, stream);
     if (rc) return rc;
-    return status_of(
-        pc2k::launch_encrypt_mfma(pk->cls, l, pk->c, m, (int)m_limbs, r, c, count));
+    return scratch_end(ctx, stream, status_of(pc2k::launch_encrypt_mfma(
+                                        pk->cls, l, pk->c, m, (int)m_limbs, r, c, count)));
   }
-  const int geo = enc_geo(pk->ctx, pk->cls, count);
-  int rc = prepare(pk->ctx, geo, pc2k::OP_ENC, count, 0, pk->L, &l, stream);
+  const int geo = enc_geo(ctx, pk->cls, count);
+  int rc = prepare(ctx, geo, pc2k::OP_ENC, count, 0, pk->L, &l, stream);
+  if (!rc) rc = scratch_begin(ctx, stream);
   if (rc) return rc;
-  return status_of(
-      pc2k::launch_encrypt(geo, l, geo_const(pk, geo), m, (int)m_limbs, r, c, count));
+  return scratch_end(ctx, stream, status_of(pc2k::launch_encrypt(
+                                      geo, l, geo_const(pk, geo), m, (int)m_limbs, r, c, count)));
 }
 
 int pc2_decrypt(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count, void* stream) {
@@ -881,15 +972,15 @@ int pc2_decrypt(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count, 
   pc2k::Launch l{};
   int rc = prepare(sk->ctx, sk->pk.cls, pc2k::OP_DEC, chunk, Ls, sk->pk.L, &l, stream,
                    chunk * 2 * (size_t)(Ls + 1));
+  if (!rc) rc = scratch_begin(sk->ctx, stream);
   if (rc) return rc;
   const size_t L2 = 2 * (size_t)sk->pk.L;
-  for (size_t b = 0; b < count; b += chunk) {
+  for (size_t b = 0; b < count && !rc; b += chunk) {
     const size_t n = std::min(chunk, count - b);
     rc = status_of(pc2k::launch_decrypt(sk->pk.cls, l, sk->c, c + b * L2, m + b * sk->pk.L, n,
                                         l.aux));
-    if (rc) return rc;
   }
-  return PC2_OK;
+  return scratch_end(sk->ctx, stream, rc);
 }
 
 int pc2_encrypt_sk(const pc2_sk* sk, const uint32_t* m, uint32_t m_limbs, const uint32_t* r,
@@ -910,14 +1001,14 @@ int pc2_encrypt_sk(const pc2_sk* sk, const uint32_t* m, uint32_t m_limbs, const 
   pc2k::Launch l{};
   int rc = prepare(sk->ctx, cls, pc2k::OP_ENC_CRT, chunk, sk->c.h[0].Ls, L, &l, stream,
                    chunk * 2 * (size_t)(nl2 + 1));
+  if (!rc) rc = scratch_begin(sk->ctx, stream);
   if (rc) return rc;
-  for (size_t b = 0; b < count; b += chunk) {
+  for (size_t b = 0; b < count && !rc; b += chunk) {
     const size_t n = std::min(chunk, count - b);
     rc = status_of(pc2k::launch_encrypt_crt(cls, l, sk->c, m + b * m_limbs, (int)m_limbs,
                                             r + b * (size_t)L, c + b * 2 * (size_t)L, n, l.aux));
-    if (rc) return rc;
   }
-  return PC2_OK;
+  return scratch_end(sk->ctx, stream, rc);
 }
 
 int pc2_hom_sum(const pc2_pk* pk, const uint32_t* const* c_k, uint32_t K, uint32_t* out,
@@ -963,9 +1054,10 @@ int pc2_hom_scalar_mul(const pc2_pk* pk, const uint32_t* c, const uint64_t* k, u
   }
   pc2k::Launch l{};
   int rc = prepare(pk->ctx, pk->cls, pc2k::OP_SMUL, count, 0, pk->L, &l, stream);
+  if (!rc) rc = scratch_begin(pk->ctx, stream);
   if (rc) return rc;
-  return status_of(
-      pc2k::launch_scalar_mul(pk->cls, l, pk->c, c, (const uint32_t*)k, out, count));
+  return scratch_end(pk->ctx, stream, status_of(pc2k::launch_scalar_mul(
+                                          pk->cls, l, pk->c, c, (const uint32_t*)k, out, count)));
 }
 
 int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t* const* r_k,
@@ -995,12 +1087,11 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
   pc2k::Launch le{}, ld{};
   int rc = prepare(ctx, cls, pc2k::OP_DEC, chunk, Ls, L, &ld, stream, aux);
   if (!rc) rc = prepare(ctx, cls, pc2k::OP_FUSED, chunk, Ls, L, &le, stream, aux);
-  if (!rc && ld.aux != le.aux)  // the second call grew the scratch
-    rc = prepare(ctx, cls, pc2k::OP_DEC, chunk, Ls, L, &ld, stream, aux);
+  if (!rc) rc = scratch_begin(ctx, stream);
   if (rc) return rc;
   uint32_t* prod = le.aux;
   uint32_t* halves = le.aux + prod_words;
-  for (size_t b = 0; b < count; b += chunk) {
+  for (size_t b = 0; b < count && !rc; b += chunk) {
     const size_t n = std::min(chunk, count - b);
     pc2k::PtrList mb{}, rb{};
     for (uint32_t k = 0; k < K; ++k) {
@@ -1011,9 +1102,8 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
         pc2k::launch_enc_prod(cls, le, sk->pk.c, mb, rb, (int)K, (int)m_limbs, prod, n));
     if (!rc)
       rc = status_of(pc2k::launch_decrypt(cls, ld, sk->c, prod, m_out + b * L, n, halves));
-    if (rc) return rc;
   }
-  return PC2_OK;
+  return scratch_end(ctx, stream, rc);
 }
 
 // ---------------------------------------------------------------- batches
@@ -1531,6 +1621,30 @@ int resident_groups(pc2_ctx* ctx, const void* k) {
     occ = 1;
   return ctx->cus * occ;
 }
+// Column chunks of a mat-vec of `rows` rows: the count (up to the aggregation
+// limit and max_chunks) whose whole wavefront groups fill the resident
+// capacity best; fewer on a near tie.
+void pick_chunks(const pc2_matvec* mv, size_t rows, size_t max_chunks, size_t* nch,
+                 size_t* chunk_cols) {
+  const size_t epw = (size_t)pc2k::elems_per_block(mv->pk->cls);
+  const size_t gpc = (rows + epw - 1) / epw;
+  const size_t cap = (size_t)mv->cap_apply;
+  *nch = 1;
+  *chunk_cols = mv->cols;
+  double best = -1;
+  const size_t top = std::min(std::min(mv->cols, (size_t)pc2k::RK_MAX), std::max<size_t>(1, max_chunks));
+  for (size_t c = 1; c <= top; ++c) {
+    const size_t cc = (mv->cols + c - 1) / c;
+    if ((mv->cols + cc - 1) / cc != c) continue;  // the same split as a smaller count
+    const size_t groups = gpc * c;
+    const double eff = (double)groups / (double)(((groups + cap - 1) / cap) * cap);
+    if (eff > best + 0.02) {
+      best = eff;
+      *nch = c;
+      *chunk_cols = cc;
+    }
+  }
+}
 }  // namespace
 
 int pc2_matvec_create(const pc2_pk* pk, size_t cols, uint32_t ebits, uint32_t window,
@@ -1573,6 +1687,21 @@ int pc2_matvec_create(const pc2_pk* pk, size_t cols, uint32_t ebits, uint32_t wi
   }
   mv->cap_table = resident_groups(ctx, pc2k::kernel_matvec(pk->cls, 0));
   mv->cap_apply = resident_groups(ctx, pc2k::kernel_matvec(pk->cls, 1));
+  // staging for the partial products of rows_hint rows split over column
+  // chunks (pc2_matvec_apply allocates nothing)
+  if (rows_hint) {
+    size_t nch = 1, cc = 0;
+    pick_chunks(mv, rows_hint, (size_t)pc2k::RK_MAX, &nch, &cc);
+    if (nch > 1) {
+      mv->parts_bytes = nch * rows_hint * 8 * (size_t)pk->L;
+      if (hipMalloc(&mv->parts, mv->parts_bytes) != hipSuccess) {
+        (void)hipFree(mv->tab);
+        delete mv;
+        return PC2_E_NOMEM;
+      }
+    }
+  }
+  (void)occupancy(ctx, pk->cls, pc2k::OP_SUM);
   *out = mv;
   return PC2_OK;
 }
@@ -1611,40 +1740,18 @@ int pc2_matvec_apply(pc2_matvec* mv, const uint64_t* B, const uint32_t* alpha, u
     if (a0 < o0 + rows * row_bytes && o0 < a0 + rows * row_bytes) return PC2_E_INVAL;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
-  // column chunks: the count (up to the aggregation limit) whose whole
-  // wavefront groups fill the resident capacity best; fewer on a near tie
+  // column chunks, as many as the plan's staging holds for this many rows
   const size_t epw = (size_t)pc2k::elems_per_block(cls);
   const size_t gpc = (rows + epw - 1) / epw;
   const size_t cap = (size_t)mv->cap_apply;
   size_t nch = 1, chunk_cols = mv->cols;
-  double best = -1;
-  for (size_t c = 1; c <= std::min(mv->cols, (size_t)pc2k::RK_MAX); ++c) {
-    const size_t cc = (mv->cols + c - 1) / c;
-    if ((mv->cols + cc - 1) / cc != c) continue;  // the same split as a smaller count
-    const size_t groups = gpc * c;
-    const double eff = (double)groups / (double)(((groups + cap - 1) / cap) * cap);
-    if (eff > best + 0.02) {
-      best = eff;
-      nch = c;
-      chunk_cols = cc;
-    }
-  }
+  pick_chunks(mv, rows, mv->parts_bytes / (rows * row_bytes), &nch, &chunk_cols);
   const size_t groups = gpc * nch;
   const int grid = (int)std::max<size_t>(1, std::min(groups, cap));
   if (nch == 1)
     return status_of(pc2k::launch_mv_apply(cls, grid, pk->c, B, rows, mv->cols, mv->ebits,
                                            mv->nw, mv->w, mv->tab, alpha, 1, chunk_cols, out,
                                            0, ctx->err, hip_stream));
-  const size_t need = nch * rows * row_bytes;
-  if (need > mv->parts_bytes) {
-    // growing the staging: wait for in-flight work that may use the old one
-    if (hipDeviceSynchronize() != hipSuccess) return PC2_E_DEVICE;
-    if (mv->parts) (void)hipFree(mv->parts);
-    mv->parts = nullptr;
-    mv->parts_bytes = 0;
-    if (hipMalloc(&mv->parts, need) != hipSuccess) return PC2_E_NOMEM;
-    mv->parts_bytes = need;
-  }
   int rc = status_of(pc2k::launch_mv_apply(cls, grid, pk->c, B, rows, mv->cols, mv->ebits,
                                            mv->nw, mv->w, mv->tab, alpha, nch, chunk_cols,
                                            mv->parts, rows * L2, ctx->err, hip_stream));

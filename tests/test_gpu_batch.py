@@ -108,6 +108,64 @@ def test_batch_ragged_sum_and_decrypt(gpu_ctx, setup):
     bd.close()
 
 
+def test_batch_sum_and_decrypt_graph_replays(gpu_ctx, setup):
+    """The ragged aggregation batch and the two-launch decryption batch (queue
+    reset, per-prime items, recombination) on a non-null stream: the first run
+    captures each in a HIP graph, the next two replay it; with the program's
+    own eager work between runs, every run equals the null-stream run, which
+    equals the oracle on sampled elements and the plaintext sums on all."""
+    from paper_2601_14980_amd import pc2
+    nodes = setup["nodes"]
+    for nd in nodes:
+        pc2.pc2_encrypt(nd["key"]["sk"].public, nd["m"], nd["r"], nd["c"])
+    assert gpu_ctx.sync() == 0
+    groups = []
+    for g, k in enumerate(setup["keys"]):
+        members = [nd for i, nd in enumerate(nodes) if i % 2 == g]
+        maxlen = max(len(nd["ms"]) for nd in members)
+        groups.append(dict(key=k, members=members, maxlen=maxlen,
+                           agg=torch.zeros((maxlen, 2 * k["sk"].L), dtype=torch.int32,
+                                           device="cuda"),
+                           dec=torch.zeros((maxlen, k["sk"].L), dtype=torch.int32,
+                                           device="cuda")))
+    bs = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_HOM_SUM, pk=g["key"]["sk"].public,
+                                  inputs=[nd["c"] for nd in g["members"]],
+                                  lengths=[len(nd["ms"]) for nd in g["members"]], out=g["agg"])
+                             for g in groups])
+    bd = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_DECRYPT, sk=g["key"]["sk"], c=g["agg"],
+                                  out=g["dec"]) for g in groups])
+    bs.run(0)
+    bd.run(0)
+    assert gpu_ctx.sync() == 0
+    ref = [(g["agg"].clone(), g["dec"].clone()) for g in groups]
+    for g in groups:
+        k = g["key"]
+        cts = [ints_from_limbs(pc2.from_device_limbs(nd["c"])) for nd in g["members"]]
+        agg = ints_from_limbs(pc2.from_device_limbs(g["agg"]))
+        dec = ints_from_limbs(pc2.from_device_limbs(g["dec"]))
+        for j in range(g["maxlen"]):
+            assert dec[j] == sum(nd["ms"][j] for nd in g["members"] if j < len(nd["ms"]))
+        for j in _sample(g["maxlen"]):
+            assert agg[j] == O.hom_sum(k["opk"], [ct[j] for ct in cts if j < len(ct)])
+            assert dec[j] == O.decrypt(k["osk"], agg[j])
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        for g in groups:        # the program's own eager work between runs
+            g["agg"].fill_(-1)
+            g["dec"].fill_(-1)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            bs.run()            # the first run captures, later runs replay
+            bd.run()
+        side.synchronize()
+        assert gpu_ctx.sync(side) == 0
+        for g, (ra, rd) in zip(groups, ref):
+            assert torch.equal(g["agg"], ra), f"aggregation, run {rep}"
+            assert torch.equal(g["dec"], rd), f"decryption, run {rep}"
+    bs.close()
+    bd.close()
+
+
 def test_batch_graph_replays_match_eager(gpu_ctx, setup):
     from paper_2601_14980_amd import pc2
     nodes = setup["nodes"]

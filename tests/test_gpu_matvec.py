@@ -37,7 +37,7 @@ def _run(ctx, sk, B, cs, alpha=None, ebits=50, window=0, rows_hint=0):
     from paper_2601_14980_amd import pc2
     L2 = 2 * sk.L
     rows, cols = len(B), len(cs)
-    mv = pc2.MatVec(sk.public, cols, ebits, window, rows_hint)
+    mv = pc2.MatVec(sk.public, cols, ebits, window, rows_hint or rows)
     mv.load(dev(to_limbs(cs, L2)))
     out = torch.full((rows, L2), -1, dtype=torch.int32, device="cuda")
     a = dev(to_limbs(alpha, L2)) if alpha is not None else None

@@ -95,12 +95,18 @@ def test_tile_batch_mixed_identical(tctx, setup, tile):
         jobs = [dict(op=pc2.PC2_OP_ENCRYPT, pk=nd["key"]["sk"].public, m=nd["m"], r=nd["r"],
                      out=o) for nd, o in zip(nodes, outs)]
         b = pc2.Batch(tctx, jobs)
-        for rep in range(2):    # the first run captures the graph, the second replays it
+        side = torch.cuda.Stream()
+        for rep in range(3):    # null stream (no graph), then capture, then replay
             for o in outs:
                 o.fill_(-1)
             torch.cuda.synchronize()
-            b.run(0)
-            assert tctx.sync() == 0
+            if rep == 0:
+                b.run(0)
+            else:
+                with torch.cuda.stream(side):
+                    b.run()
+                side.synchronize()
+            assert tctx.sync(side if rep else None) == 0
             for nd, o in zip(nodes, outs):
                 assert torch.equal(o, nd["ref"]), f"tile {tile}, run {rep}, {len(nd['ms'])}"
         b.close()

@@ -32,13 +32,19 @@
  *             all-zero bits (NaN for dequantize) and latch PC2_E_RANGE in the
  *             context; pc2_ctx_sync returns and clears the latch.
  * Threads.    A context and its keys are used from one host thread at a
- *             time.  Calls on one stream run in order; calls that share a
- *             context on different streams share its scratch memory and
- *             must not overlap (the library serialises its own launches
- *             on the stream it is given).
- * Memory.     Data calls do not allocate once the context's scratch has been
- *             sized for the largest key class used (pc2_ctx_reserve, or the
- *             first call of that class).
+ *             time.  Calls on one stream run in order.  The data calls that
+ *             use the context's scratch memory (encryptions, decryptions,
+ *             scalar powers, the fused path) also run one after another
+ *             across streams: a call on a stream other than the previous
+ *             such call's makes its stream wait (on the device) for that
+ *             call's completion event.  Under HIP graph capture no event is
+ *             waited for or recorded; the caller orders a graph's replays
+ *             against other calls on the context.
+ * Memory.     Data calls never allocate.  The key constructors (and
+ *             pc2_ctx_reserve) size the context's scratch for every data
+ *             call of the key's size class at any element count, window
+ *             and tile; a call that would still not fit returns
+ *             PC2_E_NOMEM and enqueues nothing.
  */
 #ifndef PC2_H
 #define PC2_H
@@ -90,8 +96,9 @@ int pc2_ctx_sync(pc2_ctx *ctx, void *hip_stream);
  * reflects kernels that have completed. */
 int pc2_ctx_take_error(pc2_ctx *ctx);
 
-/* Pre-size the scratch memory for keys of up to `max_nbits` bits so that no
- * later data call allocates. */
+/* Size the scratch memory for every data call under keys of up to
+ * `max_nbits` bits (the key constructors do this for their own size).  It
+ * waits for the device when the scratch grows; data calls never do. */
 int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
 
 /* Options.  PC2_OPT_WINDOW: window width w in {0 (auto), 2..6} of the

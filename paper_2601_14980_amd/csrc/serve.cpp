@@ -1,24 +1,15 @@
 // Request server for continuous batching (pc2_server_*, pc2_serve_*).
 //
 // Requests -- encryptions, aggregations and decryptions of vectors of any
-// length under one key -- arrive one at a time.  A request is admitted when
-// the bytes of its inputs and output fit in the server's HBM budget beside
-// the requests already admitted (see admit() for the order).  An admitted
-// request is cut
-// into element groups (one wavefront's share each).  Each operation has its
-// own persistent launcher (pc2_runner) on its own stream; whenever that
-// stream is idle, the next scheduling pass forms one launch over up to
-// tick_groups groups drawn from the admitted requests of the operation.
-// Two launch policies: shortest remaining first (the default: requests in
-// increasing order of the groups they have left, each taking all it can,
-// which minimises mean latency; a request admitted longer ago than a set age
-// goes first, oldest first, so that long requests are not starved) and fair
-// share (an equal slice each first, so a long request cannot hold back a
-// short one that arrived later, then what is left to the oldest).  Requests
-// that arrive
-// while launches run join the next launch of their operation, and the three
+// length under one key -- arrive one at a time.  Admission by memory, the
+// cutting of requests into element groups and the two launch policies are
+// the rules of serve_sched.hpp.  Each operation has its own persistent
+// launcher (pc2_runner) on its own stream; whenever that stream is idle, the
+// next scheduling pass forms one launch over up to tick_groups groups drawn
+// from the admitted requests of the operation.  Requests that arrive while
+// launches run join the next launch of their operation, and the three
 // operations overlap on the device.  A request is complete when the launch
-// holding its last group has finished.
+// holding its last group has finished (a HIP event on its stream).
 //
 // The server drives nothing by itself: every pc2_serve_* call makes one
 // scheduling pass (retire finished launches, admit, launch on idle streams),
@@ -26,51 +17,27 @@
 // pc2_serve_progress.  It uses the public runner calls only.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <chrono>
-#include <deque>
 #include <memory>
 #include <new>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/pc2.h"
+#include "serve_sched.hpp"
 
 namespace {
 
-constexpr int NOPS = 3;  // encrypt, hom_sum, decrypt
+using pc2s::NOPS;
+using pc2s::op_slot;
+using pc2s::Piece;
+using pc2s::Request;
 constexpr uint32_t K_MAX = 128;
-
-int op_slot(int op) {
-  if (op == PC2_OP_ENCRYPT) return 0;
-  if (op == PC2_OP_HOM_SUM) return 1;
-  if (op == PC2_OP_DECRYPT) return 2;
-  return -1;
-}
-
-enum : int { WAITING = 0, ACTIVE = 1, DONE = 2 };
-
-struct Request {
-  uint64_t id = 0;
-  int slot = 0;
-  int state = WAITING;
-  pc2_job job{};
-  std::vector<const uint32_t*> inputs;  // hom_sum: the caller's pointer array, copied
-  std::vector<size_t> lengths;          // hom_sum: the caller's lengths, copied (may be empty)
-  size_t bytes = 0;                     // inputs + output, for admission
-  size_t groups = 0, next = 0, done = 0;
-  double submitted = 0, admitted = 0;   // host clock, seconds
-};
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
 }
-
-struct Piece {
-  Request* req;
-  size_t first, n;
-};
 
 }  // namespace
 
@@ -80,25 +47,21 @@ struct pc2_server {
   const pc2_sk* sk = nullptr;
   const pc2_pk* pk = nullptr;
   uint32_t L = 0;
-  size_t budget = 0, used = 0, max_used = 0;
-  size_t tick_groups = 0, max_requests = 0;
-  int policy = PC2_SERVE_SHORTEST;
-  double max_age = 1.0;  // seconds, shortest-first policy
-  uint32_t group_elems[NOPS] = {};
+  size_t max_requests = 0;
+  pc2s::Sched sch;
   pc2_runner* runner[NOPS] = {};
   hipStream_t stream[NOPS] = {};
   hipEvent_t finished[NOPS] = {};
   bool busy[NOPS] = {};
   std::vector<Piece> tick[NOPS];
-  std::deque<Request*> waiting;
-  std::deque<Request*> active[NOPS];
   std::vector<uint64_t> completed;  // finished ids not yet drained by pc2_serve_completed
   std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
   uint64_t next_id = 1;
   uint64_t launches = 0;
-  // per-launch argument arrays, reused
+  // per-launch argument arrays and the retired requests, reused
   std::vector<pc2_job> jobs;
   std::vector<size_t> first, ngroups;
+  std::vector<Request*> done;
 };
 
 namespace {
@@ -110,102 +73,39 @@ size_t request_bytes(const pc2_server* s, const pc2_job& j) {
   return n * (8 * L + 4 * L);
 }
 
-void finish(pc2_server* s, Request* r) {
-  r->state = DONE;
-  s->used -= r->bytes;
+void note_finished(pc2_server* s, uint64_t id) {
   // ids that pc2_serve_poll already reported are dropped here, so the list
   // holds at most about twice the tracked requests
   if (s->completed.size() >= 2 * s->max_requests) {
     auto& c = s->completed;
     c.erase(std::remove_if(c.begin(), c.end(),
-                           [s](uint64_t id) { return !s->requests.count(id); }),
+                           [s](uint64_t i) { return !s->requests.count(i); }),
             c.end());
   }
-  s->completed.push_back(r->id);
+  s->completed.push_back(id);
 }
 
 // The launch of operation `op` finished: count its groups against their requests.
 void retire(pc2_server* s, int op) {
-  for (const Piece& p : s->tick[op]) {
-    Request* r = p.req;
-    r->done += p.n;
-    if (r->done == r->groups) {
-      auto& q = s->active[op];
-      q.erase(std::find(q.begin(), q.end(), r));
-      finish(s, r);
-    }
-  }
+  s->done.clear();
+  pc2s::retire(s->sch, op, s->tick[op], s->done);
+  for (Request* r : s->done) note_finished(s, r->id);
   s->tick[op].clear();
   s->busy[op] = false;
 }
 
-// Fair share admits first come, first served: a request that does not fit
-// holds back those behind it.  Shortest first admits every waiting request
-// that fits, in arrival order, except that one submitted more than the age
-// limit ago which does not fit holds back those behind it (so the memory it
-// waits for is not taken by later requests).
-void admit(pc2_server* s) {
-  const bool first_fit = s->policy == PC2_SERVE_SHORTEST;
-  const double t = now_s();
-  for (auto it = s->waiting.begin(); it != s->waiting.end();) {
-    Request* r = *it;
-    if (s->used + r->bytes > s->budget) {
-      if (!first_fit || t - r->submitted > s->max_age) break;
-      ++it;
-      continue;
-    }
-    it = s->waiting.erase(it);
-    const size_t g = s->group_elems[r->slot];
-    r->groups = (r->job.count + g - 1) / g;
-    r->state = ACTIVE;
-    r->admitted = t;
-    s->used += r->bytes;
-    s->max_used = std::max(s->max_used, s->used);
-    s->active[r->slot].push_back(r);
-  }
-}
-
 // One launch of operation `op` over the admitted requests' next groups.
 int launch(pc2_server* s, int op) {
-  std::vector<Request*> reqs;
-  for (Request* r : s->active[op])
-    if (r->next < r->groups) reqs.push_back(r);
-  if (reqs.empty()) return PC2_OK;
-  size_t room = s->tick_groups;
-  std::vector<size_t> take(reqs.size(), 0);
-  if (s->policy == PC2_SERVE_SHORTEST) {
-    // aged requests first (oldest first), then the rest by groups left
-    const double t = now_s();
-    std::stable_sort(reqs.begin(), reqs.end(), [&](const Request* a, const Request* b) {
-      const bool oa = t - a->admitted > s->max_age, ob = t - b->admitted > s->max_age;
-      if (oa != ob) return oa;
-      if (oa) return a->admitted < b->admitted;
-      return a->groups - a->next < b->groups - b->next;
-    });
-  } else {
-    const size_t share = std::max<size_t>(1, room / reqs.size());
-    for (size_t i = 0; i < reqs.size() && room; ++i) {
-      take[i] = std::min({share, reqs[i]->groups - reqs[i]->next, room});
-      room -= take[i];
-    }
-  }
-  for (size_t i = 0; i < reqs.size() && room; ++i) {
-    const size_t t = std::min(reqs[i]->groups - reqs[i]->next - take[i], room);
-    take[i] += t;
-    room -= t;
-  }
+  auto& tick = s->tick[op];
+  pc2s::form_launch(s->sch, op, now_s(), tick);
+  if (tick.empty()) return PC2_OK;
   s->jobs.clear();
   s->first.clear();
   s->ngroups.clear();
-  auto& tick = s->tick[op];
-  tick.clear();
-  for (size_t i = 0; i < reqs.size(); ++i) {
-    if (!take[i]) continue;
-    Request* r = reqs[i];
-    s->jobs.push_back(r->job);
-    s->first.push_back(r->next);
-    s->ngroups.push_back(take[i]);
-    tick.push_back({r, r->next, take[i]});
+  for (const Piece& p : tick) {
+    s->jobs.push_back(p.req->job);
+    s->first.push_back(p.first);
+    s->ngroups.push_back(p.n);
   }
   int rc = pc2_runner_launch(s->runner[op], s->jobs.data(), s->first.data(), s->ngroups.data(),
                              s->jobs.size(), s->stream[op]);
@@ -214,7 +114,7 @@ int launch(pc2_server* s, int op) {
     return rc;
   }
   if (hipEventRecord(s->finished[op], s->stream[op]) != hipSuccess) return PC2_E_DEVICE;
-  for (const Piece& p : tick) p.req->next += p.n;
+  pc2s::commit(tick);
   s->busy[op] = true;
   ++s->launches;
   return PC2_OK;
@@ -229,9 +129,9 @@ int refresh_group_sizes(pc2_server* s) {
   for (int op = 0; op < NOPS; ++op) {
     uint32_t g = 0;
     if (pc2_runner_group_size(s->pk, ops[op], &g) != PC2_OK || g == 0) return PC2_E_UNSUPPORTED;
-    if (g == s->group_elems[op]) continue;
-    if (!s->active[op].empty()) return PC2_E_UNSUPPORTED;
-    s->group_elems[op] = g;
+    if (g == s->sch.group_elems[op]) continue;
+    if (!s->sch.active[op].empty()) return PC2_E_UNSUPPORTED;
+    s->sch.group_elems[op] = g;
   }
   return PC2_OK;
 }
@@ -247,7 +147,7 @@ int pass(pc2_server* s) {
   }
   int rc = refresh_group_sizes(s);
   if (rc) return rc;
-  admit(s);
+  pc2s::admit(s->sch, now_s());
   for (int op = 0; op < NOPS; ++op) {
     if (s->busy[op]) continue;
     rc = launch(s, op);
@@ -329,14 +229,14 @@ int pc2_server_create(pc2_ctx* ctx, const pc2_sk* sk, size_t hbm_budget, size_t 
   s->sk = sk;
   s->pk = pk;
   s->L = limbs;
-  s->budget = hbm_budget;
-  s->tick_groups = tick_groups;
+  s->sch.budget = hbm_budget;
+  s->sch.tick_groups = tick_groups;
   s->max_requests = max_requests;
   static const int ops[NOPS] = {PC2_OP_ENCRYPT, PC2_OP_HOM_SUM, PC2_OP_DECRYPT};
   int rc = PC2_OK;
   for (int op = 0; op < NOPS && !rc; ++op) {
-    rc = pc2_runner_group_size(pk, ops[op], &s->group_elems[op]);
-    if (!rc && s->group_elems[op] == 0) rc = PC2_E_UNSUPPORTED;
+    rc = pc2_runner_group_size(pk, ops[op], &s->sch.group_elems[op]);
+    if (!rc && s->sch.group_elems[op] == 0) rc = PC2_E_UNSUPPORTED;
     if (!rc) rc = pc2_runner_create(ctx, ops[op], nbits, max_requests, tick_groups, &s->runner[op]);
     if (!rc && (hipStreamCreateWithFlags(&s->stream[op], hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&s->finished[op], hipEventDisableTiming) != hipSuccess))
@@ -372,18 +272,17 @@ int pc2_serve_submit(pc2_server* s, const pc2_job* job, uint64_t* req_id) {
     }
   }
   r->bytes = request_bytes(s, r->job);
-  if (r->bytes > s->budget) return PC2_E_NOMEM;  // could never be admitted
+  if (r->bytes > s->sch.budget) return PC2_E_NOMEM;  // could never be admitted
   Request* raw = r.get();
   s->requests.emplace(raw->id, std::move(r));
   *req_id = raw->id;
   if (raw->job.count == 0) {  // nothing to compute
-    raw->state = ACTIVE;
-    s->used += raw->bytes;
-    finish(s, raw);
+    raw->state = pc2s::DONE;
+    note_finished(s, raw->id);
     return PC2_OK;
   }
   raw->submitted = now_s();
-  s->waiting.push_back(raw);
+  s->sch.waiting.push_back(raw);
   return pass(s);
 }
 
@@ -393,7 +292,7 @@ int pc2_serve_poll(pc2_server* s, uint64_t req_id, int* done) {
   if (it == s->requests.end()) return PC2_E_INVAL;
   const int rc = pass(s);
   if (rc) return rc;
-  *done = it->second->state == DONE;
+  *done = it->second->state == pc2s::DONE;
   if (*done) s->requests.erase(it);
   return PC2_OK;
 }
@@ -403,8 +302,8 @@ int pc2_serve_progress(pc2_server* s, size_t* pending) {
   const int rc = pass(s);
   if (rc) return rc;
   if (pending) {
-    size_t n = s->waiting.size();
-    for (int op = 0; op < NOPS; ++op) n += s->active[op].size();
+    size_t n = s->sch.waiting.size();
+    for (int op = 0; op < NOPS; ++op) n += s->sch.active[op].size();
     *pending = n;
   }
   return PC2_OK;
@@ -427,8 +326,8 @@ int pc2_serve_completed(pc2_server* s, uint64_t* ids, size_t cap, size_t* n) {
 int pc2_server_set_policy(pc2_server* s, int policy, double max_age_s) {
   if (!s || (policy != PC2_SERVE_FAIR && policy != PC2_SERVE_SHORTEST) || !(max_age_s >= 0))
     return PC2_E_INVAL;
-  s->policy = policy;
-  s->max_age = max_age_s;
+  s->sch.policy = policy;
+  s->sch.max_age = max_age_s;
   return PC2_OK;
 }
 
@@ -436,8 +335,8 @@ int pc2_server_stats(const pc2_server* s, uint64_t* launches, size_t* max_bytes,
                      size_t* used_bytes) {
   if (!s) return PC2_E_INVAL;
   if (launches) *launches = s->launches;
-  if (max_bytes) *max_bytes = s->max_used;
-  if (used_bytes) *used_bytes = s->used;
+  if (max_bytes) *max_bytes = s->sch.max_used;
+  if (used_bytes) *used_bytes = s->sch.used;
   return PC2_OK;
 }
 

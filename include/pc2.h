@@ -196,6 +196,27 @@ int pc2_encrypt_sk(const pc2_sk *sk, const uint32_t *m, uint32_t m_limbs, const 
 int pc2_decrypt(const pc2_sk *sk, const uint32_t *c, uint32_t *m, size_t count,
                 void *stream);
 
+/* Decryption for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pc2_decrypt's arguments, layouts, data errors and results, bit for bit,
+ * with its staging and window tables in a static device array of
+ * PC2_STATIC_SCRATCH_BYTES per device (placed when the library's code is
+ * loaded on the device, held until the process ends; its address is taken
+ * by pc2_ctx_create) instead of the context's scratch.  The call allocates
+ * nothing and waits for nothing.  Any count is accepted: it runs in chunks
+ * whose staging fits an eighth of the array, with the widest window (up to
+ * pc2_decrypt's) whose device-filling grid's tables fit the rest (w = 3 at
+ * 2048-4096 bits), else a narrower grid; a key whose single workgroup does not fit is PC2_E_NOMEM
+ * (no supported key size reaches it).  Every call on one device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * contexts or threads) race and give wrong results; calls on one stream run
+ * in order.  The array's contents are overwritten before they are read, so
+ * nothing needs clearing between calls.  PC2_E_DEVICE if the array's
+ * address could not be taken on the key's device. */
+#define PC2_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+int pc2_decrypt_static(const pc2_sk *sk, const uint32_t *c, uint32_t *m, size_t count,
+                       void *stream);
+
 /* Homomorphic addition (Definition 1): out = c1 c2 mod n^2.  [count][2L]. */
 int pc2_hom_add(const pc2_pk *pk, const uint32_t *c1, const uint32_t *c2, uint32_t *out,
                 size_t count, void *stream);

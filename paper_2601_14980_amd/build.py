@@ -35,6 +35,7 @@ UNITS = {
     "kernels_quant.hip": ["-ffp-contract=off"],
     "kernels_admm.hip": ["-ffp-contract=off"],
     "kernels_colsplit.hip": ["-ffp-contract=off"],
+    "static_scratch.hip": [],
     "api.cpp": [],
     "serve.cpp": [],
 }

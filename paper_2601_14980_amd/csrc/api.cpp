@@ -669,6 +669,8 @@ int pc2_ctx_create(int hip_device, pc2_ctx** out) {
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return PC2_E_DEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PC2_E_DEVICE;
   if (hipSetDevice(hip_device) != hipSuccess) return PC2_E_DEVICE;
+  // the device address of the allocation-free calls' static scratch
+  if (pc2k::static_scratch_setup(hip_device) != 0) return PC2_E_DEVICE;
   pc2_ctx* c = new (std::nothrow) pc2_ctx();
   if (!c) return PC2_E_NOMEM;
   c->device = hip_device;
@@ -981,6 +983,53 @@ int pc2_decrypt(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count, 
                                         l.aux));
   }
   return scratch_end(sk->ctx, stream, rc);
+}
+
+// pc2_decrypt with its staging and tables in the static device scratch
+// (static_scratch.hip) instead of the context's: nothing is allocated and no
+// event is waited for or recorded.
+int pc2_decrypt_static(const pc2_sk* sk, const uint32_t* c, uint32_t* m, size_t count,
+                       void* stream) {
+  if (!sk || !sk->ctx) return PC2_E_INVAL;
+  if (count == 0) return PC2_OK;
+  if (!c || !m) return PC2_E_INVAL;
+  if (partial_overlap(c, 8 * (size_t)sk->pk.L * count, m, 4 * (size_t)sk->pk.L * count))
+    return PC2_E_INVAL;
+  uint32_t* base = pc2k::static_scratch(sk->pk.device);
+  if (!base) return PC2_E_DEVICE;
+  pc2_ctx* ctx = sk->ctx;
+  const int Ls = sk->c.h[0].Ls, L = sk->pk.L, cls = sk->pk.cls;
+  const size_t total = PC2_STATIC_SCRATCH_BYTES / 4;
+  // staging of one chunk's CRT halves: at most an eighth of the array
+  const size_t per = 2 * (size_t)(Ls + 1);
+  const size_t chunk = std::min({count, pc2k::DEC_CHUNK, total / 8 / per});
+  if (chunk == 0) return PC2_E_NOMEM;
+  const size_t aux = (chunk * per + 63) & ~(size_t)63;
+  const size_t tab_words = total - aux;
+  // the widest window up to pc2_decrypt's whose device-filling grid fits;
+  // else the narrowest window on as many workgroups as fit
+  pc2k::Launch l{};
+  int w = window_for(ctx, cls, pc2k::OP_DEC);
+  size_t need = 0;
+  for (;; --w) {
+    need = plan_launch(ctx, cls, pc2k::OP_DEC, chunk, Ls, L, w, &l, stream, 0) / 4;
+    if (need <= tab_words || w == pc2k::SCHED_WMIN) break;
+  }
+  if (need > tab_words) {
+    const size_t per_wg = need / (size_t)l.grid;  // tiles x slot words of one workgroup
+    const size_t grid = tab_words / per_wg;
+    if (grid == 0) return PC2_E_NOMEM;
+    l.grid = (int)grid;
+  }
+  l.aux = base;
+  l.scratch = base + aux;
+  const size_t L2 = 2 * (size_t)L;
+  int rc = PC2_OK;
+  for (size_t b = 0; b < count && !rc; b += chunk) {
+    const size_t n = std::min(chunk, count - b);
+    rc = status_of(pc2k::launch_decrypt(cls, l, sk->c, c + b * L2, m + b * L, n, l.aux));
+  }
+  return rc;
 }
 
 int pc2_encrypt_sk(const pc2_sk* sk, const uint32_t* m, uint32_t m_limbs, const uint32_t* r,

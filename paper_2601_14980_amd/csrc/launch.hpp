@@ -102,4 +102,10 @@ hipError_t launch_quantize(const Launch& l, int log2_scale, uint64_t offset, uin
 hipError_t launch_dequantize(const Launch& l, int log2_scale, uint64_t offset, const uint32_t* m,
                              int m_limbs, uint64_t weight, double* x, size_t count);
 
+// the static device scratch of the allocation-free calls (static_scratch.hip):
+// setup takes its address on `device`, which must be current (0, or -1 on
+// failure); static_scratch returns that address (null before setup)
+int static_scratch_setup(int device);
+uint32_t* static_scratch(int device);
+
 }  // namespace pc2k

@@ -47,7 +47,7 @@ EXPORTS = [
     "pc2_ctx_reserve", "pc2_ctx_set_option", "pc2_ctx_get_option", "pc2_strerror",
     "pc2_pk_create", "pc2_sk_create", "pc2_sk_public", "pc2_pk_destroy", "pc2_sk_destroy",
     "pc2_pk_info", "pc2_quantize", "pc2_dequantize", "pc2_encrypt", "pc2_encrypt_sk",
-    "pc2_decrypt",
+    "pc2_decrypt", "pc2_decrypt_static",
     "pc2_hom_add", "pc2_hom_scalar_mul", "pc2_hom_sum", "pc2_enc_sum_dec",
     "pc2_matvec_create", "pc2_matvec_info", "pc2_matvec_load", "pc2_matvec_apply",
     "pc2_matvec_destroy", "pc2_colsplit_create", "pc2_colsplit_iterate", "pc2_colsplit_destroy",
@@ -105,6 +105,7 @@ def _load() -> ctypes.CDLL:
         "pc2_encrypt": (c_int, [P, P, c_uint32, P, P, c_size_t, P]),
         "pc2_encrypt_sk": (c_int, [P, P, c_uint32, P, P, c_size_t, P]),
         "pc2_decrypt": (c_int, [P, P, P, c_size_t, P]),
+        "pc2_decrypt_static": (c_int, [P, P, P, c_size_t, P]),
         "pc2_hom_add": (c_int, [P, P, P, P, c_size_t, P]),
         "pc2_hom_scalar_mul": (c_int, [P, P, P, P, c_size_t, P]),
         "pc2_hom_sum": (c_int, [P, POINTER(P), c_uint32, P, c_size_t, P]),
@@ -334,6 +335,17 @@ def pc2_decrypt(sk: SecretKey, c: torch.Tensor, m: torch.Tensor, stream=None) ->
         raise ValueError("m and c must have the same count")
     _check(lib.pc2_decrypt(sk.handle, _dev_ptr(c, torch.int32, "c"),
                            _dev_ptr(m, torch.int32, "m"), count, _stream(stream)), "pc2_decrypt")
+
+
+def pc2_decrypt_static(sk: SecretKey, c: torch.Tensor, m: torch.Tensor, stream=None) -> None:
+    """pc2_decrypt with the library's static device scratch: allocates nothing."""
+    count = _rows(c, 2 * sk.L, "c")
+    _rows(m, sk.L, "m")
+    if m.shape[0] != count:
+        raise ValueError("m and c must have the same count")
+    _check(lib.pc2_decrypt_static(sk.handle, _dev_ptr(c, torch.int32, "c"),
+                                  _dev_ptr(m, torch.int32, "m"), count, _stream(stream)),
+           "pc2_decrypt_static")
 
 
 def pc2_hom_add(pk: PublicKey, c1: torch.Tensor, c2: torch.Tensor, out: torch.Tensor,

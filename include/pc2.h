@@ -306,6 +306,12 @@ int pc2_matvec_destroy(pc2_matvec *mv);
  *   Synchronises the stream (the setup's workspace is released); A, y and
  *   r_pool must stay valid while the object lives (r_pool is read every
  *   iteration).
+ * pc2_colsplit_set_scale: quantize again at scale 2^log2_scale (same bounds as
+ *   at creation): G_k, its row sums, Enc(Gamma_1(alpha_k)) (pool rows 0 .. N-1
+ *   again) and the mat-vec plans over (log2_scale + 4)-bit constants; the
+ *   float64 setup (B_k, alpha_k) is kept.  Synchronises the stream.  After
+ *   an error the object only runs unquantized iterations (quantized ones
+ *   return PC2_E_INVAL) until a change of scale succeeds.
  * pc2_colsplit_iterate: one iteration on device double [N] arrays x (out),
  *   z and v (in and out).  quantized != 0 runs the encrypted node step;
  *   quantized = 0 the same iteration in float64 without quantization
@@ -316,6 +322,7 @@ int pc2_colsplit_create(const pc2_sk *sk, const double *A, const double *y, uint
                         uint32_t N, uint32_t K, double rho, uint32_t log2_scale,
                         const uint32_t *r_pool, size_t r_count, void *hip_stream,
                         pc2_colsplit **out);
+int pc2_colsplit_set_scale(pc2_colsplit *cs, uint32_t log2_scale, void *hip_stream);
 int pc2_colsplit_iterate(pc2_colsplit *cs, double lambda, int quantized, double *x, double *z,
                          double *v, void *hip_stream);
 int pc2_colsplit_destroy(pc2_colsplit *cs);

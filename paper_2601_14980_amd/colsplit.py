@@ -3,7 +3,8 @@
 A is split by columns over K simulated edge nodes.  At set-up each node's
 B_k = (A_k^T A_k + rho I)^-1, the quantized matrix Gamma_2(rho B_k) and the
 master's Enc(Gamma_1(B_k A_k^T y)) are computed on the device
-(pc2_colsplit_create).  Every iteration (pc2_colsplit_iterate):
+(pc2_colsplit_create; pc2_colsplit_set_scale quantizes again at another
+scale).  Every iteration (pc2_colsplit_iterate):
 
     master:  Enc(Gamma_2(z_k)), Enc(Gamma_2(-v_k))          pc2_encrypt
     node k:  alpha_k (+) Gamma_2(rho B_k) (x) (z_k (+) -v_k)   pc2_hom_add, pc2_matvec_*
@@ -45,6 +46,11 @@ class ColumnSplitLasso:
         self.x = torch.zeros(N, dtype=torch.float64, device=dev)
         self.z = torch.zeros(N, dtype=torch.float64, device=dev)
         self.v = torch.zeros(N, dtype=torch.float64, device=dev)
+
+    def set_scale(self, log2_scale: int, stream=None) -> None:
+        """Quantize again at scale 2^log2_scale (the float64 setup is kept)."""
+        pc2._check(_lib.pc2_colsplit_set_scale(self.handle, log2_scale, pc2._stream(stream)),
+                   "pc2_colsplit_set_scale")
 
     def iterate(self, lam: float, quantized: bool = True, stream=None) -> None:
         pc2._check(_lib.pc2_colsplit_iterate(

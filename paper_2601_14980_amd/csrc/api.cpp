@@ -98,6 +98,7 @@ struct pc2_colsplit {
   uint32_t* ahat = nullptr;                       // [K][Nk][2L] Enc(Gamma_1(alpha_k))
   uint64_t *w = nullptr, *S = nullptr;            // [2][N] Gamma_2(z), Gamma_2(-v); [K]
   uint32_t *cw = nullptr, *c = nullptr, *xhat = nullptr, *P = nullptr;  // [2N][2L], [N][2L] x2, [N][L]
+  uint32_t* g1 = nullptr;                         // [K][Nk][4] Gamma_1(alpha_k)
 };
 
 struct pc2_pk {
@@ -1839,6 +1840,43 @@ int ceil_log2(size_t v) {
 }
 }  // namespace
 
+namespace {
+// Plaintexts of the node step stay below 2^(2k + 9 + log2 Nk): they must fit
+// 127 bits (the inverse quantization's integers) and the key.
+bool colsplit_scale_ok(const pc2_sk* sk, int Nk, int k) {
+  const int pbits = 2 * k + 9 + ceil_log2((size_t)Nk);
+  return k >= 1 && pbits <= 126 && pbits < (int)sk->pk.c.nbits && sk->pk.L >= 4;
+}
+
+// Quantization of every node at scale 2^k: G_k = Gamma_2(rho B_k), its row
+// sums, Enc(Gamma_1(alpha_k)) (randomness rows kk Nk .. (kk + 1) Nk - 1 of the
+// pool) and the nodes' mat-vec plans over (k + 4)-bit constants.  Earlier
+// plans are destroyed first (after the stream's work that reads them).
+int colsplit_quantize(pc2_colsplit* cs, int k, void* stream) {
+  const pc2_sk* sk = cs->sk;
+  const size_t nk = (size_t)cs->Nk, L2 = 2 * (size_t)sk->pk.L;
+  if (!cs->mv.empty()) {
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PC2_E_DEVICE;
+    for (pc2_matvec* mv : cs->mv) pc2_matvec_destroy(mv);
+    cs->mv.clear();
+  }
+  int rc = PC2_OK;
+  for (int kk = 0; kk < cs->K && !rc; ++kk) {
+    const size_t o1 = kk * nk, o2 = kk * nk * nk;
+    rc = status_of(pc2k::cs_quantize_node(cs->rhoB + o2, cs->alpha + o1, cs->Nk, k, cs->G + o2,
+                                          cs->R + o1, cs->g1 + o1 * 4, cs->ctx->err, stream));
+    if (!rc)
+      rc = pc2_encrypt(&sk->pk, cs->g1 + o1 * 4, 4, cs->r_pool + o1 * sk->pk.L,
+                       cs->ahat + o1 * L2, nk, stream);
+    pc2_matvec* mv = nullptr;
+    if (!rc) rc = pc2_matvec_create(&sk->pk, nk, (uint32_t)(k + 4), 0, nk, &mv);
+    if (!rc) cs->mv.push_back(mv);
+  }
+  if (!rc) cs->k = k;
+  return rc;
+}
+}  // namespace
+
 int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint32_t M,
                         uint32_t N, uint32_t K, double rho, uint32_t log2_scale,
                         const uint32_t* r_pool, size_t r_count, void* hip_stream,
@@ -1848,9 +1886,7 @@ int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint
     return PC2_E_INVAL;
   *out = nullptr;
   const int Nk = (int)(N / K), k = (int)log2_scale, L = sk->pk.L;
-  // plaintexts stay below 2^(2k + 9 + log2 Nk): they must fit 127 bits and n
-  const int pbits = 2 * k + 9 + ceil_log2((size_t)Nk);
-  if (pbits > 126 || pbits >= (int)sk->pk.c.nbits || L < 4) return PC2_E_UNSUPPORTED;
+  if (!colsplit_scale_ok(sk, Nk, k)) return PC2_E_UNSUPPORTED;
   if (r_count < 3 * (size_t)N) return PC2_E_INVAL;
   pc2_ctx* ctx = sk->ctx;
   if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
@@ -1868,12 +1904,12 @@ int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint
   cs->r_count = r_count;
   const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L, n = N;
   const size_t bytes = 256 * 16 + K * nk * 8 * 2 + K * nk * nk * 16 + K * nk * L2 * 4 +
-                       n * 8 * 2 + K * 8 + n * L2 * 4 * 4 + n * L * 4;
+                       n * 8 * 2 + K * 8 + n * L2 * 4 * 4 + n * L * 4 + K * nk * 16;
   void* tmp = nullptr;
   int rc = PC2_OK;
   if (hipMalloc(&cs->dev, bytes) != hipSuccess) rc = PC2_E_NOMEM;
-  // setup workspace: T (Nk x 2Nk), rp (2Nk), f (Nk), aty (Nk), Gamma_1 limbs (Nk x 4)
-  const size_t tbytes = 256 * 8 + nk * 2 * nk * 8 + nk * 4 * 8 + nk * 16;
+  // setup workspace: T (Nk x 2Nk), rp (2Nk), f (Nk), aty (Nk)
+  const size_t tbytes = 256 * 8 + nk * 2 * nk * 8 + nk * 4 * 8;
   if (!rc && hipMalloc(&tmp, tbytes) != hipSuccess) rc = PC2_E_NOMEM;
   if (!rc) {
     char* at = (char*)cs->dev;
@@ -1888,24 +1924,18 @@ int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint
     cs->c = (uint32_t*)carve(at, (n * L2) * sizeof(uint32_t));
     cs->xhat = (uint32_t*)carve(at, (n * L2) * sizeof(uint32_t));
     cs->P = (uint32_t*)carve(at, (n * L) * sizeof(uint32_t));
+    cs->g1 = (uint32_t*)carve(at, (K * nk * 4) * sizeof(uint32_t));
     char* wt = (char*)tmp;
     double* T = (double*)carve(wt, (nk * 2 * nk) * sizeof(double));
     double* rp = (double*)carve(wt, (2 * nk) * sizeof(double));
     double* f = (double*)carve(wt, (nk) * sizeof(double));
     double* aty = (double*)carve(wt, (nk) * sizeof(double));
-    uint32_t* g1 = (uint32_t*)carve(wt, (nk * 4) * sizeof(uint32_t));
     for (int kk = 0; kk < (int)K && !rc; ++kk) {
       const size_t o1 = kk * nk, o2 = kk * nk * nk;
-      rc = status_of(pc2k::cs_setup_node(A, y, (int)M, (int)N, kk * Nk, Nk, rho, k, T, rp, f,
-                                         aty, cs->alpha + o1, cs->rhoB + o2, cs->G + o2,
-                                         cs->R + o1, g1, ctx->err, hip_stream));
-      // alpha_k = Enc(Gamma_1(B_k A_k^T y)), randomness rows kk Nk .. (kk + 1) Nk - 1
-      if (!rc)
-        rc = pc2_encrypt(&sk->pk, g1, 4, r_pool + o1 * L, cs->ahat + o1 * L2, nk, hip_stream);
-      pc2_matvec* mv = nullptr;
-      if (!rc) rc = pc2_matvec_create(&sk->pk, nk, (uint32_t)(k + 4), 0, nk, &mv);
-      if (!rc) cs->mv.push_back(mv);
+      rc = status_of(pc2k::cs_setup_node(A, y, (int)M, (int)N, kk * Nk, Nk, rho, T, rp, f, aty,
+                                         cs->alpha + o1, cs->rhoB + o2, hip_stream));
     }
+    if (!rc) rc = colsplit_quantize(cs, k, hip_stream);
     // the workspace is released once the setup has run
     if (!rc && hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) rc = PC2_E_DEVICE;
   }
@@ -1921,6 +1951,15 @@ int pc2_colsplit_create(const pc2_sk* sk, const double* A, const double* y, uint
   return PC2_OK;
 }
 
+int pc2_colsplit_set_scale(pc2_colsplit* cs, uint32_t log2_scale, void* hip_stream) {
+  if (!cs || !cs->ctx) return PC2_E_INVAL;
+  if (!colsplit_scale_ok(cs->sk, cs->Nk, (int)log2_scale)) return PC2_E_UNSUPPORTED;
+  if (hipSetDevice(cs->ctx->device) != hipSuccess) return PC2_E_DEVICE;
+  int rc = colsplit_quantize(cs, (int)log2_scale, hip_stream);
+  if (!rc && hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) rc = PC2_E_DEVICE;
+  return rc;
+}
+
 int pc2_colsplit_iterate(pc2_colsplit* cs, double lambda, int quantized, double* x, double* z,
                          double* v, void* hip_stream) {
   if (!cs || !cs->ctx || !x || !z || !v || !(lambda >= 0)) return PC2_E_INVAL;
@@ -1932,6 +1971,7 @@ int pc2_colsplit_iterate(pc2_colsplit* cs, double lambda, int quantized, double*
   const size_t nk = (size_t)Nk, L2 = 2 * (size_t)L, n = (size_t)cs->N;
   int rc = PC2_OK;
   if (quantized) {
+    if (cs->mv.size() != (size_t)cs->K) return PC2_E_INVAL;  // a failed change of scale
     // master: Gamma_2(z) and Gamma_2(-v) of every node, encrypted in one launch
     // with the next 2N rows of the randomness pool (after the rows of alpha)
     const size_t span = cs->r_count - 3 * n + 1;

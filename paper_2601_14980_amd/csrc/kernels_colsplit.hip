@@ -7,7 +7,9 @@
 //   k_cs_gram        T = [A_k^T A_k + rho I | I]   (rows of A summed in order)
 //   k_cs_gj_pivot/update   Gauss-Jordan on T, pivots in order, no exchanges
 //   k_cs_aty, k_cs_matvec  alpha_k = B_k (A_k^T y)  (sums in index order)
-//   k_cs_rhob        rho B_k, G = Gamma_2(rho B_k) = rint(rho B 2^k) + 2^(k+3)
+//   k_cs_rhob        rho B_k
+// Quantization of node k at scale 2^k (at setup, and again on a change of scale):
+//   k_cs_quant_g     G = Gamma_2(rho B_k) = rint(rho B 2^k) + 2^(k+3)
 //   k_cs_rowsum      R_i = sum_j G_ij
 //   k_cs_gamma1      Gamma_1(alpha) = rint(alpha 2^(2k)) + 2^(2k+3), 4 limbs
 // Per iteration (all nodes at once; node of element i = i / Nk):
@@ -94,14 +96,21 @@ __global__ void k_cs_matvec(const double* __restrict__ Bm, size_t ld, int Nk,
   out[i] = add ? add[i] + acc : acc;
 }
 
-// rho B (from the right half of T) and G = Gamma_2(rho B)
-__global__ void k_cs_rhob(const double* __restrict__ T, int Nk, double rho, int k,
-                          double* __restrict__ rhoB, uint64_t* __restrict__ G, int* err) {
+// rho B (from the right half of T)
+__global__ void k_cs_rhob(const double* __restrict__ T, int Nk, double rho,
+                          double* __restrict__ rhoB) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)Nk * Nk) return;
   const size_t i = idx / Nk, j = idx % Nk;
-  const double u = rho * T[i * 2 * Nk + Nk + j];
-  rhoB[idx] = u;
+  rhoB[idx] = rho * T[i * 2 * Nk + Nk + j];
+}
+
+// G = Gamma_2(rho B)
+__global__ void k_cs_quant_g(const double* __restrict__ rhoB, size_t count, int k,
+                             uint64_t* __restrict__ G, int* err) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const double u = rhoB[idx];
   const bool ok = in_range(u);
   G[idx] = ok ? (uint64_t)((int64_t)rint(ldexp(u, k)) + ((int64_t)1 << (k + ZLOG2))) : 0;
   if (!ok) atomicOr(err, pc2k::ERR_RANGE);
@@ -234,9 +243,8 @@ inline unsigned blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b
 namespace pc2k {
 
 hipError_t cs_setup_node(const double* A, const double* y, int M, int N, int k0, int Nk,
-                         double rho, int k, double* T, double* rp, double* f, double* aty,
-                         double* alpha, double* rhoB, uint64_t* G, uint64_t* R, uint32_t* g1,
-                         int* err, void* stream) {
+                         double rho, double* T, double* rp, double* f, double* aty,
+                         double* alpha, double* rhoB, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const size_t nt = (size_t)Nk * 2 * Nk;
   hipLaunchKernelGGL(k_cs_gram, dim3(blocks(nt, 256)), dim3(256), 0, s, A, M, N, k0, Nk, rho, T);
@@ -250,7 +258,15 @@ hipError_t cs_setup_node(const double* A, const double* y, int M, int N, int k0,
   hipLaunchKernelGGL(k_cs_matvec, dim3(blocks(Nk, 256)), dim3(256), 0, s, T + Nk,
                      2 * (size_t)Nk, Nk, aty, (const double*)nullptr, alpha);
   hipLaunchKernelGGL(k_cs_rhob, dim3(blocks((size_t)Nk * Nk, 256)), dim3(256), 0, s, T, Nk, rho,
-                     k, rhoB, G, err);
+                     rhoB);
+  return hipGetLastError();
+}
+
+hipError_t cs_quantize_node(const double* rhoB, const double* alpha, int Nk, int k, uint64_t* G,
+                            uint64_t* R, uint32_t* g1, int* err, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nn = (size_t)Nk * Nk;
+  hipLaunchKernelGGL(k_cs_quant_g, dim3(blocks(nn, 256)), dim3(256), 0, s, rhoB, nn, k, G, err);
   hipLaunchKernelGGL(k_cs_rowsum, dim3(blocks(Nk, 256)), dim3(256), 0, s, G, Nk, R);
   hipLaunchKernelGGL(k_cs_gamma1, dim3(blocks(Nk, 256)), dim3(256), 0, s, alpha, Nk, k, g1, err);
   return hipGetLastError();

@@ -58,13 +58,16 @@ hipError_t launch_mv_apply(int cls, int grid, const PkConst& pk, const uint64_t*
                            const uint32_t* alpha, size_t nchunks, size_t chunk_cols,
                            uint32_t* out, size_t chunk_stride, int* err, void* stream);
 
-// column-split ADMM (kernels_colsplit.hip): setup of one node's constants,
-// and the float64 / integer steps of an iteration around the encrypted node
-// step.  T: Nk x 2Nk doubles; rp: 2Nk; f, aty: Nk doubles of workspace.
+// column-split ADMM (kernels_colsplit.hip): float64 setup of one node's
+// constants (alpha_k, rho B_k), their quantization at scale 2^k (G, R and
+// Gamma_1(alpha_k) as 4 limbs in g1), and the float64 / integer steps of an
+// iteration around the encrypted node step.  T: Nk x 2Nk doubles; rp: 2Nk;
+// f, aty: Nk doubles of workspace.
 hipError_t cs_setup_node(const double* A, const double* y, int M, int N, int k0, int Nk,
-                         double rho, int k, double* T, double* rp, double* f, double* aty,
-                         double* alpha, double* rhoB, uint64_t* G, uint64_t* R, uint32_t* g1,
-                         int* err, void* stream);
+                         double rho, double* T, double* rp, double* f, double* aty,
+                         double* alpha, double* rhoB, void* stream);
+hipError_t cs_quantize_node(const double* rhoB, const double* alpha, int Nk, int k, uint64_t* G,
+                            uint64_t* R, uint32_t* g1, int* err, void* stream);
 // every node at once over N = K Nk elements (S: K sums, R: [K][Nk])
 hipError_t cs_quant_zv(const double* z, const double* v, int N, int K, int k, uint64_t* wz,
                        uint64_t* wv, uint64_t* S, int* err, void* stream);

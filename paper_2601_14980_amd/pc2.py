@@ -50,7 +50,8 @@ EXPORTS = [
     "pc2_decrypt", "pc2_decrypt_static",
     "pc2_hom_add", "pc2_hom_scalar_mul", "pc2_hom_sum", "pc2_enc_sum_dec",
     "pc2_matvec_create", "pc2_matvec_info", "pc2_matvec_load", "pc2_matvec_apply",
-    "pc2_matvec_destroy", "pc2_colsplit_create", "pc2_colsplit_iterate", "pc2_colsplit_destroy",
+    "pc2_matvec_destroy", "pc2_colsplit_create", "pc2_colsplit_set_scale",
+    "pc2_colsplit_iterate", "pc2_colsplit_destroy",
     "pc2_batch_create", "pc2_batch_run", "pc2_batch_destroy", "pc2_autotune",
     "pc2_runner_create", "pc2_runner_group_size", "pc2_runner_launch", "pc2_runner_destroy",
     "pc2_pk_context", "pc2_server_create", "pc2_serve_submit", "pc2_serve_poll",
@@ -118,6 +119,7 @@ def _load() -> ctypes.CDLL:
         "pc2_matvec_destroy": (c_int, [P]),
         "pc2_colsplit_create": (c_int, [P, P, P, c_uint32, c_uint32, c_uint32, c_double,
                                         c_uint32, P, c_size_t, P, POINTER(P)]),
+        "pc2_colsplit_set_scale": (c_int, [P, c_uint32, P]),
         "pc2_colsplit_iterate": (c_int, [P, c_double, c_int, P, P, P, P]),
         "pc2_colsplit_destroy": (c_int, [P]),
         "pc2_batch_create": (c_int, [P, POINTER(pc2_job), c_size_t, POINTER(P)]),

@@ -39,6 +39,7 @@ def _rel(a, b):
     (40, 90, 3, 1.0, 30, 256, 6),
     (120, 600, 3, 1.5, 40, 1024, 3),
     (30, 20, 1, 0.5, 24, 2048, 4),       # one node; rho < 1 scales the threshold up
+    (90, 300, 3, 1.0, 46, 2048, 3),      # Delta = 1e15 on [-8, 8): the paper's finest scale
 ])
 def test_colsplit_matches_oracle(gpu_ctx, M, N, K, rho, k, nbits, iters):
     from paper_2601_14980_amd import pc2
@@ -66,6 +67,37 @@ def test_colsplit_matches_oracle(gpu_ctx, M, N, K, rho, k, nbits, iters):
                 exact &= bool(np.array_equal(g, o))
         print(f"quantized={quantized}: bit-identical to the oracle: {exact}")
         cs.close()
+
+
+def test_colsplit_set_scale_matches_oracle(gpu_ctx):
+    """One object quantized again at each scale of a sweep (the float64 setup
+    kept) gives the iterates of the oracle created at that scale."""
+    from paper_2601_14980_amd import pc2
+    from paper_2601_14980_amd.colsplit import ColumnSplitLasso
+    M, N, K, rho, nbits, iters = 60, 240, 3, 1.0, 2048, 3
+    A, y = _data(M, N, 7)
+    lam = 0.1 * float(np.max(np.abs(A.T @ y)))
+    p, q = gen.primes_for(15, nbits)
+    sk = pc2.SecretKey(gpu_ctx, nbits, p, q)
+    pool = pc2.to_device_limbs(gen.gen_r_limbs(p * q, 3 * N, sk.L, 15))
+    Ad, yd = torch.from_numpy(A).cuda(), torch.from_numpy(y).cuda()
+    cs = ColumnSplitLasso(gpu_ctx, sk, Ad, yd, K, rho, 20, pool)
+    for k in (46, 13, 33):
+        cs.set_scale(k)
+        cs.x.zero_(), cs.z.zero_(), cs.v.zero_()
+        ref = C.ColumnSplitLasso(A, y, K, rho, k)
+        z, v = np.zeros(N), np.zeros(N)
+        for t in range(iters):
+            cs.iterate(lam, True)
+            x, z, v = ref.iterate(z, v, lam, True)
+        assert gpu_ctx.sync() == 0
+        for name, g, o in (("x", cs.x, x), ("z", cs.z, z), ("v", cs.v, v)):
+            assert _rel(g.cpu().numpy(), o) <= 1e-12, f"{name} at 2^{k}"
+    with pytest.raises(pc2.PC2Error):           # 2 k + 9 + log2 Nk above 126 bits
+        cs.set_scale(60)
+    cs.iterate(lam, True)                        # the last good scale still runs
+    assert gpu_ctx.sync() == 0
+    cs.close()
 
 
 def test_colsplit_quantized_close_to_plain(gpu_ctx):

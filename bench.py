@@ -132,22 +132,84 @@ def _oracle_job(args):
     return O.decrypt(key, a)
 
 
-def cpu_baseline(p: int, q: int, ms, rs, cts, budget_s: float = 20.0) -> dict:
-    """The oracle as it stands, on every host core, over a bounded sample."""
+# key sizes of the oracle timing and the seeds of their keys (the workloads'
+# own keys: tiny, batching 1024-bit, main 2048-bit, lasso 3072-bit)
+CPU_SIZES = ((256, 1), (1024, 3), (2048, 2), (3072, 4))
+CPU_ONE_CORE = 8
+
+
+def cpu_baseline(pc2, gen, ctx, torch, np) -> dict:
+    """The oracle as it stands, timed on the host's cores: per key size,
+    max(256, 8 cores) encryptions and as many decryptions over every core
+    (a process pool), and CPU_ONE_CORE of each in this process alone.  The
+    same (m, r) are encrypted and the resulting ciphertexts decrypted by the
+    GPU, and every oracle output is compared with the GPU's."""
     from oracle import paillier as O
+    from workload.limbs import ints_from_limbs, to_limbs
     cores = len(os.sched_getaffinity(0))
-    pk, sk = O.derive_keys(p, q)
-    per_core = 6
-    n_enc = n_dec = per_core * cores
-    jobs = [("enc", pk, ms[i % len(ms)], rs[i % len(rs)]) for i in range(n_enc)]
-    jobs += [("dec", sk, cts[i % len(cts)], None) for i in range(n_dec)]
-    t0 = time.perf_counter()
+    count = max(256, 8 * cores)
+    rows, exact = {}, True
     with mp.get_context("fork").Pool(cores) as pool:
-        pool.map(_oracle_job, jobs, chunksize=1)
-    dt = time.perf_counter() - t0
-    return {"value": (n_enc + n_dec) / dt, "unit": "ops/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_enc} encryptions + {n_dec} decryptions of the same 2048-bit "
-                      f"workload ({dt:.1f} s wall, multiprocessing pool of {cores})"}
+        for bits, seed in CPU_SIZES:
+            p, q = gen.primes_for(seed, bits)
+            n = p * q
+            pk, sk = O.derive_keys(p, q)
+            rng = np.random.default_rng(gen.seed_seq(seed, gen.DATA, 77))
+            ms = [int(v) for v in rng.integers(0, 1 << 24, size=count)]
+            rs = gen.gen_r(n, count, seed, extra=77)
+            gsk = pc2.SecretKey(ctx, bits, p, q)
+            L = gsk.L
+            c_dev = torch.empty((count, 2 * L), dtype=torch.int32, device="cuda")
+            m_dev = torch.empty((count, L), dtype=torch.int32, device="cuda")
+            pc2.pc2_encrypt(gsk.public, pc2.to_device_limbs(to_limbs(ms, 1)),
+                            pc2.to_device_limbs(to_limbs(rs, L)), c_dev)
+            pc2.pc2_decrypt(gsk, c_dev, m_dev)
+            if ctx.sync() != 0:
+                raise RuntimeError("device reported a data error in the oracle sample")
+            c_gpu = ints_from_limbs(pc2.from_device_limbs(c_dev))
+            m_gpu = ints_from_limbs(pc2.from_device_limbs(m_dev))
+            gsk.close()
+            t0 = time.perf_counter()
+            c_cpu = pool.map(_oracle_job, [("enc", pk, m, r) for m, r in zip(ms, rs)], chunksize=1)
+            t1 = time.perf_counter()
+            m_cpu = pool.map(_oracle_job, [("dec", sk, c, None) for c in c_gpu], chunksize=1)
+            t2 = time.perf_counter()
+            k = CPU_ONE_CORE
+            for j in range(k):
+                c_cpu[j] = O.encrypt(pk, ms[j], rs[j])
+            t3 = time.perf_counter()
+            for j in range(k):
+                m_cpu[j] = O.decrypt(sk, c_gpu[j])
+            t4 = time.perf_counter()
+            same = c_cpu == c_gpu and m_cpu == m_gpu and m_gpu == ms
+            exact &= same
+            rows[str(bits)] = {
+                "enc_per_s": round(count / (t1 - t0), 2), "dec_per_s": round(count / (t2 - t1), 2),
+                "enc_dec_ops_per_s": round(2 * count / (t2 - t0), 2),
+                "one_core_enc_per_s": round(k / (t3 - t2), 3),
+                "one_core_dec_per_s": round(k / (t4 - t3), 3),
+                "equal_to_gpu": same}
+            log(f"oracle {bits}-bit: {rows[str(bits)]['enc_dec_ops_per_s']} enc+dec ops/s on "
+                f"{cores} cores, one core {rows[str(bits)]['one_core_enc_per_s']} enc/s, "
+                f"equal to the GPU: {same}")
+    main = rows["2048"]
+    return {"value": main["enc_dec_ops_per_s"], "unit": "ops/s", "cores": cores, "kind": "oracle",
+            "sample": f"{count} encryptions + {count} decryptions per key size (256, 1024, 2048, "
+                      f"3072 bits) over a pool of {cores} processes, {CPU_ONE_CORE} + "
+                      f"{CPU_ONE_CORE} on one core; value: the 2048-bit enc+dec rate on all "
+                      f"cores; every oracle output compared with the GPU's",
+            "cpu_model": _cpu_model(), "by_key_bits": rows, "all_equal_to_gpu": bool(exact)}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
 
 
 # ------------------------------------------------------- batching (config 3)
@@ -281,10 +343,15 @@ SERVE_MAX_AGE = 1.0
 def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
     """Poisson arrivals of encrypt / aggregate / decrypt requests (1/3 each),
     lengths log-uniform in [256, 65536], the 2048-bit key resident, K ~ U{2..8}
-    resident ciphertext vectors per aggregate, admission by a 4 GiB budget,
-    served by libpc2's request server.  Run at the configured 2000 req/s
-    (overload: latency is queueing) and at 0.7x the capacity that run
-    measured."""
+    resident ciphertext vectors per aggregate, admission by a 4 GiB budget.
+
+    The plain path serves the configured trace (2000 req/s) one request at a
+    time in arrival order, each as one synchronous call (one launch per call,
+    no batching or overlap); its outputs are every request's result run
+    alone.  libpc2's request server then serves the same trace at 2000 req/s
+    (overload: latency is queueing) and at 0.7x the capacity it measured
+    there (the same requests, arrivals spread out), and every request's
+    output of every served run is compared with its alone result."""
     from paper_2601_14980_amd.serve import Request, percentile, serve_trace
     import random
     L = sk.L
@@ -308,6 +375,8 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
         raise RuntimeError("device reported a data error while warming the pool")
 
     def make_trace(n, rate, seed):
+        """n requests; the same seed gives the same requests at any rate
+        (only the gaps between arrivals scale)."""
         r = random.Random(seed)
         t, out = 0.0, []
         for i in range(n):
@@ -331,57 +400,86 @@ def run_serving(pc2, gen, ctx, sk, torch, np, args) -> dict:
         return out
 
     budget = 4 << 30
+    n = args.serve_requests
+    enc_dec = lambda reqs: sum(r.length for r in reqs if r.op in ("encrypt", "decrypt"))
 
-    def alone_equal(req) -> bool:
-        job = req.payload
-        ref = torch.empty_like(job["out"])
-        if req.op == "encrypt":
-            pc2.pc2_encrypt(sk.public, job["m"], job["r"], ref)
-        elif req.op == "aggregate":
-            pc2.pc2_hom_sum(sk.public, [c[:req.length] for c in job["inputs"]], ref)
-        else:
-            pc2.pc2_decrypt(sk, job["c"], ref)
-        return bool(torch.equal(ref, job["out"]))
+    def summary(reqs, span):
+        lat = [r.latency for r in reqs]
+        return dict(requests=len(reqs),
+                    rate_req_per_s=round(len(reqs) / max(reqs[-1].arrival - reqs[0].arrival,
+                                                         1e-9), 1),
+                    p50_ms=round(1e3 * percentile(lat, 50), 2),
+                    p99_ms=round(1e3 * percentile(lat, 99), 2),
+                    makespan_s=round(span, 3),
+                    enc_dec_ops_per_s=round(enc_dec(reqs) / span, 1),
+                    elements_per_s=round(sum(r.length for r in reqs) / span, 1))
 
-    def serve(reqs, policy=pc2.PC2_SERVE_FAIR):
+    def plain(reqs):
+        """One request at a time in arrival order, each one synchronous call."""
+        clock = time.perf_counter
+        start = clock()
+        for r in reqs:
+            r.arrival += start
+        for r in sorted(reqs, key=lambda q: (q.arrival, q.rid)):
+            while clock() < r.arrival:
+                time.sleep(min(1e-3, max(0.0, r.arrival - clock())))
+            job = r.payload
+            if r.op == "encrypt":
+                pc2.pc2_encrypt(sk.public, job["m"], job["r"], job["out"])
+            elif r.op == "aggregate":
+                pc2.pc2_hom_sum(sk.public, [c[:r.length] for c in job["inputs"]], job["out"])
+            else:
+                pc2.pc2_decrypt(sk, job["c"], job["out"])
+            if ctx.sync() != 0:
+                raise RuntimeError("device reported a data error on the plain path")
+            r.completed = clock()
+        return clock() - start
+
+    def serve(reqs, ref, policy):
         srv = pc2.Server(ctx, sk, hbm_budget=budget, tick_groups=args.serve_tick_groups,
-                         max_requests=1024)
+                         max_requests=max(1024, 2 * len(reqs)))
         srv.set_policy(policy, SERVE_MAX_AGE)
         span = serve_trace(srv, reqs)
         torch.cuda.synchronize()
         st = srv.stats()
         srv.close()
-        lat = [r.latency for r in reqs]
-        ed = sum(r.length for r in reqs if r.op in ("encrypt", "decrypt"))
-        sample = [reqs[i] for i in (0, len(reqs) // 2, len(reqs) - 1)]
-        return dict(requests=len(reqs),
-                    rate_req_per_s=round(len(reqs) / max(reqs[-1].arrival - reqs[0].arrival
-                                                         + 1e-9, 1e-9), 1),
-                    p50_ms=round(1e3 * percentile(lat, 50), 2),
-                    p99_ms=round(1e3 * percentile(lat, 99), 2),
-                    makespan_s=round(span, 3), launches=st["launches"],
-                    enc_dec_ops_per_s=round(ed / span, 1),
-                    max_hbm_bytes=st["max_bytes"],
-                    sampled_requests_equal_alone=all(alone_equal(r) for r in sample))
+        if ctx.sync() != 0:
+            raise RuntimeError("device reported a data error while serving")
+        out = summary(reqs, span)
+        out.update(launches=st["launches"], max_hbm_bytes=st["max_bytes"],
+                   all_requests_equal_alone=all(torch.equal(a.payload["out"], b.payload["out"])
+                                                for a, b in zip(reqs, ref)))
+        return out
 
-    n = args.serve_requests
-    hot = serve(make_trace(n, 2000.0, SERVE_SEED), pc2.PC2_SERVE_SHORTEST)
+    ref = make_trace(n, 2000.0, SERVE_SEED)
+    plain_run = summary(ref, plain(ref))
+    log(f"serving (plain path, {n} requests): p50 {plain_run['p50_ms']} ms p99 "
+        f"{plain_run['p99_ms']} ms, {plain_run['enc_dec_ops_per_s']} enc+dec ops/s")
+    hot = serve(make_trace(n, 2000.0, SERVE_SEED), ref, pc2.PC2_SERVE_SHORTEST)
     cap = hot["requests"] / hot["makespan_s"]
-    sub = serve(make_trace(n, 0.7 * cap, SERVE_SEED + 1), pc2.PC2_SERVE_SHORTEST)
-    hot_f = serve(make_trace(n, 2000.0, SERVE_SEED), pc2.PC2_SERVE_FAIR)
-    sub_f = serve(make_trace(n, 0.7 * cap, SERVE_SEED + 1), pc2.PC2_SERVE_FAIR)
-    if ctx.sync() != 0:
-        raise RuntimeError("device reported a data error while serving")
-    for name, h, u in (("shortest first", hot, sub), ("fair share", hot_f, sub_f)):
+    sub = serve(make_trace(n, 0.7 * cap, SERVE_SEED), ref, pc2.PC2_SERVE_SHORTEST)
+    runs = [("shortest first", hot, sub)]
+    out = {"workload": f"{n} requests per run, Poisson arrivals, encrypt/aggregate/decrypt 1/3 "
+                       "each, lengths log-uniform [256, 65536], 2048-bit key, HBM budget 4 GiB, "
+                       "libpc2 request server; the plain path serves the same trace one "
+                       "synchronous call per request",
+           "tick_groups": args.serve_tick_groups,
+           "policy": f"shortest remaining first, requests older than {SERVE_MAX_AGE} s first",
+           "configured_2000_req_s": hot, "sub_saturation_0p7_capacity": sub,
+           "plain_path_2000_req_s": plain_run,
+           "served_over_plain": round(hot["enc_dec_ops_per_s"] / plain_run["enc_dec_ops_per_s"],
+                                      3)}
+    if args.serve_fair:
+        hot_f = serve(make_trace(n, 2000.0, SERVE_SEED), ref, pc2.PC2_SERVE_FAIR)
+        sub_f = serve(make_trace(n, 0.7 * cap, SERVE_SEED), ref, pc2.PC2_SERVE_FAIR)
+        runs.append(("fair share", hot_f, sub_f))
+        out["fair_share"] = {"configured_2000_req_s": hot_f, "sub_saturation_0p7_capacity": sub_f}
+    for name, h, u in runs:
         log(f"serving ({name}): offered 2000 req/s -> p50 {h['p50_ms']} ms p99 {h['p99_ms']} ms; "
-            f"at 0.7x capacity ({0.7 * cap:.0f} req/s) p50 {u['p50_ms']} ms p99 {u['p99_ms']} ms")
-    return {"workload": f"{n} requests per run, Poisson arrivals, encrypt/aggregate/decrypt 1/3 each, "
-                        "lengths log-uniform [256, 65536], 2048-bit key, HBM budget 4 GiB, "
-                        "libpc2 request server",
-            "tick_groups": args.serve_tick_groups,
-            "policy": f"shortest remaining first, requests older than {SERVE_MAX_AGE} s first",
-            "configured_2000_req_s": hot, "sub_saturation_0p7_capacity": sub,
-            "fair_share": {"configured_2000_req_s": hot_f, "sub_saturation_0p7_capacity": sub_f}}
+            f"at 0.7x capacity ({0.7 * cap:.0f} req/s) p50 {u['p50_ms']} ms p99 {u['p99_ms']} ms; "
+            f"every request equal alone: {h['all_requests_equal_alone']} / "
+            f"{u['all_requests_equal_alone']}")
+    return out
 
 
 # ------------------------------------------------------------- ADMM (config 4)
@@ -395,17 +493,21 @@ COLSPLIT_SEED = 8
 
 
 def run_colsplit(pc2, gen, ctx, sk, torch, np, args) -> dict:
-    """Algorithm 1 with A split by columns: A M x N ~ N(0, 1/M) (the paper's
-    3000 x 27000 over 3 nodes reduced tenfold by default), x* 5 %-sparse with
-    N(0,1) nonzeros, noise 1e-3, rho = 1, lambda = 0.1 ||A^T y||_inf, the
-    2048-bit key.  For each quantization scale 2^k the encrypted loop runs T
-    iterations beside the float64 loop without quantization; reported: the
-    mean squared difference of z between the two (the quantization error the
-    paper's Delta sweep measures), the MSE of each against x*, and the time of
+    """Algorithm 1 with A split by columns, at the paper's shape by default:
+    A 3000 x 27000 ~ N(0, 1/M) over 3 nodes of 9000 columns, x* 5 %-sparse
+    with N(0,1) nonzeros, noise 1e-3, rho = 1, lambda = 0.1 ||A^T y||_inf,
+    the 2048-bit key.  The float64 set-up runs once; the float64 loop without
+    quantization runs T iterations; then for each quantization scale 2^k of
+    the sweep (Delta = 16 2^k on [-8, 8): k = 13 .. 46 spans Delta = 1e5 ..
+    1e15) the object is quantized again and the encrypted loop runs T
+    iterations from zero.  Reported per scale: the mean squared and largest
+    difference of z from the float64 loop's (the quantization loss the
+    paper's Delta sweep measures), the MSE of z against x*, and the time of
     one encrypted iteration (encrypt 2N, hom_add N, K ciphertext mat-vecs of
     N/K x N/K, decrypt N, inverse quantization, update)."""
     from paper_2601_14980_amd.colsplit import ColumnSplitLasso
     M, N, K, T = args.colsplit_m, args.colsplit_n, 3, args.colsplit_iters
+    scales = args.colsplit_scales
     rng = np.random.default_rng(gen.seed_seq(COLSPLIT_SEED, gen.DATA))
     A = rng.standard_normal((M, N)) / np.sqrt(M)
     xs = np.zeros(N)
@@ -414,40 +516,49 @@ def run_colsplit(pc2, gen, ctx, sk, torch, np, args) -> dict:
     y = A @ xs + 1e-3 * rng.standard_normal(M)
     lam = 0.1 * float(np.max(np.abs(A.T @ y)))
     Ad, yd = torch.from_numpy(A).cuda(), torch.from_numpy(y).cuda()
+    del A
     pool = pc2.to_device_limbs(gen.gen_r_limbs(sk.n, 3 * N, sk.L, COLSPLIT_SEED))
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    sweep = []
-    zp = None
-    for k in args.colsplit_scales:
-        t0 = time.perf_counter()
-        cs = ColumnSplitLasso(ctx, sk, Ad, yd, K, 1.0, k, pool)
-        setup_s = time.perf_counter() - t0
-        if zp is None:
-            for _ in range(T):
-                cs.iterate(lam, quantized=False)
-            torch.cuda.synchronize()
-            zp = cs.z.cpu().numpy()
-            cs.x.zero_(), cs.z.zero_(), cs.v.zero_()
+    t0 = time.perf_counter()
+    cs = ColumnSplitLasso(ctx, sk, Ad, yd, K, 1.0, scales[0], pool)
+    setup_s = time.perf_counter() - t0
+    log(f"colsplit {M}x{N} over {K} nodes: set-up {setup_s:.1f} s")
+
+    def loop(quantized):
+        cs.x.zero_(), cs.z.zero_(), cs.v.zero_()
         ms = []
         for _ in range(T):
             ev[0].record(stream)
-            cs.iterate(lam, quantized=True)
+            cs.iterate(lam, quantized=quantized)
             ev[1].record(stream)
             torch.cuda.synchronize()
             ms.append(ev[0].elapsed_time(ev[1]))
         if ctx.sync() != 0:
             raise RuntimeError("device reported a data error in the column-split loop")
-        zq = cs.z.cpu().numpy()
-        cs.close()
-        row = {"log2_scale": k, "mse_vs_float64": float(np.mean((zq - zp) ** 2)),
+        return cs.z.cpu().numpy(), float(np.median(ms))
+
+    zp, plain_ms = loop(False)
+    sweep = []
+    for i, k in enumerate(scales):
+        t1 = time.perf_counter()
+        if i:
+            cs.set_scale(k)
+        rescale_s = time.perf_counter() - t1
+        zq, it_ms = loop(True)
+        row = {"log2_scale": k, "delta": 16 * 2 ** k,
+               "mse_vs_float64": float(np.mean((zq - zp) ** 2)),
+               "max_abs_vs_float64": float(np.max(np.abs(zq - zp))),
                "mse_vs_xstar": float(np.mean((zq - xs) ** 2)),
-               "iteration_ms": round(float(np.median(ms)), 2), "setup_s": round(setup_s, 2)}
+               "iteration_ms": round(it_ms, 2), "quantize_again_s": round(rescale_s, 2)}
         sweep.append(row)
         log(f"colsplit 2^{k}: MSE vs float64 {row['mse_vs_float64']:.3e}, vs x* "
             f"{row['mse_vs_xstar']:.3e}, {row['iteration_ms']:.1f} ms per iteration")
+    cs.close()
     return {"workload": f"A {M}x{N} ~ N(0,1/{M}) split by columns over {K} nodes, x* 5% sparse, "
-                        f"noise 1e-3, rho 1, lambda {lam:.4g}, 2048-bit key, {T} iterations",
+                        f"noise 1e-3, rho 1, lambda {lam:.4g}, 2048-bit key, {T} iterations "
+                        f"per scale from zero",
+            "setup_s": round(setup_s, 2), "float64_iteration_ms": round(plain_ms, 2),
             "float64_mse_vs_xstar": float(np.mean((zp - xs) ** 2)), "sweep": sweep}
 
 
@@ -662,10 +773,55 @@ def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
                        "enc_dec_ops_per_s": round((K * N + N) / mt, 1),
                        "mse_z_vs_xstar": float(np.mean((zh - xstar) ** 2)),
                        "nnz_z": int(np.count_nonzero(zh))}
-    drv.close()
     if len(final) > 1:
         vals = list(final.values())
         out["engines_agree_exactly"] = all(np.array_equal(vals[0], v) for v in vals[1:])
+
+    # Accuracy over a long run: the encrypted aggregate Dec(prod_k Enc(m_k))
+    # equals the integer sum of the quantized m_k (no wrap mod n), so the
+    # encrypted loop's iterates are those of the loop that sums the quantized
+    # values exactly (checked against the encrypted run above after the same
+    # number of iterations); it runs T iterations beside the float64 loop
+    # without quantization.  The integer sum over the nodes is torch's (int64,
+    # exact); every other step is the library's.
+    T, t_check = args.admm_mse_iters, args.admm_warmup + args.admm_iters
+    runs, snap = {}, None
+    for quantized in (True, False):
+        z = torch.zeros(N, dtype=torch.float64, device="cuda")
+        u = torch.zeros((K, N), dtype=torch.float64, device="cuda")
+        for it in range(T):
+            drv.local(z, u)
+            if quantized:
+                pc2.pc2_quantize(ctx, qa.log2_scale, qa.offset, qa.delta, drv.xu.reshape(-1),
+                                 drv.m)
+                msum = drv.m.view(K, N).sum(dim=0)
+                pc2.pc2_dequantize(ctx, qa.log2_scale, qa.offset,
+                                   msum.view(torch.int32).reshape(N, 2), K, drv.total)
+            else:
+                torch.sum(drv.xu, dim=0, out=drv.total)
+            drv.consensus(z, u)
+            if quantized and it + 1 == t_check:
+                snap = z.cpu().numpy()
+        if ctx.sync() != 0:
+            raise RuntimeError("device reported a data error in the plaintext lasso loops")
+        runs[quantized] = z.cpu().numpy()
+    drv.close()
+    zq, zf = runs[True], runs[False]
+    out["long_run"] = {
+        "iterations": T,
+        "mse_quantized_vs_float64": float(np.mean((zq - zf) ** 2)),
+        "max_abs_quantized_vs_float64": float(np.max(np.abs(zq - zf))),
+        "mse_z_vs_xstar_quantized": float(np.mean((zq - xstar) ** 2)),
+        "mse_z_vs_xstar_float64": float(np.mean((zf - xstar) ** 2)),
+        "nnz_z": int(np.count_nonzero(zq)),
+        "quantized_loop_equals_encrypted": bool(snap is not None and "valu" in final
+                                                and np.array_equal(snap, final["valu"])),
+    }
+    log(f"admm long run ({T} iterations): MSE quantized vs float64 "
+        f"{out['long_run']['mse_quantized_vs_float64']:.3e}, vs x* "
+        f"{out['long_run']['mse_z_vs_xstar_quantized']:.3e} (float64 "
+        f"{out['long_run']['mse_z_vs_xstar_float64']:.3e}); quantized loop equals the encrypted "
+        f"one: {out['long_run']['quantized_loop_equals_encrypted']}")
     return out
 
 
@@ -680,21 +836,25 @@ def main() -> int:
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-fair", action="store_true",
+                    help="also serve both loads under the fair-share policy")
     ap.add_argument("--serve-tick-groups", type=int, default=2048,
                     help="element groups per serving launch (16 encryptions each at 2048 bits)")
     ap.add_argument("--no-admm", action="store_true")
     ap.add_argument("--no-matvec", action="store_true")
     ap.add_argument("--no-key4096", action="store_true")
     ap.add_argument("--no-colsplit", action="store_true")
-    ap.add_argument("--colsplit-m", type=int, default=300)
-    ap.add_argument("--colsplit-n", type=int, default=2700)
-    ap.add_argument("--colsplit-iters", type=int, default=10)
-    ap.add_argument("--colsplit-scales", type=int, nargs="+", default=[16, 24, 32, 40])
+    ap.add_argument("--colsplit-m", type=int, default=3000)
+    ap.add_argument("--colsplit-n", type=int, default=27000)
+    ap.add_argument("--colsplit-iters", type=int, default=5)
+    ap.add_argument("--colsplit-scales", type=int, nargs="+", default=[13, 23, 33, 46])
     ap.add_argument("--key4096-count", type=int, default=32768)
     ap.add_argument("--matvec-dim", type=int, default=9000)
     ap.add_argument("--admm-iters", type=int, default=2)
     ap.add_argument("--admm-warmup", type=int, default=1)
+    ap.add_argument("--admm-mse-iters", type=int, default=200,
+                    help="iterations of the lasso accuracy run (plaintext-equivalent loops)")
     ap.add_argument("--admm-modmul", default="valu,mfma",
                     help="Montgomery engines to run the lasso leg with (comma-separated)")
     ap.add_argument("--modmul", choices=("valu", "mfma"), default="valu",
@@ -755,6 +915,7 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     enc_ms: list[float] = []
+    sum_ms: list[float] = []
     dec_ms: list[float] = []
 
     def step_batched(record: bool) -> None:
@@ -770,6 +931,7 @@ def main() -> int:
         if record:
             torch.cuda.synchronize()
             enc_ms.append(ev[0].elapsed_time(ev[1]))
+            sum_ms.append(ev[1].elapsed_time(ev[2]))
             dec_ms.append(ev[2].elapsed_time(ev[3]))
 
     def step_plain() -> None:
@@ -831,6 +993,25 @@ def main() -> int:
     del c_sk
     log(f"key-holder encryption: {enc_sk_ms:.1f} ms, identical ciphertexts: {enc_sk_same}")
 
+    # the fused path (Dec(prod_k Enc(m_k, r_k)) in one call, the ciphertexts
+    # never written out) on the same inputs, against the three calls of a step
+    m_nodes = [m2_all[k * LENGTH:(k + 1) * LENGTH] for k in range(NODES)]
+    r_nodes = [r_all[k * LENGTH:(k + 1) * LENGTH] for k in range(NODES)]
+    fused_out = torch.empty_like(msum)
+    fused_ms = []
+    for rep in range(2):                      # rep 0 warms up
+        ev[0].record(stream)
+        pc2.pc2_enc_sum_dec(sk, m_nodes, r_nodes, fused_out)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            fused_ms.append(ev[0].elapsed_time(ev[1]))
+    fused_same = bool(torch.equal(fused_out, msum)) and ctx.sync() == 0
+    unfused_ms = (sum(enc_ms) + sum(sum_ms) + sum(dec_ms)) / len(enc_ms)
+    del fused_out
+    log(f"fused enc->sum->dec: {fused_ms[0]:.1f} ms vs {unfused_ms:.1f} ms unfused, "
+        f"identical: {fused_same}")
+
     # plain path
     t_plain = []
     for i in range(args.plain_steps):
@@ -849,12 +1030,8 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        from workload.limbs import ints_from_limbs
-        ms_s = [int(v) for v in m_host[0, :64]]
-        rs_s = ints_from_limbs(rs[0][:64])
-        cts = ints_from_limbs(pc2.from_device_limbs(agg[:64]))
         log("timing the oracle on the host cores")
-        cpu = cpu_baseline(p, q, ms_s, rs_s, cts)
+        cpu = cpu_baseline(pc2, gen, ctx, torch, np)
 
     batching = None if args.no_batching else run_batching(pc2, gen, ctx, torch, np, args)
     serving = None if args.no_serving else run_serving(pc2, gen, ctx, sk, torch, np, args)
@@ -885,6 +1062,11 @@ def main() -> int:
         "dec_per_s": round(LENGTH / (sum(dec_ms) / len(dec_ms) / 1e3), 1),
         "key_holder_enc_per_s": round(total / (enc_sk_ms / 1e3), 1),
         "key_holder_enc_identical": enc_sk_same,
+        "fused": {"enc_sum_dec_ms": round(fused_ms[0], 2), "unfused_ms": round(unfused_ms, 2),
+                  "fused_over_unfused": round(unfused_ms / fused_ms[0], 3),
+                  "identical": fused_same,
+                  "unfused": "encrypt 524288 + 8-way hom_sum + decrypt 65536 (per-call event "
+                             "times of the timed steps)"},
         "plain": ({"value": round(plain_value, 1), "unit": "ops/s",
                    "ms_per_step": round(1e3 * sum(t_plain) / len(t_plain), 2)}
                   if t_plain else None),

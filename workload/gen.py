@@ -6,6 +6,7 @@ gives one independent stream per (configuration, purpose).  Prime search uses
 """
 from __future__ import annotations
 
+import functools
 import math
 import random
 from dataclasses import dataclass
@@ -56,6 +57,7 @@ def gen_primes(nbits: int, seed: int) -> tuple[int, int]:
     return p, q
 
 
+@functools.lru_cache(maxsize=None)
 def primes_for(config: int, nbits: int, extra: int = 0) -> tuple[int, int]:
     seed = int(seed_seq(config, KEYS, extra).generate_state(1)[0])
     return gen_primes(nbits, seed)

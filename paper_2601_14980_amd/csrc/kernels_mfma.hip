@@ -3,11 +3,13 @@
 //
 // One wavefront per element (mfma_mont.hpp); workgroups stride over the
 // elements.  Per element: g^m = MM(m, n R) + 1 (exact: m n < n^2); r R =
-// MM(r, R^2); a table of (r R)^k, k < 2^w, in the workgroup's scratch slot;
-// left-to-right fixed windows over n (zero windows skipped); one product
-// with g^m leaves normal form; a conditional subtraction of n^2 makes it
-// canonical.  Data errors (m >= n, r = 0, r >= n) zero the element and set
-// ERR_RANGE.
+// MM(r, R^2); the odd powers (r R)^(2j+1) R^-2j, j < 2^(w-1), in the
+// workgroup's scratch slot (after (r R)^2 R^-1, the slot's last entry);
+// left-to-right sliding windows over n from the key's precomputed schedule
+// (the VALU kernels' schedule: square nsq times, then multiply by an odd
+// power); one product with g^m leaves normal form; a conditional
+// subtraction of n^2 makes it canonical.  Data errors (m >= n, r = 0,
+// r >= n) zero the element and set ERR_RANGE.
 #include <hip/hip_runtime.h>
 
 #include "engine.hpp"
@@ -33,8 +35,12 @@ __global__ __launch_bounds__(64, 2) void k_encrypt_mfma(PkConst pk, const uint32
   const pc2m::MConst& K = pk.mf;
   uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::FB << w);
   const int L = pk.L;
+  const int half = 1 << (w - 1);                  // odd powers in the table
+  uint8_t* sq = table + (size_t)half * G::FB;     // (r R)^2 R^-1
+  const uint32_t* sched = pk.nsch.p[w - pc2k::SCHED_WMIN];
+  const int nsched = pk.nsch.n[w - pc2k::SCHED_WMIN];
   pc2m::init_work<G>(ws, K, lane);
-  pc2m::init_table<G>(table, 1 << w, lane);
+  pc2m::init_table<G>(table, half + 1, lane);
   uint32_t U[G::NT];
   for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
     const uint32_t* me = m + e * m_limbs;
@@ -43,19 +49,23 @@ __global__ __launch_bounds__(64, 2) void k_encrypt_mfma(PkConst pk, const uint32
     // g^m = 1 + m n
     pc2m::load_x<G>(ws, me, m_limbs, lane);
     pc2m::mont_mul<G>(ws, K.nR, lane, false, ws.gm, true, U);
-    // table entry 1 = r R, entries k = (r R)^k R^-(k-1)
+    // table entry j = (r R)^(2j+1) R^-2j: entry 0 = r R, the square, then
+    // one product by the square per entry
     pc2m::load_x<G>(ws, re, L, lane);
-    pc2m::mont_mul<G>(ws, K.R2, lane, false, table + G::FB, false, U);
-    for (int k = 2; k < (1 << w); ++k)
-      pc2m::mont_mul<G>(ws, table + G::FB, lane, false, table + (size_t)k * G::FB, false, U);
-    // (r R)^n by windows of n, most significant first
-    const int nw = (pk.nbits + w - 1) / w;
-    const uint32_t top = exp_window(pk.n, L, (nw - 1) * w, w);
-    pc2m::load_fwd<G>(ws, table + (size_t)top * G::FB, lane);
-    for (int win = nw - 2; win >= 0; --win) {
-      for (int s = 0; s < w; ++s) pc2m::mont_mul<G>(ws, ws.xf, lane, true, nullptr, false, U);
-      const uint32_t dig = exp_window(pk.n, L, win * w, w);
-      if (dig) pc2m::mont_mul<G>(ws, table + (size_t)dig * G::FB, lane, true, nullptr, false, U);
+    pc2m::mont_mul<G>(ws, K.R2, lane, true, table, false, U);
+    pc2m::mont_mul<G>(ws, ws.xf, lane, false, sq, false, U);
+    pc2m::load_fwd<G>(ws, table, lane);
+    for (int j = 1; j < half; ++j)
+      pc2m::mont_mul<G>(ws, sq, lane, false, table + (size_t)j * G::FB, false, U);
+    // (r R)^n by the sliding-window schedule of n, most significant first
+    pc2m::load_fwd<G>(ws, table + (size_t)((sched[0] & 0xFFFFu) >> 1) * G::FB, lane);
+    for (int si = 1; si < nsched; ++si) {
+      const uint32_t en = sched[si];
+      for (uint32_t k = en >> 16; k; --k)
+        pc2m::mont_mul<G>(ws, ws.xf, lane, true, nullptr, false, U);
+      const uint32_t dig = en & 0xFFFFu;
+      if (dig)
+        pc2m::mont_mul<G>(ws, table + (size_t)(dig >> 1) * G::FB, lane, true, nullptr, false, U);
     }
     // r^n g^m = MM(r^n R, g^m), < 2 n^2
     pc2m::mont_mul<G>(ws, ws.gm, lane, false, nullptr, false, U);

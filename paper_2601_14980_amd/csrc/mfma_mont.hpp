@@ -20,6 +20,13 @@
 // between limbs) leave carries of 0 or 1, and a carry-lookahead over the
 // limbs (two ballots per tile and a multiword add on the scalar unit)
 // settles them.
+//
+// Only what U needs is formed.  T's limbs below S are normalised for q (the
+// carry out of them moves to limb S); its limbs from S up stay as column
+// values and are normalised once, together with those of q N.  Since
+// T + q N = 0 mod R, its part below limb S is c R for an integer c that the
+// two column values just below S fix (every lower limb adds less than
+// 2^-36 to c), so q N is formed only from the tile holding limb S - 2 up.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -39,6 +46,8 @@ struct MGeo {
   static constexpr int FB = PF + D8 + 16;            // bytes of a forward digit array
   static constexpr int NT = (2 * S + 1 + 63) / 64;   // 64-limb tiles of a double-length value
   static constexpr int NTLO = (S + 63) / 64;         // tiles of a product taken mod R
+  static constexpr int QLO = (S - 2) / 64;           // lowest tile of q N that is formed
+  static constexpr int QH = S / 64;                  // tile holding limb S
   static constexpr int TMIN = -3;                    // Toeplitz bands t = TMIN..TMAX
   static constexpr int TMAX = (D + 62) / 64;
   static constexpr int UMIN = -1;                    // forward chunks u that can reach [0, D)
@@ -47,6 +56,7 @@ struct MGeo {
   static constexpr int X0 = 64 * TMAX + 195;         // reversed array: byte X0 - i = digit i
   static constexpr int RB = (X0 + 256 + 15) & ~15;   // bytes of a reversed digit array
   static_assert(NTLO <= NT, "low product within the full one");
+  static_assert(S % 64 != 0 && S >= 3, "limb S lies in the last tile of the low half");
   static_assert((X0 & 3) == 3, "reversed limbs are dword aligned");
   static_assert(4 * S <= RB, "the limb scratch fits in a reversed array");
 };
@@ -92,22 +102,22 @@ __device__ __forceinline__ void load_b(v4i (&B)[G::NU], const uint8_t* y, int la
   }
 }
 
-// Digit sums of x y for the NTQ lowest tiles: x from its reversed array in
+// Digit sums of x y for tiles Q0 .. NTQ - 1: x from its reversed array in
 // LDS (lane (i, g) reads bytes X0 - alpha(i) - 64 t + 16 g .. +16, i.e.
 // digits alpha(i) + 64 t - 16 g - s), y as preloaded B chunks.  Tile Q,
 // lane l: limb 64 Q + l, digit c in accumulator c.
-template <class G, int NTQ>
+template <class G, int NTQ, int Q0 = 0>
 __device__ __forceinline__ void product(v4i (&C)[NTQ], const uint8_t* xr, const v4i (&B)[G::NU],
                                         int lane) {
   const int i = lane & 15;
   const uint8_t* ap = xr + G::X0 - (64 * (i >> 2) + (i & 3)) + 16 * (lane >> 4);
 #pragma unroll
-  for (int q = 0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
+  for (int q = Q0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
 #pragma unroll
   for (int t = G::TMIN; t <= G::TMAX; ++t) {
     bool any = false;
 #pragma unroll
-    for (int q = 0; q < NTQ; ++q) {
+    for (int q = Q0; q < NTQ; ++q) {
       const int u = 4 * q - t;
       any |= (u >= G::UMIN && u <= G::UMAX);
     }
@@ -118,7 +128,7 @@ __device__ __forceinline__ void product(v4i (&C)[NTQ], const uint8_t* xr, const 
     const v4i a = v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
                       (int)(uint32_t)(hi >> 32)};
 #pragma unroll
-    for (int q = 0; q < NTQ; ++q) {
+    for (int q = Q0; q < NTQ; ++q) {
       const int u = 4 * q - t;
       if (u >= G::UMIN && u <= G::UMAX)
         C[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, B[u - G::UMIN], C[q], 0, 0, 0);
@@ -126,12 +136,22 @@ __device__ __forceinline__ void product(v4i (&C)[NTQ], const uint8_t* xr, const 
   }
 }
 
+// the value of lane l (a constant) of a 64-bit register pair, wave-uniform
+__device__ __forceinline__ uint64_t read_lane64(uint64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t fold1(const v4i& c) {
+  return (uint64_t)(uint32_t)c[0] + ((uint64_t)(uint32_t)c[1] << 7) +
+         ((uint64_t)(uint32_t)c[2] << 14) + ((uint64_t)(uint32_t)c[3] << 21);
+}
+
 template <int NTQ>
 __device__ __forceinline__ void fold(uint64_t (&v)[NTQ], const v4i (&C)[NTQ]) {
 #pragma unroll
-  for (int q = 0; q < NTQ; ++q)
-    v[q] = (uint64_t)(uint32_t)C[q][0] + ((uint64_t)(uint32_t)C[q][1] << 7) +
-           ((uint64_t)(uint32_t)C[q][2] << 14) + ((uint64_t)(uint32_t)C[q][3] << 21);
+  for (int q = 0; q < NTQ; ++q) v[q] = fold1(C[q]);
 }
 
 // x[q] += the value of the previous limb (lane - 1 of tile q, or lane 63 of
@@ -215,21 +235,30 @@ __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 // digit array (LDS or global).  The result also goes, as forward digits, to
 // ws.xf (fwd) and to out (if not null); plus_one adds 1 to the result
 // before its carries are resolved.  U: the result's limbs (limb 64 q + lane
-// - S in U[q]).
+// - S in U[q] for q >= QH; the entries below are zero).
 template <class G>
 __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lane, bool fwd,
                                          uint8_t* out, bool plus_one, uint32_t (&U)[G::NT]) {
   v4i B[G::NU];
-  uint64_t v[G::NT];
-  uint32_t T[G::NT];
+  uint64_t v[G::NT];  // column values of T, then of T + q N (limb 64 q + lane)
   {
     v4i C[G::NT];
     load_b<G>(B, y, lane);
     product<G, G::NT>(C, ws.xr, B, lane);
     fold<G::NT>(v, C);
   }
-  normalize<G::NT>(T, v, lane);
-  write_rev<G, G::NT>(ws.tr, T, lane, 0);
+  {
+    // T mod R in 28-bit limbs; the carry out of limb S - 1 lands in limb S
+    // (inside tile NTLO - 1), the limbs above it stay zero
+    uint64_t vl[G::NTLO];
+    uint32_t Tl[G::NTLO];
+#pragma unroll
+    for (int q = 0; q < G::NTLO; ++q) vl[q] = 64 * q + lane < G::S ? v[q] : 0;
+    normalize<G::NTLO>(Tl, vl, lane);
+#pragma unroll
+    for (int q = 0; q < G::NTLO; ++q) v[q] = 64 * q + lane < G::S ? (uint64_t)Tl[q] : v[q] + Tl[q];
+    write_rev<G, G::NTLO>(ws.tr, Tl, lane, 0);
+  }
   wave_sync();
   {
     v4i C[G::NTLO];
@@ -248,15 +277,27 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lan
   {
     v4i C[G::NT];
     load_b<G>(B, ws.nf, lane);
-    product<G, G::NT>(C, ws.qr, B, lane);
-    fold<G::NT>(v, C);
-  }
+    product<G, G::NT, G::QLO>(C, ws.qr, B, lane);
 #pragma unroll
-  for (int q = 0; q < G::NT; ++q) {
-    v[q] += T[q];
-    if (plus_one && 64 * q + lane == G::S) v[q] += 1;
+    for (int q = G::QLO; q < G::NT; ++q) v[q] += fold1(C[q]);
   }
-  normalize<G::NT>(U, v, lane);
+  // c = (the part of T + q N below limb S) / R, from limbs S - 1 and S - 2
+  const uint64_t a = read_lane64(v[(G::S - 1) / 64], (G::S - 1) % 64);
+  const uint64_t b = read_lane64(v[(G::S - 2) / 64], (G::S - 2) % 64);
+  const uint64_t c = (a >> 28) + ((((a & M28) + (b >> 28)) >= (1ull << 27)) ? 1u : 0u);
+  {
+    constexpr int NH = G::NT - G::QH;
+    uint64_t vh[NH];
+    uint32_t Uh[NH];
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      const int limb = 64 * (q + G::QH) + lane;
+      vh[q] = limb < G::S ? 0 : v[q + G::QH] + (limb == G::S ? c + (plus_one ? 1u : 0u) : 0u);
+    }
+    normalize<NH>(Uh, vh, lane);
+#pragma unroll
+    for (int q = 0; q < G::NT; ++q) U[q] = q < G::QH ? 0u : Uh[q - G::QH];
+  }
   write_rev<G, G::NT>(ws.xr, U, lane, G::S);
   if (fwd) write_fwd<G, G::NT>(ws.xf, U, lane, G::S);
   if (out) write_fwd<G, G::NT>(out, U, lane, G::S);

@@ -21,13 +21,13 @@ namespace {
 
 using pc2k::PkConst;
 
+// three wavefronts per SIMD up to 3072-bit keys (a few registers spill at
+// 2048 and 3072 bits, and the launch is still faster than with two); two
+// for 4096-bit keys, where three would spill hundreds of bytes per lane
 template <int S>
-__global__ __launch_bounds__(64, 2) void k_encrypt_mfma(PkConst pk, const uint32_t* __restrict__ m,
-                                                        int m_limbs,
-                                                        const uint32_t* __restrict__ r,
-                                                        uint32_t* __restrict__ c, size_t count,
-                                                        uint8_t* __restrict__ scratch, int w,
-                                                        int* err) {
+__global__ __launch_bounds__(64, S > 256 ? 2 : 3) void k_encrypt_mfma(
+    PkConst pk, const uint32_t* __restrict__ m, int m_limbs, const uint32_t* __restrict__ r,
+    uint32_t* __restrict__ c, size_t count, uint8_t* __restrict__ scratch, int w, int* err) {
   using G = pc2m::MGeo<S>;
   __shared__ __align__(16) pc2m::MWork<G> ws;
   __shared__ uint32_t s_ok;

@@ -88,50 +88,64 @@ __device__ __forceinline__ uint32_t limb_digits(uint32_t v) {
   return (v & 0x7Fu) | ((v << 1) & 0x7F00u) | ((v << 2) & 0x7F0000u) | ((v << 3) & 0x7F000000u);
 }
 
-// B operand chunks of a forward digit array y (LDS or global; digit i at
-// byte PF + i): lane (j, g) takes digits [64 u + 4 j + 16 g, +16).
-template <class G>
-__device__ __forceinline__ void load_b(v4i (&B)[G::NU], const uint8_t* y, int lane) {
-  const int base = 4 * (lane & 15) + 16 * (lane >> 4);
-#pragma unroll
-  for (int u = 0; u < G::NU; ++u) {
-    const int off = 64 * (u + G::UMIN) + base;  // >= -64
-    v4i b = v4i{0, 0, 0, 0};
-    if (off < G::D8) __builtin_memcpy(&b, y + G::PF + off, 16);
-    B[u] = b;
-  }
-}
-
-// Digit sums of x y for tiles Q0 .. NTQ - 1: x from its reversed array in
-// LDS (lane (i, g) reads bytes X0 - alpha(i) - 64 t + 16 g .. +16, i.e.
-// digits alpha(i) + 64 t - 16 g - s), y as preloaded B chunks.  Tile Q,
-// lane l: limb 64 Q + l, digit c in accumulator c.
-template <class G, int NTQ, int Q0 = 0>
-__device__ __forceinline__ void product(v4i (&C)[NTQ], const uint8_t* xr, const v4i (&B)[G::NU],
-                                        int lane) {
+// Digit sums of x y for tiles Q0 .. NTQ - 1.  y: a forward digit array (LDS
+// or global; digit i at byte PF + i); lane (j, g) takes the B chunk of
+// digits [64 u + 4 j + 16 g, +16), read as four dword-aligned words, for
+// every chunk u in one of NPART parts (one part's chunks held in registers
+// at a time).  x: its reversed array in LDS; lane (i, g) takes the Toeplitz
+// band of digits alpha(i) + 64 t - 16 g - s, s < 16, i.e. bytes
+// X0 - alpha(i) - 64 t + 16 g .. +16, which start 3 - i % 4 bytes past a
+// 16-byte boundary: the lane reads the aligned 20 bytes around them and
+// shifts them into place (v_alignbyte), since unaligned LDS reads stall the
+// LDS pipeline.  Tile Q, lane l: limb 64 Q + l, digit c in accumulator c.
+template <class G, int NTQ, int Q0 = 0, int NPART = 1>
+__device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, const uint8_t* y,
+                                          int lane) {
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+  constexpr int NUP = (G::NU + NPART - 1) / NPART;
   const int i = lane & 15;
-  const uint8_t* ap = xr + G::X0 - (64 * (i >> 2) + (i & 3)) + 16 * (lane >> 4);
+  const uint8_t* bp = xr + G::X0 - 3 - 64 * (i >> 2) + 16 * (lane >> 4);  // 16-byte aligned
+  const uint32_t sb = 3u - (uint32_t)(i & 3);
+  const int base = 4 * (lane & 15) + 16 * (lane >> 4);
 #pragma unroll
   for (int q = Q0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
 #pragma unroll
-  for (int t = G::TMIN; t <= G::TMAX; ++t) {
-    bool any = false;
+  for (int part = 0; part < NPART; ++part) {
+    const int ulo = G::UMIN + part * NUP;
+    const int uhi = part == NPART - 1 ? G::UMAX : ulo + NUP - 1;
+    v4i B[NUP];
 #pragma unroll
-    for (int q = Q0; q < NTQ; ++q) {
-      const int u = 4 * q - t;
-      any |= (u >= G::UMIN && u <= G::UMAX);
+    for (int k = 0; k < NUP; ++k) {
+      const int off = 64 * (ulo + k) + base;  // >= -64
+      v4i b = v4i{0, 0, 0, 0};
+      if (ulo + k <= uhi && off < G::D8) {
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(y + G::PF + off);
+        b = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+      }
+      B[k] = b;
     }
-    if (!any) continue;
-    uint64_t lo, hi;  // 16 unaligned bytes as two 8-byte LDS reads
-    __builtin_memcpy(&lo, ap - 64 * t, 8);
-    __builtin_memcpy(&hi, ap - 64 * t + 8, 8);
-    const v4i a = v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
-                      (int)(uint32_t)(hi >> 32)};
 #pragma unroll
-    for (int q = Q0; q < NTQ; ++q) {
-      const int u = 4 * q - t;
-      if (u >= G::UMIN && u <= G::UMAX)
-        C[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, B[u - G::UMIN], C[q], 0, 0, 0);
+    for (int t = G::TMIN; t <= G::TMAX; ++t) {
+      bool any = false;
+#pragma unroll
+      for (int q = Q0; q < NTQ; ++q) {
+        const int u = 4 * q - t;
+        any |= (u >= ulo && u <= uhi);
+      }
+      if (!any) continue;
+      const uint8_t* wp = bp - 64 * t;
+      const v4u w = *reinterpret_cast<const v4u*>(__builtin_assume_aligned(wp, 16));
+      const uint32_t w4 = *reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(wp + 16, 4));
+      const v4i a = v4i{(int)__builtin_amdgcn_alignbyte(w[1], w[0], sb),
+                        (int)__builtin_amdgcn_alignbyte(w[2], w[1], sb),
+                        (int)__builtin_amdgcn_alignbyte(w[3], w[2], sb),
+                        (int)__builtin_amdgcn_alignbyte(w4, w[3], sb)};
+#pragma unroll
+      for (int q = Q0; q < NTQ; ++q) {
+        const int u = 4 * q - t;
+        if (u >= ulo && u <= uhi)
+          C[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, B[u - ulo], C[q], 0, 0, 0);
+      }
     }
   }
 }
@@ -239,12 +253,10 @@ __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 template <class G>
 __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lane, bool fwd,
                                          uint8_t* out, bool plus_one, uint32_t (&U)[G::NT]) {
-  v4i B[G::NU];
   uint64_t v[G::NT];  // column values of T, then of T + q N (limb 64 q + lane)
   {
     v4i C[G::NT];
-    load_b<G>(B, y, lane);
-    product<G, G::NT>(C, ws.xr, B, lane);
+    mul_tiles<G, G::NT>(C, ws.xr, y, lane);
     fold<G::NT>(v, C);
   }
   {
@@ -264,8 +276,7 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lan
     v4i C[G::NTLO];
     uint64_t vl[G::NTLO];
     uint32_t Q[G::NTLO];
-    load_b<G>(B, ws.npf, lane);
-    product<G, G::NTLO>(C, ws.tr, B, lane);
+    mul_tiles<G, G::NTLO>(C, ws.tr, ws.npf, lane);
     fold<G::NTLO>(vl, C);
 #pragma unroll
     for (int q = 0; q < G::NTLO; ++q)
@@ -276,8 +287,7 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lan
   wave_sync();
   {
     v4i C[G::NT];
-    load_b<G>(B, ws.nf, lane);
-    product<G, G::NT, G::QLO>(C, ws.qr, B, lane);
+    mul_tiles<G, G::NT, G::QLO>(C, ws.qr, ws.nf, lane);
 #pragma unroll
     for (int q = G::QLO; q < G::NT; ++q) v[q] += fold1(C[q]);
   }

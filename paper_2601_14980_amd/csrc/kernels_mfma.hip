@@ -21,11 +21,13 @@ namespace {
 
 using pc2k::PkConst;
 
-// three wavefronts per SIMD up to 3072-bit keys (a few registers spill at
-// 2048 and 3072 bits, and the launch is still faster than with two); two
-// for 4096-bit keys, where three would spill hundreds of bytes per lane
+// Wavefronts per SIMD, as measured on the MI355X: three up to 2048-bit keys
+// (one launch of 32768 encryptions: 120.5 ms against 134.2 ms with two,
+// although a few registers spill), two from 3072 bits on, where three spill
+// more than they gain (16384 encryptions: 148.3 ms with two, 192.9 ms with
+// three)
 template <int S>
-__global__ __launch_bounds__(64, S > 256 ? 2 : 3) void k_encrypt_mfma(
+__global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
     PkConst pk, const uint32_t* __restrict__ m, int m_limbs, const uint32_t* __restrict__ r,
     uint32_t* __restrict__ c, size_t count, uint8_t* __restrict__ scratch, int w, int* err) {
   using G = pc2m::MGeo<S>;

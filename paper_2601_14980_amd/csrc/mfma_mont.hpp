@@ -79,8 +79,7 @@ constexpr uint32_t M28 = (1u << 28) - 1u;
 
 // value of lane (l - 1) mod 64
 __device__ __forceinline__ uint32_t rotate_up(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C /* wave_ror:1 */, 0xF, 0xF,
-                                               false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C /* wave_ror:1 */, 0xF, 0xF, false);
 }
 
 // 28-bit limb -> its four 7-bit digits as bytes, least significant first
@@ -116,9 +115,13 @@ __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, cons
     v4i B[NUP];
 #pragma unroll
     for (int k = 0; k < NUP; ++k) {
-      const int off = 64 * (ulo + k) + base;  // >= -64
+      // chunks past the end of the digits (only in the last chunk, for some
+      // lanes) are read from the zero front pad instead
+      const int u = ulo + k;
+      int off = 64 * u + base;  // >= -64
+      if (64 * u + 108 >= G::D8 && off >= G::D8) off = -G::PF;
       v4i b = v4i{0, 0, 0, 0};
-      if (ulo + k <= uhi && off < G::D8) {
+      if (u <= uhi) {
         const uint32_t* w = reinterpret_cast<const uint32_t*>(y + G::PF + off);
         b = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
       }
@@ -198,33 +201,38 @@ __device__ __forceinline__ void normalize(uint32_t (&o)[NTQ], const uint64_t (&v
     o[q] &= M28;
   }
   add_from_prev_limb<NTQ>(o, c, lane);  // <= 2^28
-  // carry-lookahead over the limbs: limb L generates (value 2^28) or
-  // propagates (2^28 - 1); with A = G | P, the carry into limb L is bit L of
-  // (A + G) ^ A ^ G, taken tile by tile as a multiword add
-  uint64_t carry = 0;
+  // A limb is now 2^28 only where it was 2^28 - 1 and took a carry.  Each
+  // further round moves such carries one limb up, and makes a new one only
+  // where that limb was 2^28 - 1 in turn, so a round is rarely needed (the
+  // test is wave-uniform) and the rounds end: the top limb's carry drops.
+  for (;;) {
+    uint32_t hi = 0;
 #pragma unroll
-  for (int q = 0; q < NTQ; ++q) {
-    const bool gen = (o[q] >> 28) != 0;
-    o[q] &= M28;
-    const uint64_t gm = __ballot(gen);
-    const uint64_t pm = __ballot(!gen && o[q] == M28);
-    const uint64_t a = gm | pm;
-    const uint64_t s1 = a + gm;
-    const uint64_t s2 = s1 + carry;
-    carry = (s1 < a || s2 < s1) ? 1u : 0u;
-    o[q] = (o[q] + (uint32_t)(((s2 ^ a ^ gm) >> lane) & 1ull)) & M28;
+    for (int q = 0; q < NTQ; ++q) hi |= o[q] >> 28;
+    if (__ballot(hi != 0) == 0) break;
+#pragma unroll
+    for (int q = 0; q < NTQ; ++q) {
+      c[q] = o[q] >> 28;
+      o[q] &= M28;
+    }
+    add_from_prev_limb<NTQ>(o, c, lane);
   }
 }
 
-// Write limbs lo .. lo + S - 1 (as limbs 0 .. S - 1) as digits.
+// Write limbs lo .. lo + S - 1 (as limbs 0 .. S - 1) as digits.  Tiles with
+// no such limb are skipped (lo is a constant at every call); in the others a
+// lane outside the range writes zero into the zero pad above digit 0, so no
+// lane branches.
 template <class G, int NTQ>
 __device__ __forceinline__ void write_rev(uint8_t* xr, const uint32_t (&o)[NTQ], int lane,
                                           int lo) {
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) {
+    if (64 * q + 63 < lo || 64 * q - lo >= G::S) continue;
     const int gi = 64 * q + lane - lo;
-    if (gi >= 0 && gi < G::S)
-      *reinterpret_cast<uint32_t*>(xr + G::X0 - 4 * gi - 3) = __builtin_bswap32(limb_digits(o[q]));
+    const bool in = gi >= 0 && gi < G::S;
+    const int at = in ? G::X0 - 4 * gi - 3 : G::X0 + 1;
+    *reinterpret_cast<uint32_t*>(xr + at) = in ? __builtin_bswap32(limb_digits(o[q])) : 0u;
   }
 }
 // (forward arrays also get their zero tail [D, D8 + 16) written, since the
@@ -235,9 +243,11 @@ __device__ __forceinline__ void write_fwd(uint8_t* y, const uint32_t (&o)[NTQ], 
                                           int lo) {
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) {
+    if (64 * q + 63 < lo || 64 * q - lo >= G::S) continue;
     const int gi = 64 * q + lane - lo;
-    if (gi >= 0 && gi < G::S)
-      *reinterpret_cast<uint32_t*>(y + G::PF + 4 * gi) = limb_digits(o[q]);
+    const bool in = gi >= 0 && gi < G::S;
+    const int at = in ? G::PF + 4 * gi : 0;  // out of range: zero into the front pad
+    *reinterpret_cast<uint32_t*>(y + at) = in ? limb_digits(o[q]) : 0u;
   }
   if (lane < (G::D8 + 16) / 4 - G::S)
     *reinterpret_cast<uint32_t*>(y + G::PF + 4 * (G::S + lane)) = 0u;

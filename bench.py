@@ -761,7 +761,7 @@ def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
                 enc_ms.append(ev[0].elapsed_time(ev[1]))
                 dec_ms.append(ev[2].elapsed_time(ev[3]))
             log(f"admm ({engine}) iteration {it + 1}: {dt * 1e3:.0f} ms")
-        ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_VALU)
+        ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
         if ctx.sync() != 0:
             raise RuntimeError("device reported a data error in the ADMM loop")
         zh = z.cpu().numpy()
@@ -857,8 +857,8 @@ def main() -> int:
                     help="iterations of the lasso accuracy run (plaintext-equivalent loops)")
     ap.add_argument("--admm-modmul", default="valu,mfma",
                     help="Montgomery engines to run the lasso leg with (comma-separated)")
-    ap.add_argument("--modmul", choices=("valu", "mfma"), default="valu",
-                    help="Montgomery engine of the main leg's encryptions")
+    ap.add_argument("--modmul", choices=("auto", "valu", "mfma"), default="auto",
+                    help="Montgomery engine of the main leg's encryptions (auto: VALU at 2048 bits)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run an elementwise kernel that reads and writes MIB MiB "
                          "(reference for the HBM byte counters) and exit")
@@ -894,8 +894,9 @@ def main() -> int:
     log(f"inputs generated in {time.perf_counter() - t0:.1f}s")
 
     ctx = pc2.Context(0)
-    if args.modmul == "mfma":
-        ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_MFMA)
+    if args.modmul != "auto":
+        ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_MFMA if args.modmul == "mfma"
+                       else pc2.PC2_MODMUL_VALU)
     if args.window:
         ctx.set_option(pc2.PC2_OPT_WINDOW, args.window)
     ctx.reserve(NBITS)

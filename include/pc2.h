@@ -103,12 +103,15 @@ int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
 
 /* Options.  PC2_OPT_WINDOW: window width w in {0 (auto), 2..6} of the
  * modular exponentiations (sliding windows over the key's exponents n,
- * p - 1, q - 1; fixed windows over per-element exponents).  PC2_OPT_MODMUL: limb-product engine for the
- * Montgomery products of pc2_encrypt: PC2_MODMUL_VALU (default; 27/28-bit
- * digits, one v_mad_u64_u32 per limb product) or PC2_MODMUL_MFMA (7-bit
- * digits, the three limb-product matrices of each product on the i8 matrix
- * cores with int32 accumulation, carries resolved on the vector ALUs).  Both
- * give identical results; the other operations always use the VALU engine.
+ * p - 1, q - 1; fixed windows over per-element exponents).
+ * PC2_OPT_MODMUL: limb-product engine for the Montgomery products of
+ * pc2_encrypt: PC2_MODMUL_VALU (27/28-bit digits, one v_mad_u64_u32 per limb
+ * product), PC2_MODMUL_MFMA (7-bit digits, the three limb-product matrices
+ * of each product on the i8 matrix cores with int32 accumulation, carries
+ * resolved on the vector ALUs) or PC2_MODMUL_AUTO (the default: the MFMA
+ * engine for keys of more than 2048 bits, where it is the faster one on the
+ * MI355X, the VALU engine otherwise).  All give identical results; the other
+ * operations always use the VALU engine.
  * PC2_OPT_TILE: the limb tile of the VALU encryption kernels (pc2_encrypt,
  * batches and runners of encryptions), i.e. how many lanes of a wavefront
  * share one ciphertext.  1024-bit keys run with 2 (own) or 4 lanes,
@@ -125,7 +128,7 @@ int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
  * Options apply to calls made after they are set. */
 enum { PC2_OPT_WINDOW = 1, PC2_OPT_MODMUL = 2, PC2_OPT_TILE = 3 };
 enum { PC2_TILE_AUTO = 0, PC2_TILE_WIDE = 1 };
-enum { PC2_MODMUL_VALU = 0, PC2_MODMUL_MFMA = 1 };
+enum { PC2_MODMUL_VALU = 0, PC2_MODMUL_MFMA = 1, PC2_MODMUL_AUTO = 2 };
 int pc2_ctx_set_option(pc2_ctx *ctx, int option, int64_t value);
 int pc2_ctx_get_option(pc2_ctx *ctx, int option, int64_t *value);
 

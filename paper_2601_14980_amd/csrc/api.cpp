@@ -25,7 +25,7 @@ struct pc2_ctx {
   void* done_stream = nullptr; // ... on this stream
   bool done_valid = false;
   int window = 0;              // 0 = automatic
-  int modmul = PC2_MODMUL_VALU;
+  int modmul = PC2_MODMUL_AUTO;
   int tile = 0;                // PC2_OPT_TILE: 0 automatic, 1 wide, else lanes per ciphertext
   int occ[pc2k::NUM_GEOS][pc2k::OP_COUNT] = {};    // workgroups per CU (0 = not queried)
   int tuned[pc2k::NUM_GEOS][pc2k::OP_COUNT] = {};  // autotuned windows (0 = none)
@@ -735,7 +735,7 @@ int pc2_ctx_set_option(pc2_ctx* ctx, int option, int64_t value) {
     return PC2_OK;
   }
   if (option == PC2_OPT_MODMUL) {
-    if (value == PC2_MODMUL_VALU || value == PC2_MODMUL_MFMA) {
+    if (value == PC2_MODMUL_VALU || value == PC2_MODMUL_MFMA || value == PC2_MODMUL_AUTO) {
       ctx->modmul = (int)value;
       return PC2_OK;
     }
@@ -947,7 +947,9 @@ int pc2_encrypt(const pc2_pk* pk, const uint32_t* m, uint32_t m_limbs, const uin
     return PC2_E_INVAL;
   pc2_ctx* ctx = pk->ctx;
   pc2k::Launch l{};
-  if (ctx->modmul == PC2_MODMUL_MFMA) {
+  // the matrix-core engine when asked for, or automatically above 2048-bit
+  // keys, where it measured faster than the VALU engine on the MI355X
+  if (ctx->modmul == PC2_MODMUL_MFMA || (ctx->modmul == PC2_MODMUL_AUTO && pk->cls >= 7)) {
     int rc = prepare(ctx, pk->cls, pc2k::OP_ENC_MFMA, count, 0, pk->L, &l, stream);
     if (!rc) rc = scratch_begin(ctx, stream);
     if (rc) return rc;

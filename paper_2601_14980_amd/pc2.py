@@ -36,6 +36,7 @@ PC2_TILE_AUTO = 0
 PC2_TILE_WIDE = 1
 PC2_MODMUL_VALU = 0
 PC2_MODMUL_MFMA = 1
+PC2_MODMUL_AUTO = 2
 PC2_OP_ENCRYPT = 1
 PC2_OP_HOM_SUM = 2
 PC2_OP_DECRYPT = 3

@@ -3,7 +3,8 @@
 Longest carry chains and boundary values -- r = 1 and r = n - 1, m = 0 and
 m = n - 1, ciphertexts 1 and n^2 - 1, all-ones limbs below the modulus,
 values at 2^(32 i) - 1 and 2^(32 i) -- fed to encryption in each limb tile of
-the key's class (PC2_OPT_TILE forced, the own tiles included), and to
+the key's class (PC2_OPT_TILE forced, the own tiles included; the VALU
+engine, and the matrix-core engine once per key size), and to
 decryption, K-way aggregation and scalar powers, in the one-call path and in
 a persistent batch.  Counts span two wavefront groups and a ragged tail;
 every output is compared with the oracle element by element.
@@ -91,12 +92,18 @@ def test_encrypt_edges_in_each_tile(gpu_ctx, keys, nbits, lanes):
     count = 2 * (64 // lanes) + 3
     idx = _spread(list(range(len(pairs))), count)
     gpu_ctx.set_option(pc2.PC2_OPT_TILE, lanes)
+    # the VALU engine in this tile; once per key size also the matrix-core engine
+    engines = [pc2.PC2_MODMUL_VALU] + ([pc2.PC2_MODMUL_MFMA] if lanes == TILES[nbits][0] else [])
     try:
-        got, st = gpu_encrypt(gpu_ctx, sk.public, [pairs[i][0] for i in idx],
-                              [pairs[i][1] for i in idx])
-        assert st == 0
-        for j, i in enumerate(idx):
-            assert got[j] == want[i], f"{nbits}-bit, {lanes} lanes, element {j}, (m, r) #{i}"
+        for eng in engines:
+            gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, eng)
+            got, st = gpu_encrypt(gpu_ctx, sk.public, [pairs[i][0] for i in idx],
+                                  [pairs[i][1] for i in idx])
+            assert st == 0
+            for j, i in enumerate(idx):
+                assert got[j] == want[i], \
+                    f"{nbits}-bit, {lanes} lanes, engine {eng}, element {j}, (m, r) #{i}"
+        gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
         # the same inputs as one job of a persistent batch in this tile
         L = sk.L
         m = dev(to_limbs([pairs[i][0] for i in idx], L))
@@ -109,6 +116,7 @@ def test_encrypt_edges_in_each_tile(gpu_ctx, keys, nbits, lanes):
         b.close()
     finally:
         gpu_ctx.set_option(pc2.PC2_OPT_TILE, 0)
+        gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
 
 
 @pytest.mark.parametrize("nbits", list(TILES))

@@ -2,7 +2,8 @@
 
 With PC2_OPT_MODMUL = PC2_MODMUL_MFMA, pc2_encrypt runs its modular
 products on the matrix cores.  Every ciphertext must equal the oracle's and
-the VALU path's bit for bit; decryption must invert it."""
+the VALU path's bit for bit; decryption must invert it.  The default
+(PC2_MODMUL_AUTO) takes the matrix cores above 2048 bits."""
 from __future__ import annotations
 
 import math
@@ -28,6 +29,16 @@ def mfma_ctx():
     ctx.close()
 
 
+@pytest.fixture(scope="module")
+def valu_ctx():
+    from paper_2601_14980_amd import pc2
+    ctx = pc2.Context(0)
+    ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_VALU)
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
 def _key(ctx, p, q, nbits=None):
     from paper_2601_14980_amd import pc2
     n = p * q
@@ -47,7 +58,7 @@ def test_mfma_bruteforce_tiny(mfma_ctx, p, q):
 
 
 @pytest.mark.parametrize("nbits", [64, 256, 1024, 2048, 3072, 4096])
-def test_mfma_matches_oracle_and_valu(gpu_ctx, mfma_ctx, nbits):
+def test_mfma_matches_oracle_and_valu(valu_ctx, mfma_ctx, nbits):
     from paper_2601_14980_amd import pc2
     p, q = gen.primes_for(1, nbits, extra=7)
     n = p * q
@@ -58,13 +69,13 @@ def test_mfma_matches_oracle_and_valu(gpu_ctx, mfma_ctx, nbits):
     rs = [1, n - 1, 2] + gen.gen_r(n, count - 3, 1, extra=nbits)
     cs, st = gpu_encrypt(mfma_ctx, sk.public, ms, rs)
     assert st == 0
-    sk_v = pc2.SecretKey(gpu_ctx, nbits, p, q)
-    cv, st = gpu_encrypt(gpu_ctx, sk_v.public, ms, rs)
+    sk_v = pc2.SecretKey(valu_ctx, nbits, p, q)
+    cv, st = gpu_encrypt(valu_ctx, sk_v.public, ms, rs)
     assert st == 0
     assert cs == cv, "MFMA and VALU ciphertexts differ"
     for j in (sorted({0, 1, 2, 3, count // 2, count - 1}) if nbits <= 3072 else (1, count - 1)):
         assert cs[j] == O.encrypt(opk, ms[j], rs[j]), f"element {j}"
-    dec, st = gpu_decrypt(gpu_ctx, sk_v, cs)
+    dec, st = gpu_decrypt(valu_ctx, sk_v, cs)
     assert st == 0 and dec == ms
 
 
@@ -93,3 +104,28 @@ def test_mfma_range_errors(mfma_ctx):
     assert cs[0] == O.encrypt(opk, 5, 3)
     assert cs[1:] == [0, 0, 0]
     assert mfma_ctx.sync() == 0   # the error latch was cleared
+
+
+@pytest.mark.parametrize("nbits", [2048, 3072])
+def test_auto_engine(valu_ctx, nbits):
+    """A fresh context defaults to PC2_MODMUL_AUTO; its ciphertexts (the MFMA
+    engine at 3072 bits, the VALU engine at 2048) equal the VALU engine's."""
+    from paper_2601_14980_amd import pc2
+    ctx = pc2.Context(0)
+    assert ctx.get_option(pc2.PC2_OPT_MODMUL) == pc2.PC2_MODMUL_AUTO
+    with pytest.raises(pc2.PC2Error):
+        ctx.set_option(pc2.PC2_OPT_MODMUL, 3)
+    p, q = gen.primes_for(1, nbits, extra=11)
+    n = p * q
+    sk, opk, _ = _key(ctx, p, q, nbits)
+    sk_v = pc2.SecretKey(valu_ctx, nbits, p, q)
+    rng = random.Random(nbits + 1)
+    ms = [n - 1, 0] + [rng.randrange(n) for _ in range(69)]
+    rs = [n - 1, 1] + gen.gen_r(n, 69, 1, extra=nbits + 1)
+    cs, st = gpu_encrypt(ctx, sk.public, ms, rs)
+    cv, st_v = gpu_encrypt(valu_ctx, sk_v.public, ms, rs)
+    assert st == 0 and st_v == 0 and cs == cv
+    assert cs[0] == O.encrypt(opk, ms[0], rs[0])
+    sk.close()
+    sk_v.close()
+    ctx.close()

@@ -93,6 +93,27 @@ def montgomery_products_per_decrypt(p: int, q: int, window: int) -> tuple[int, i
     return total_mm, total_prod
 
 
+# MI355X i8 matrix cores, dense: 5.0 POP/s = 2.5e15 multiply-accumulates/s
+PEAK_I8_MACS = 2.5e15
+MFMA_S = {256: 10, 512: 19, 1024: 37, 2048: 74, 4096: 147, 6144: 220, 8192: 293}
+
+
+def mfma_per_product(nbits_n2: int) -> int:
+    """v_mfma_i32_16x16x64_i8 instructions per Montgomery product of the
+    matrix-core engine: the tiles of T = x y, of q (the low S limbs) and of
+    q N from the tile holding limb S - 2 up, each over the Toeplitz bands
+    that reach it."""
+    S = MFMA_S[nbits_n2]
+    D = 4 * S
+    tmin, tmax, umin, umax = -3, (D + 62) // 64, -1, (D - 1) // 64
+
+    def tiles(q0, ntq):
+        return sum(1 for q in range(q0, ntq) for t in range(tmin, tmax + 1)
+                   if umin <= 4 * q - t <= umax)
+    nt, ntlo, qlo = (2 * S + 1 + 63) // 64, (S + 63) // 64, (S - 2) // 64
+    return tiles(0, nt) + tiles(0, ntlo) + tiles(qlo, nt)
+
+
 # ------------------------------------------------------- measured HBM traffic
 # Sources that define k_encrypt: a traffic record counts only while they are
 # unchanged since its counters were taken.
@@ -767,7 +788,27 @@ def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
         zh = z.cpu().numpy()
         final[engine] = zh
         mt = float(np.median(times))
+        enc_s = float(np.median(enc_ms)) / 1e3
+        if engine == "mfma":
+            # algorithmic i8 work: 2 d^2 multiply-accumulates per Montgomery
+            # product with d = bytes of n^2 (8-bit digits); issued: the
+            # matrix instructions the engine runs, 16 x 16 x 64 each
+            mm, _ = montgomery_products_per_encrypt(ADMM_BITS, p * q, 5)
+            d = 2 * ADMM_BITS // 8
+            alg = K * N * mm * 2 * d * d / enc_s
+            issued = K * N * mm * mfma_per_product(2 * ADMM_BITS) * 16 * 16 * 64 / enc_s
+            roof = {"bound": "mfma", "unit": "T i8 MAC/s", "achieved": round(alg / 1e12, 1),
+                    "peak": PEAK_I8_MACS / 1e12, "frac": round(alg / PEAK_I8_MACS, 4),
+                    "issued_frac": round(issued / PEAK_I8_MACS, 4), "mm_per_encrypt": mm,
+                    "mfma_per_product": mfma_per_product(2 * ADMM_BITS)}
+        else:
+            mm, prod = montgomery_products_per_encrypt(ADMM_BITS, p * q, 6)
+            alg = K * N * prod / enc_s
+            roof = {"bound": "alu", "unit": "T limb-products/s", "achieved": round(alg / 1e12, 3),
+                    "peak": round(PEAK_PRODUCTS / 1e12, 3), "frac": round(alg / PEAK_PRODUCTS, 4),
+                    "mm_per_encrypt": mm}
         out[engine] = {"iterations_timed": len(times), "ms_per_iteration": round(mt * 1e3, 1),
+                       "encrypt_roofline": roof,
                        "encrypt_ms": round(float(np.median(enc_ms)), 1),
                        "decrypt_ms": round(float(np.median(dec_ms)), 1),
                        "enc_dec_ops_per_s": round((K * N + N) / mt, 1),

@@ -557,7 +557,8 @@ size_t class_scratch_need(pc2_ctx* ctx, int cls, int L, int Ls, int nl2) {
   take(cls, pc2k::OP_SMUL, 0);
   take(cls, pc2k::OP_ENC_MFMA, 0);
   take(cls, pc2k::OP_DEC, ch * 2 * (size_t)(Ls + 1));
-  const size_t fused_aux = ch * 2 * (size_t)L + ch * 2 * (size_t)(Ls + 1);
+  const size_t fused_aux = ch * 2 * (size_t)L + ch * 2 * (size_t)(Ls + 1) + 128 +
+                           ch * (pc2k::chunk_words(cls) + 1);
   take(cls, pc2k::OP_DEC, fused_aux);
   take(cls, pc2k::OP_FUSED, fused_aux);
   take(cls, pc2k::OP_ENC_CRT, ch * 2 * (size_t)(nl2 + 1));
@@ -1130,12 +1131,15 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
     ms.p[k] = m_k[k];
     rs.p[k] = r_k[k];
   }
-  // per chunk: the products (2L limbs per element) then the CRT halves
+  // per chunk: the products (2L limbs per element), the CRT halves, the
+  // running products (chunked, 16-byte aligned) and the input checks
   pc2_ctx* ctx = sk->ctx;
   const int Ls = sk->c.h[0].Ls, L = sk->pk.L, cls = sk->pk.cls;
   const size_t chunk = std::min(count, pc2k::DEC_CHUNK);
-  const size_t prod_words = chunk * 2 * (size_t)L;
-  const size_t aux = prod_words + chunk * 2 * (size_t)(Ls + 1);
+  const size_t prod_words = (chunk * 2 * (size_t)L + 63) & ~(size_t)63;
+  const size_t half_words = (chunk * 2 * (size_t)(Ls + 1) + 63) & ~(size_t)63;
+  const size_t acc_words = chunk * pc2k::chunk_words(cls);
+  const size_t aux = prod_words + half_words + acc_words + chunk;
   pc2k::Launch le{}, ld{};
   int rc = prepare(ctx, cls, pc2k::OP_DEC, chunk, Ls, L, &ld, stream, aux);
   if (!rc) rc = prepare(ctx, cls, pc2k::OP_FUSED, chunk, Ls, L, &le, stream, aux);
@@ -1143,6 +1147,8 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
   if (rc) return rc;
   uint32_t* prod = le.aux;
   uint32_t* halves = le.aux + prod_words;
+  uint32_t* acc = halves + half_words;
+  uint32_t* okw = acc + acc_words;
   for (size_t b = 0; b < count && !rc; b += chunk) {
     const size_t n = std::min(chunk, count - b);
     pc2k::PtrList mb{}, rb{};
@@ -1151,7 +1157,7 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
       rb.p[k] = rs.p[k] + b * (size_t)L;
     }
     rc = status_of(
-        pc2k::launch_enc_prod(cls, le, sk->pk.c, mb, rb, (int)K, (int)m_limbs, prod, n));
+        pc2k::launch_enc_prod(cls, le, sk->pk.c, mb, rb, (int)K, (int)m_limbs, prod, n, acc, okw));
     if (!rc)
       rc = status_of(pc2k::launch_decrypt(cls, ld, sk->c, prod, m_out + b * L, n, halves));
   }

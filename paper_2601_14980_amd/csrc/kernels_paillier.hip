@@ -158,24 +158,33 @@ __global__ __launch_bounds__(64, 2) void k_scalar_mul(PkConst pk, const uint32_t
   }
 }
 
-// prod[j] = prod_k Enc(m_k[j], r_k[j]) mod n^2, the first phase of the fused
-// encrypt -> aggregate -> decrypt path: the K ciphertexts never leave the
-// element's scratch slot, and the product goes to the caller's staging area,
-// from which the two decryption phases produce m_out.
+// One step of the fused encrypt -> aggregate -> decrypt path, the first
+// phase of which is prod[j] = prod_k Enc(m_k[j], r_k[j]) mod n^2: step k
+// encrypts (m_k, r_k) and multiplies it into the element's running product
+// acc_j (chunked layout, CH words per element), x = MM(c_k, acc_j).  acc
+// starts as R^K (a key constant, read by step 0), so after k steps it holds
+// c_0 .. c_(k-1) R^(K-k) and the last step leaves the plain product, which
+// it writes canonical to prod (2L limbs); the ciphertexts never reach the
+// caller's memory.  ok: one word per element, the AND of every step's input
+// checks.  Every step runs the encryption kernel's program and then one
+// product, so it keeps close to that kernel's register budget (one launch
+// that looped over k spilled tens of registers).
 template <class G>
-__global__ __launch_bounds__(64, 2) void k_enc_prod(PkConst pk, PtrList ms, PtrList rs, int K,
-                                                    int m_limbs, uint32_t* __restrict__ prod,
-                                                    size_t count, uint32_t* __restrict__ scratch,
-                                                    size_t slot_words, int w, int* err) {
+__global__ __launch_bounds__(64, 2) void k_enc_acc(PkConst pk, const uint32_t* __restrict__ m,
+                                                   int m_limbs, const uint32_t* __restrict__ r,
+                                                   int K, int step, uint32_t* __restrict__ acc,
+                                                   uint32_t* __restrict__ ok_all,
+                                                   uint32_t* __restrict__ prod, size_t count,
+                                                   uint32_t* __restrict__ scratch,
+                                                   size_t slot_words, int w, int* err) {
   constexpr int EPW = 64 / G::T;
   __shared__ __align__(16) uint32_t lds_all[EPW * G::SP];
   const int tl = threadIdx.x & (G::T - 1);
   const int tile = threadIdx.x / G::T;
   uint32_t* lds = lds_all + tile * G::SP;
-  // per element: the table slot, then the running product
-  uint32_t* slot = scratch + ((size_t)blockIdx.x * EPW + tile) * 2 * slot_words;
-  uint32_t* slot_acc = slot + slot_words;
+  uint32_t* slot = scratch + ((size_t)blockIdx.x * EPW + tile) * slot_words;
   const int L = pk.L, L2 = 2 * L;
+  const bool last = step + 1 == K;
   uint32_t N[G::K];
   load_chunk<G>(N, pk.n2.N, tl);
   const uint32_t np = pk.n2.nprime;
@@ -184,34 +193,32 @@ __global__ __launch_bounds__(64, 2) void k_enc_prod(PkConst pk, PtrList ms, PtrL
     size_t e = gi * EPW + tile;
     const bool live = e < count;
     if (!live) e = count - 1;
-    uint32_t okall = 1;
+    const uint32_t* me = m + e * m_limbs;
+    const uint32_t* re = r + e * L;
+    uint32_t ok = 1;
+    if (tl == 0) ok = encrypt_inputs_ok(pk, me, m_limbs, re) & (step ? ok_all[e] : 1u);
+    Program P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl, w);
     uint32_t x[G::K];
-    // k = 0..K-1: encrypt and fold into the running product; k = K: remove R^-(K-1)
-    for (int k = 0; k <= K; ++k) {
-      Program P;
-      if (k < K) {
-        const uint32_t* me = ms.p[k] + e * m_limbs;
-        const uint32_t* re = rs.p[k] + e * L;
-        if (tl == 0) okall &= encrypt_inputs_ok(pk, me, m_limbs, re);
-        P = encrypt_program<G>(pk, me, m_limbs, re, slot, tl, w);
-        if (k > 0) {
-          P.npost = 2;
-          P.post1_a = op_x();
-          P.post1_b = op_chunk(slot_acc);
-        }
-      } else {
-        P = empty_program();
-        P.npre = 1;
-        P.pre0_a = op_chunk(pk.Rk + (size_t)K * G::CH);
-        P.pre0_b = op_chunk(slot_acc);
+    run_program<G, true>(P, x, lds, slot, w, N, np, tl);
+    // x = MM(acc, c_k): a program of its own (as a second post-step of the
+    // encryption program it pushed the kernel into tens of spilled registers)
+    uint32_t* acc_e = acc + e * G::CH;  // formed here: nothing more is live in the powering
+    Program Q = empty_program();
+    Q.npre = 1;
+    Q.pre0_a = op_chunk(step ? acc_e : pk.Rk + (size_t)K * G::CH);
+    Q.pre0_b = op_x();
+    run_program<G, true>(Q, x, lds, slot, w, N, np, tl);
+    if (!last) {
+      if (live) {
+        store_chunk<G>(acc_e, x, tl);
+        if (tl == 0) ok_all[e] = ok;
       }
-      run_program<G, true>(P, x, lds, slot, w, N, np, tl);
-      if (k < K) store_chunk<G>(slot_acc, x, tl);
+    } else {
+      lds_sync();
+      to_lds<G>(lds, x, tl);
+      lds_sync();
+      if (tl == 0) store_canonical<G>(lds, pk.n2, prod + e * L2, live, ok, err);
     }
-    lds_sync();
-    to_lds<G>(lds, x, tl);
-    lds_sync();
-    if (tl == 0) store_canonical<G>(lds, pk.n2, prod + e * L2, live, okall, err);
   }
 }
 
@@ -259,7 +266,7 @@ static const void* kernel_ptr(int op) {
       case OP_DEC: return (const void*)&k_decrypt_half<Gp>;
       case OP_SUM: return (const void*)&k_hom_sum<Gn>;
       case OP_SMUL: return (const void*)&k_scalar_mul<Gn>;
-      case OP_FUSED: return (const void*)&k_enc_prod<Gn>;
+      case OP_FUSED: return (const void*)&k_enc_acc<Gn>;
       case OP_ENC_CRT: return (const void*)&k_encrypt_crt_half<Gp>;
     }
     return nullptr;
@@ -297,7 +304,7 @@ static void slot_shape_t(int op, int w, int Ls, int L, int* tiles, size_t* words
       *words = std::max((size_t)Gp::CH * table_entries(w, true), scal);
       break;
     case OP_FUSED:
-      *tiles = 2 * epw;
+      *tiles = epw;
       *words = (size_t)Gn::CH * table_entries(w, true);
       break;
     case OP_ENC_CRT:
@@ -403,16 +410,26 @@ hipError_t launch_encrypt_crt(int cls, const Launch& l, const SkConst& sk, const
 
 template <int C>
 static hipError_t fused_t(const Launch& l, const PkConst& pk, const PtrList& ms,
-                          const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count) {
-  hipLaunchKernelGGL((k_enc_prod<typename Geos<C>::Gn>), dim3(l.grid), dim3(64), 0,
-                     (hipStream_t)l.stream, pk, ms, rs, K, m_limbs, prod, count, l.scratch,
-                     l.slot_words, l.window, l.err);
-  return hipGetLastError();
+                          const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count,
+                          uint32_t* acc, uint32_t* ok) {
+  for (int k = 0; k < K; ++k) {
+    hipLaunchKernelGGL((k_enc_acc<typename Geos<C>::Gn>), dim3(l.grid), dim3(64), 0,
+                       (hipStream_t)l.stream, pk, ms.p[k], m_limbs, rs.p[k], K, k, acc, ok, prod,
+                       count, l.scratch, l.slot_words, l.window, l.err);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 hipError_t launch_enc_prod(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
-                           const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count) {
-  PC2_DISPATCH(cls, return fused_t<C>(l, pk, ms, rs, K, m_limbs, prod, count));
+                           const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count,
+                           uint32_t* acc, uint32_t* ok) {
+  PC2_DISPATCH(cls, return fused_t<C>(l, pk, ms, rs, K, m_limbs, prod, count, acc, ok));
   return hipErrorInvalidValue;
+}
+size_t chunk_words(int geo) {
+  PC2_DISPATCH_GEO(geo, return (size_t)Geos<C>::Gn::CH);
+  return 0;
 }
 
 }  // namespace pc2k

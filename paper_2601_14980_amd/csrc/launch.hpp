@@ -36,9 +36,13 @@ hipError_t launch_scalar_mul(int cls, const Launch& l, const PkConst& pk, const 
 hipError_t launch_encrypt_crt(int cls, const Launch& l, const SkConst& sk, const uint32_t* m,
                               int m_limbs, const uint32_t* r, uint32_t* c, size_t count,
                               uint32_t* stage);
-// first phase of the fused path: prod = prod_k Enc(m_k, r_k), 2L limbs per element
+// first phase of the fused path: prod = prod_k Enc(m_k, r_k), 2L limbs per
+// element, as K launches; acc: chunk_words(cls) words per element of running
+// products, ok: one word per element
 hipError_t launch_enc_prod(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
-                           const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count);
+                           const PtrList& rs, int K, int m_limbs, uint32_t* prod, size_t count,
+                           uint32_t* acc, uint32_t* ok);
+size_t chunk_words(int geo);  // words of one n^2 residue in the geometry's chunked layout
 
 // encryption with the i8-MFMA Montgomery product (kernels_mfma.hip); the
 // scratch holds 2^window forward digit arrays per workgroup

@@ -156,6 +156,39 @@ def test_fused_enc_sum_dec(gpu_ctx, sized):
     assert out == want
 
 
+@pytest.mark.parametrize("nbits,K", [(1024, 1), (1024, 2), (1024, 9), (256, 128)])
+def test_fused_number_of_addends(gpu_ctx, nbits, K):
+    """The fused path runs one encrypt-and-accumulate step per addend: one
+    addend (the first step is also the last), a few, and the most a call
+    takes; a bad input in any step zeroes that element and latches the
+    error, the others stay exact."""
+    p, q = gen.primes_for(98, nbits)
+    sk, _, osk = keys(gpu_ctx, p, q, nbits)
+    n = p * q
+    count = 3 * 32 + 7 if nbits > 256 else 37     # several element groups and a tail
+    rng = random.Random(nbits * 1000 + K)
+    mvs = [[rng.randrange(0, n) for _ in range(count)] for _ in range(K)]
+    rvs = [gen.gen_r(n, count, 98, extra=K * 100 + k) for k in range(K)]
+    bad = count // 2
+    rvs[K - 1][bad] = 0                      # a data error in the last step
+    if K > 1:
+        mvs[0][bad + 1] = n                  # ... and one in the first
+    out, st = gpu_enc_sum_dec(gpu_ctx, sk, mvs, rvs)
+    assert st == pc2_range_error()
+    for j in range(count):
+        if j == bad or (K > 1 and j == bad + 1):
+            assert out[j] == 0, f"element {j} with a bad input"
+        else:
+            assert out[j] == sum(mv[j] for mv in mvs) % n, f"element {j}"
+    for j in (0, count - 1):
+        assert out[j] == O.enc_sum_dec(osk, [mv[j] for mv in mvs], [rv[j] for rv in rvs])
+
+
+def pc2_range_error():
+    from paper_2601_14980_amd import pc2
+    return pc2.PC2_E_RANGE
+
+
 def test_range_errors(gpu_ctx):
     p, q = gen.primes_for(99, 256)
     sk, opk, _ = keys(gpu_ctx, p, q, 256)

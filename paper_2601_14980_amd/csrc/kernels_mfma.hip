@@ -2,13 +2,13 @@
 // products on the i8 matrix cores: c = (1 + m n) r^n mod n^2.
 //
 // One wavefront per element (mfma_mont.hpp); workgroups stride over the
-// elements.  Per element: g^m = MM(m, n R) + 1 (exact: m n < n^2); r R =
+// elements.  Per element: g^m = MM(m, n R) + 1 = 1 + m n (mod n^2); r R =
 // MM(r, R^2); the odd powers (r R)^(2j+1) R^-2j, j < 2^(w-1), in the
 // workgroup's scratch slot (after (r R)^2 R^-1, the slot's last entry);
 // left-to-right sliding windows over n from the key's precomputed schedule
 // (the VALU kernels' schedule: square nsq times, then multiply by an odd
-// power); one product with g^m leaves normal form; a conditional
-// subtraction of n^2 makes it canonical.  Data errors (m >= n, r = 0,
+// power); one product with g^m leaves normal form; resolving the signed
+// limbs' carries (and adding n^2 to a negative result) makes it canonical.  Data errors (m >= n, r = 0,
 // r >= n) zero the element and set ERR_RANGE.
 #include <hip/hip_runtime.h>
 
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
   const int nsched = pk.nsch.n[w - pc2k::SCHED_WMIN];
   pc2m::init_work<G>(ws, K, lane);
   pc2m::init_table<G>(table, half + 1, lane);
-  uint32_t U[G::NT];
+  int32_t U[G::NT];
   for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
     const uint32_t* me = m + e * m_limbs;
     const uint32_t* re = r + e * L;
@@ -69,26 +69,30 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
       if (dig)
         pc2m::mont_mul<G>(ws, table + (size_t)(dig >> 1) * G::FB, lane, true, nullptr, false, U);
     }
-    // r^n g^m = MM(r^n R, g^m), < 2 n^2
+    // r^n g^m = MM(r^n R, g^m), |.| < 0.52 n^2
     pc2m::mont_mul<G>(ws, ws.gm, lane, false, nullptr, false, U);
-    // canonical: subtract n^2 once if needed, then 28-bit limbs -> 32-bit words
+    // canonical: resolve the carries of the signed limbs; a negative value
+    // (a borrow out of the top limb) takes n^2 once
     uint32_t* u = reinterpret_cast<uint32_t*>(ws.tr);
 #pragma unroll
     for (int q = 0; q < G::NT; ++q) {
       const int gi = 64 * q + lane - G::S;
-      if (gi >= 0 && gi < G::S) u[gi] = U[q];
+      if (gi >= 0 && gi < G::S) u[gi] = (uint32_t)U[q];
     }
     pc2m::wave_sync();
     if (lane == 0) {
-      int cmp = 0;
-      for (int i = G::S - 1; i >= 0 && cmp == 0; --i)
-        cmp = u[i] > K.N28[i] ? 1 : (u[i] < K.N28[i] ? -1 : 0);
-      if (cmp >= 0) {
-        int32_t bor = 0;
+      int32_t cy = 0;
+      for (int i = 0; i < G::S; ++i) {
+        const int32_t t = (int32_t)u[i] + cy;
+        u[i] = (uint32_t)t & pc2m::M28;
+        cy = t >> 28;
+      }
+      if (cy < 0) {
+        uint32_t cr = 0;
         for (int i = 0; i < G::S; ++i) {
-          const int32_t d = (int32_t)u[i] - (int32_t)K.N28[i] - bor;
-          bor = d < 0 ? 1 : 0;
-          u[i] = (uint32_t)(d + (bor << 28));
+          const uint32_t t = u[i] + K.N28[i] + cr;
+          u[i] = t & pc2m::M28;
+          cr = t >> 28;
         }
       }
     }

@@ -15,18 +15,25 @@
 // (digits 256 Q + 4 j - 64 t + k); summing over t covers every digit pair
 // once.  With that column order, lane l of tile Q ends up holding the four
 // columns of limb 64 Q + l in its four accumulators, so the digits fold into
-// 28-bit limbs in registers.  Column sums stay below D 127^2 < 2^24.  The
-// carries are explicit: two rounds of split-and-shift (a DPP lane rotation
-// between limbs) leave carries of 0 or 1, and a carry-lookahead over the
-// limbs (two ballots per tile and a multiword add on the scalar unit)
-// settles them.
+// 28-bit limbs in registers.
 //
-// Only what U needs is formed.  T's limbs below S are normalised for q (the
-// carry out of them moves to limb S); its limbs from S up stay as column
-// values and are normalised once, together with those of q N.  Since
-// T + q N = 0 mod R, its part below limb S is c R for an integer c that the
-// two column values just below S fix (every lower limb adds less than
-// 2^-36 to c), so q N is formed only from the tile holding limb S - 2 up.
+// Limbs are signed and redundant: a value is sum l_i 2^(28 i) with
+// -2^27 - 2^20 <= l_i < 2^28, written as digits l & 127, (l >> 7) & 127,
+// (l >> 14) & 127 and l >> 21 (the top digit of a limb signed, so every digit
+// fits a signed byte).  A column sum then stays within D 127^2 < 2^31.  The
+// carries of a product are never resolved: one balanced split per column
+// (keep the low 28 bits less 2^27, hand the rest to the next limb) bounds
+// every limb again, and every output stays below 0.52 N in magnitude, since
+// |U| <= |x y| / R + |q| N / R with |q| < 0.51 R and N/R < 2^-20.  The carry
+// out of the top limb of U is zero by the same bound; the caller makes the
+// final result canonical once.
+//
+// Only what U needs is formed.  T's limbs below S are split for q (the carry
+// out of them moves to limb S); its columns from S up stay in the matrix
+// accumulators, and q N is accumulated onto them.  Since T + q N = 0 mod R,
+// its part below limb S is c R for an integer c that the two column values
+// just below S fix (every lower column adds less than 2^-36 to c), so q N is
+// formed only from the tile holding limb S - 2 up.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -57,6 +64,8 @@ struct MGeo {
   static constexpr int RB = (X0 + 256 + 15) & ~15;   // bytes of a reversed digit array
   static_assert(NTLO <= NT, "low product within the full one");
   static_assert(S % 64 != 0 && S >= 3, "limb S lies in the last tile of the low half");
+  static_assert(QLO == QH && S - 64 * QH >= 2, "limbs S - 2 .. S in one tile");
+  static_assert(D * 127 * 127 * 2 < (1ll << 31), "two products' column sums fit int32");
   static_assert((X0 & 3) == 3, "reversed limbs are dword aligned");
   static_assert(4 * S <= RB, "the limb scratch fits in a reversed array");
 };
@@ -82,9 +91,10 @@ __device__ __forceinline__ uint32_t rotate_up(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C /* wave_ror:1 */, 0xF, 0xF, false);
 }
 
-// 28-bit limb -> its four 7-bit digits as bytes, least significant first
+// limb (signed, -2^27 - 2^20 <= v < 2^28) -> its four digits as bytes, least
+// significant first: three of 7 bits and the signed top digit v >> 21
 __device__ __forceinline__ uint32_t limb_digits(uint32_t v) {
-  return (v & 0x7Fu) | ((v << 1) & 0x7F00u) | ((v << 2) & 0x7F0000u) | ((v << 3) & 0x7F000000u);
+  return (v & 0x7Fu) | ((v << 1) & 0x7F00u) | ((v << 2) & 0x7F0000u) | ((v << 3) & 0xFF000000u);
 }
 
 // Digit sums of x y for tiles Q0 .. NTQ - 1.  y: a forward digit array (LDS
@@ -97,7 +107,8 @@ __device__ __forceinline__ uint32_t limb_digits(uint32_t v) {
 // 16-byte boundary: the lane reads the aligned 20 bytes around them and
 // shifts them into place (v_alignbyte), since unaligned LDS reads stall the
 // LDS pipeline.  Tile Q, lane l: limb 64 Q + l, digit c in accumulator c.
-template <class G, int NTQ, int Q0 = 0, int NPART = 1>
+// ACC: add to C instead of starting from zero.
+template <class G, int NTQ, int Q0 = 0, bool ACC = false, int NPART = 1>
 __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, const uint8_t* y,
                                           int lane) {
   typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -106,8 +117,10 @@ __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, cons
   const uint8_t* bp = xr + G::X0 - 3 - 64 * (i >> 2) + 16 * (lane >> 4);  // 16-byte aligned
   const uint32_t sb = 3u - (uint32_t)(i & 3);
   const int base = 4 * (lane & 15) + 16 * (lane >> 4);
+  if constexpr (!ACC) {
 #pragma unroll
-  for (int q = Q0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
+    for (int q = Q0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
+  }
 #pragma unroll
   for (int part = 0; part < NPART; ++part) {
     const int ulo = G::UMIN + part * NUP;
@@ -160,62 +173,46 @@ __device__ __forceinline__ uint64_t read_lane64(uint64_t x, int l) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t fold1(const v4i& c) {
-  return (uint64_t)(uint32_t)c[0] + ((uint64_t)(uint32_t)c[1] << 7) +
-         ((uint64_t)(uint32_t)c[2] << 14) + ((uint64_t)(uint32_t)c[3] << 21);
+constexpr int32_t BIAS = 1 << 27;
+
+// The column value of limb 64 q + lane from its four digit-column sums,
+// plus 2^27, exactly (|value| < 2^47).  The weights sit in scalar registers
+// the compiler cannot see through, so each term is one v_mad_i64_i32.
+__device__ __forceinline__ int64_t fold_biased(const v4i& c, int32_t k7, int32_t k14,
+                                               int32_t k21) {
+  int64_t v = (int64_t)(c[0] + BIAS);
+  v = (int64_t)c[1] * k7 + v;
+  v = (int64_t)c[2] * k14 + v;
+  v = (int64_t)c[3] * k21 + v;
+  return v;
 }
 
-template <int NTQ>
-__device__ __forceinline__ void fold(uint64_t (&v)[NTQ], const v4i (&C)[NTQ]) {
-#pragma unroll
-  for (int q = 0; q < NTQ; ++q) v[q] = fold1(C[q]);
-}
+struct FoldK {
+  int32_t k7 = 1 << 7, k14 = 1 << 14, k21 = 1 << 21;
+  __device__ FoldK() { asm volatile("" : "+s"(k7), "+s"(k14), "+s"(k21)); }
+};
 
-// x[q] += the value of the previous limb (lane - 1 of tile q, or lane 63 of
-// tile q - 1 for lane 0)
+// One balanced split of biased column values vb = v + 2^27: each limb keeps
+// v - 2^28 carry (in [-2^27, 2^27)) and takes the carry of the limb below
+// (lane - 1 of its tile, lane 63 of the tile below for lane 0, nothing for
+// limb 0); cin[q] returns the carry each lane took.  |carry| < 2^20.
 template <int NTQ>
-__device__ __forceinline__ void add_from_prev_limb(uint32_t (&x)[NTQ], const uint32_t (&c)[NTQ],
-                                                   int lane) {
-  uint32_t r[NTQ];
-#pragma unroll
-  for (int q = 0; q < NTQ; ++q) r[q] = rotate_up(c[q]);
-#pragma unroll
-  for (int q = 0; q < NTQ; ++q) x[q] += lane ? r[q] : (q ? r[q - 1] : 0u);
-}
-
-// Limb values (< 2^47; limb 64 q + lane in v[q]) -> 28-bit limbs with every
-// carry resolved; the carry out of the top limb is dropped.
-template <int NTQ>
-__device__ __forceinline__ void normalize(uint32_t (&o)[NTQ], const uint64_t (&v)[NTQ],
-                                          int lane) {
-  uint32_t c[NTQ];
+__device__ __forceinline__ void split(int32_t (&l)[NTQ], int32_t (&cin)[NTQ],
+                                      const int64_t (&vb)[NTQ], int lane) {
+  int32_t c[NTQ];
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) {
-    o[q] = (uint32_t)v[q] & M28;
-    c[q] = (uint32_t)(v[q] >> 28);  // < 2^19
+    c[q] = (int32_t)__builtin_amdgcn_alignbit((uint32_t)((uint64_t)vb[q] >> 32), (uint32_t)vb[q],
+                                              28);
+    l[q] = (int32_t)((uint32_t)vb[q] & M28);
   }
-  add_from_prev_limb<NTQ>(o, c, lane);  // < 2^28 + 2^19
+  int32_t r[NTQ];
+#pragma unroll
+  for (int q = 0; q < NTQ; ++q) r[q] = (int32_t)rotate_up((uint32_t)c[q]);
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) {
-    c[q] = o[q] >> 28;  // 0 or 1
-    o[q] &= M28;
-  }
-  add_from_prev_limb<NTQ>(o, c, lane);  // <= 2^28
-  // A limb is now 2^28 only where it was 2^28 - 1 and took a carry.  Each
-  // further round moves such carries one limb up, and makes a new one only
-  // where that limb was 2^28 - 1 in turn, so a round is rarely needed (the
-  // test is wave-uniform) and the rounds end: the top limb's carry drops.
-  for (;;) {
-    uint32_t hi = 0;
-#pragma unroll
-    for (int q = 0; q < NTQ; ++q) hi |= o[q] >> 28;
-    if (__ballot(hi != 0) == 0) break;
-#pragma unroll
-    for (int q = 0; q < NTQ; ++q) {
-      c[q] = o[q] >> 28;
-      o[q] &= M28;
-    }
-    add_from_prev_limb<NTQ>(o, c, lane);
+    cin[q] = lane ? r[q] : (q ? r[q - 1] : 0);
+    l[q] = l[q] + cin[q] - BIAS;
   }
 }
 
@@ -224,7 +221,7 @@ __device__ __forceinline__ void normalize(uint32_t (&o)[NTQ], const uint64_t (&v
 // lane outside the range writes zero into the zero pad above digit 0, so no
 // lane branches.
 template <class G, int NTQ>
-__device__ __forceinline__ void write_rev(uint8_t* xr, const uint32_t (&o)[NTQ], int lane,
+__device__ __forceinline__ void write_rev(uint8_t* xr, const int32_t (&o)[NTQ], int lane,
                                           int lo) {
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) {
@@ -232,14 +229,15 @@ __device__ __forceinline__ void write_rev(uint8_t* xr, const uint32_t (&o)[NTQ],
     const int gi = 64 * q + lane - lo;
     const bool in = gi >= 0 && gi < G::S;
     const int at = in ? G::X0 - 4 * gi - 3 : G::X0 + 1;
-    *reinterpret_cast<uint32_t*>(xr + at) = in ? __builtin_bswap32(limb_digits(o[q])) : 0u;
+    *reinterpret_cast<uint32_t*>(xr + at) =
+        in ? __builtin_bswap32(limb_digits((uint32_t)o[q])) : 0u;
   }
 }
 // (forward arrays also get their zero tail [D, D8 + 16) written, since the
 // products read whole 16-byte chunks and global table entries start out
 // uninitialised; the front pad is written once, with the table's slot)
 template <class G, int NTQ>
-__device__ __forceinline__ void write_fwd(uint8_t* y, const uint32_t (&o)[NTQ], int lane,
+__device__ __forceinline__ void write_fwd(uint8_t* y, const int32_t (&o)[NTQ], int lane,
                                           int lo) {
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) {
@@ -247,7 +245,7 @@ __device__ __forceinline__ void write_fwd(uint8_t* y, const uint32_t (&o)[NTQ], 
     const int gi = 64 * q + lane - lo;
     const bool in = gi >= 0 && gi < G::S;
     const int at = in ? G::PF + 4 * gi : 0;  // out of range: zero into the front pad
-    *reinterpret_cast<uint32_t*>(y + at) = in ? limb_digits(o[q]) : 0u;
+    *reinterpret_cast<uint32_t*>(y + at) = in ? limb_digits((uint32_t)o[q]) : 0u;
   }
   if (lane < (G::D8 + 16) / 4 - G::S)
     *reinterpret_cast<uint32_t*>(y + G::PF + 4 * (G::S + lane)) = 0u;
@@ -255,72 +253,67 @@ __device__ __forceinline__ void write_fwd(uint8_t* y, const uint32_t (&o)[NTQ], 
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
-// x <- x y R^-1 mod N (inputs < 2N, output < 2N), x in ws.xr; y a forward
-// digit array (LDS or global).  The result also goes, as forward digits, to
-// ws.xf (fwd) and to out (if not null); plus_one adds 1 to the result
-// before its carries are resolved.  U: the result's limbs (limb 64 q + lane
-// - S in U[q] for q >= QH; the entries below are zero).
+// x <- x y R^-1 (mod N; |inputs| < N, |output| < 0.52 N), x in ws.xr; y a
+// forward digit array (LDS or global).  The result also goes, as forward
+// digits, to ws.xf (fwd) and to out (if not null); plus_one adds 1 to it.
+// U: the result's limbs (limb 64 q + lane - S in U[q] for q >= QH; the
+// entries below are zero).
 template <class G>
 __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lane, bool fwd,
-                                         uint8_t* out, bool plus_one, uint32_t (&U)[G::NT]) {
-  uint64_t v[G::NT];  // column values of T, then of T + q N (limb 64 q + lane)
+                                         uint8_t* out, bool plus_one, int32_t (&U)[G::NT]) {
+  constexpr int NT = G::NT, NL = G::NTLO, QH = G::QH, NH = NT - QH;
+  const FoldK k;
+  const int ls = G::S - 64 * QH;  // lane of limb S in tile QH
+  v4i C[NT];                      // digit columns of T, then of T + q N
+  mul_tiles<G, NT>(C, ws.xr, y, lane);
+  int32_t Lq[NL];                 // T mod R (limbs below S)
   {
-    v4i C[G::NT];
-    mul_tiles<G, G::NT>(C, ws.xr, y, lane);
-    fold<G::NT>(v, C);
-  }
-  {
-    // T mod R in 28-bit limbs; the carry out of limb S - 1 lands in limb S
-    // (inside tile NTLO - 1), the limbs above it stay zero
-    uint64_t vl[G::NTLO];
-    uint32_t Tl[G::NTLO];
+    int64_t vb[NL];
+    int32_t cin[NL];
 #pragma unroll
-    for (int q = 0; q < G::NTLO; ++q) vl[q] = 64 * q + lane < G::S ? v[q] : 0;
-    normalize<G::NTLO>(Tl, vl, lane);
-#pragma unroll
-    for (int q = 0; q < G::NTLO; ++q) v[q] = 64 * q + lane < G::S ? (uint64_t)Tl[q] : v[q] + Tl[q];
-    write_rev<G, G::NTLO>(ws.tr, Tl, lane, 0);
+    for (int q = 0; q < NL; ++q) vb[q] = fold_biased(C[q], k.k7, k.k14, k.k21);
+    split<NL>(Lq, cin, vb, lane);
+    // the carry out of limb S - 1 joins column S
+    if (lane == ls) C[QH][0] += cin[QH];
+    write_rev<G, NL>(ws.tr, Lq, lane, 0);
   }
   wave_sync();
   {
-    v4i C[G::NTLO];
-    uint64_t vl[G::NTLO];
-    uint32_t Q[G::NTLO];
-    mul_tiles<G, G::NTLO>(C, ws.tr, ws.npf, lane);
-    fold<G::NTLO>(vl, C);
+    v4i Cq[NL];
+    int64_t vb[NL];
+    int32_t Q[NL], cin[NL];
+    mul_tiles<G, NL>(Cq, ws.tr, ws.npf, lane);
 #pragma unroll
-    for (int q = 0; q < G::NTLO; ++q)
-      if (64 * q + lane >= G::S) vl[q] = 0;
-    normalize<G::NTLO>(Q, vl, lane);
-    write_rev<G, G::NTLO>(ws.qr, Q, lane, 0);
+    for (int q = 0; q < NL; ++q) vb[q] = fold_biased(Cq[q], k.k7, k.k14, k.k21);
+    split<NL>(Q, cin, vb, lane);  // limbs from S up are not written: q mod R
+    write_rev<G, NL>(ws.qr, Q, lane, 0);
   }
+  // below limb S, tile QH carries T mod R as limb values into q N
+  if (lane < ls) C[QH] = v4i{Lq[QH], 0, 0, 0};
   wave_sync();
+  mul_tiles<G, NT, QH, true>(C, ws.qr, ws.nf, lane);
+  int64_t vb[NH];
+#pragma unroll
+  for (int q = 0; q < NH; ++q) vb[q] = fold_biased(C[QH + q], k.k7, k.k14, k.k21);
+  // c = (the part of T + q N below limb S) / R, rounded from columns S - 1
+  // and S - 2
   {
-    v4i C[G::NT];
-    mul_tiles<G, G::NT, G::QLO>(C, ws.qr, ws.nf, lane);
-#pragma unroll
-    for (int q = G::QLO; q < G::NT; ++q) v[q] += fold1(C[q]);
+    const int64_t a = (int64_t)read_lane64((uint64_t)vb[0], ls - 1) - BIAS;
+    const int64_t b = (int64_t)read_lane64((uint64_t)vb[0], ls - 2) - BIAS;
+    const int64_t c = (a + (b >> 28) + BIAS) >> 28;
+    if (lane == ls) vb[0] += c + (plus_one ? 1 : 0);
   }
-  // c = (the part of T + q N below limb S) / R, from limbs S - 1 and S - 2
-  const uint64_t a = read_lane64(v[(G::S - 1) / 64], (G::S - 1) % 64);
-  const uint64_t b = read_lane64(v[(G::S - 2) / 64], (G::S - 2) % 64);
-  const uint64_t c = (a >> 28) + ((((a & M28) + (b >> 28)) >= (1ull << 27)) ? 1u : 0u);
   {
-    constexpr int NH = G::NT - G::QH;
-    uint64_t vh[NH];
-    uint32_t Uh[NH];
+    int32_t Uh[NH], cin[NH];
+    split<NH>(Uh, cin, vb, lane);
+    // limb S takes no carry from below (the low part is c R)
+    if (lane == ls) Uh[0] -= cin[0];
 #pragma unroll
-    for (int q = 0; q < NH; ++q) {
-      const int limb = 64 * (q + G::QH) + lane;
-      vh[q] = limb < G::S ? 0 : v[q + G::QH] + (limb == G::S ? c + (plus_one ? 1u : 0u) : 0u);
-    }
-    normalize<NH>(Uh, vh, lane);
-#pragma unroll
-    for (int q = 0; q < G::NT; ++q) U[q] = q < G::QH ? 0u : Uh[q - G::QH];
+    for (int q = 0; q < NT; ++q) U[q] = q < QH ? 0 : Uh[q - QH];
   }
-  write_rev<G, G::NT>(ws.xr, U, lane, G::S);
-  if (fwd) write_fwd<G, G::NT>(ws.xf, U, lane, G::S);
-  if (out) write_fwd<G, G::NT>(out, U, lane, G::S);
+  write_rev<G, NT>(ws.xr, U, lane, G::S);
+  if (fwd) write_fwd<G, NT>(ws.xf, U, lane, G::S);
+  if (out) write_fwd<G, NT>(out, U, lane, G::S);
   wave_sync();
 }
 

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
   uint8_t* sq = table + (size_t)half * G::FB;     // (r R)^2 R^-1
   const uint32_t* sched = pk.nsch.p[w - pc2k::SCHED_WMIN];
   const int nsched = pk.nsch.n[w - pc2k::SCHED_WMIN];
-  pc2m::init_work<G>(ws, K, lane);
+  pc2m::init_work<G>(ws, lane);
   pc2m::init_table<G>(table, half + 1, lane);
   int32_t U[G::NT];
   for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
@@ -50,27 +50,27 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
     if (lane == 0) s_ok = pc2ops::encrypt_inputs_ok(pk, me, m_limbs, re);
     // g^m = 1 + m n
     pc2m::load_x<G>(ws, me, m_limbs, lane);
-    pc2m::mont_mul<G>(ws, K.nR, lane, false, ws.gm, true, U);
+    pc2m::mont_mul<G>(ws, K, K.nR, lane, false, ws.gm, true, U);
     // table entry j = (r R)^(2j+1) R^-2j: entry 0 = r R, the square, then
     // one product by the square per entry
     pc2m::load_x<G>(ws, re, L, lane);
-    pc2m::mont_mul<G>(ws, K.R2, lane, true, table, false, U);
-    pc2m::mont_mul<G>(ws, ws.xf, lane, false, sq, false, U);
+    pc2m::mont_mul<G>(ws, K, K.R2, lane, true, table, false, U);
+    pc2m::mont_mul<G>(ws, K, ws.xf, lane, false, sq, false, U);
     pc2m::load_fwd<G>(ws, table, lane);
     for (int j = 1; j < half; ++j)
-      pc2m::mont_mul<G>(ws, sq, lane, false, table + (size_t)j * G::FB, false, U);
+      pc2m::mont_mul<G>(ws, K, sq, lane, false, table + (size_t)j * G::FB, false, U);
     // (r R)^n by the sliding-window schedule of n, most significant first
     pc2m::load_fwd<G>(ws, table + (size_t)((sched[0] & 0xFFFFu) >> 1) * G::FB, lane);
     for (int si = 1; si < nsched; ++si) {
       const uint32_t en = sched[si];
       for (uint32_t k = en >> 16; k; --k)
-        pc2m::mont_mul<G>(ws, ws.xf, lane, true, nullptr, false, U);
+        pc2m::mont_mul<G>(ws, K, ws.xf, lane, true, nullptr, false, U);
       const uint32_t dig = en & 0xFFFFu;
       if (dig)
-        pc2m::mont_mul<G>(ws, table + (size_t)(dig >> 1) * G::FB, lane, true, nullptr, false, U);
+        pc2m::mont_mul<G>(ws, K, table + (size_t)(dig >> 1) * G::FB, lane, true, nullptr, false, U);
     }
     // r^n g^m = MM(r^n R, g^m), |.| < 0.52 n^2
-    pc2m::mont_mul<G>(ws, ws.gm, lane, false, nullptr, false, U);
+    pc2m::mont_mul<G>(ws, K, ws.gm, lane, false, nullptr, false, U);
     // canonical: resolve the carries of the signed limbs; a negative value
     // (a borrow out of the top limb) takes n^2 once
     uint32_t* u = reinterpret_cast<uint32_t*>(ws.tr);

@@ -78,8 +78,6 @@ struct MWork {
   uint8_t qr[G::RB];     // q, reversed
   uint8_t xf[G::FB];     // x, forward (B operand of a squaring)
   uint8_t gm[G::FB];     // a per-element multiplier, forward
-  uint8_t nf[G::FB];     // N, forward
-  uint8_t npf[G::FB];    // N', forward
 };
 
 using MConst = pc2k::MfmaConst;
@@ -254,13 +252,16 @@ __device__ __forceinline__ void write_fwd(uint8_t* y, const int32_t (&o)[NTQ], i
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
 // x <- x y R^-1 (mod N; |inputs| < N, |output| < 0.52 N), x in ws.xr; y a
-// forward digit array (LDS or global).  The result also goes, as forward
+// forward digit array (LDS or global); N and N' (K) are read from global
+// memory, through the vector L1 cache, which leaves the LDS bandwidth to the
+// per-element operands.  The result also goes, as forward
 // digits, to ws.xf (fwd) and to out (if not null); plus_one adds 1 to it.
 // U: the result's limbs (limb 64 q + lane - S in U[q] for q >= QH; the
 // entries below are zero).
 template <class G>
-__device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lane, bool fwd,
-                                         uint8_t* out, bool plus_one, int32_t (&U)[G::NT]) {
+__device__ __forceinline__ void mont_mul(MWork<G>& ws, const MConst& K, const uint8_t* y,
+                                         int lane, bool fwd, uint8_t* out, bool plus_one,
+                                         int32_t (&U)[G::NT]) {
   constexpr int NT = G::NT, NL = G::NTLO, QH = G::QH, NH = NT - QH;
   const FoldK k;
   const int ls = G::S - 64 * QH;  // lane of limb S in tile QH
@@ -282,7 +283,7 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lan
     v4i Cq[NL];
     int64_t vb[NL];
     int32_t Q[NL], cin[NL];
-    mul_tiles<G, NL>(Cq, ws.tr, ws.npf, lane);
+    mul_tiles<G, NL>(Cq, ws.tr, K.Np, lane);
 #pragma unroll
     for (int q = 0; q < NL; ++q) vb[q] = fold_biased(Cq[q], k.k7, k.k14, k.k21);
     split<NL>(Q, cin, vb, lane);  // limbs from S up are not written: q mod R
@@ -291,7 +292,7 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const uint8_t* y, int lan
   // below limb S, tile QH carries T mod R as limb values into q N
   if (lane < ls) C[QH] = v4i{Lq[QH], 0, 0, 0};
   wave_sync();
-  mul_tiles<G, NT, QH, true>(C, ws.qr, ws.nf, lane);
+  mul_tiles<G, NT, QH, true>(C, ws.qr, K.N, lane);
   int64_t vb[NH];
 #pragma unroll
   for (int q = 0; q < NH; ++q) vb[q] = fold_biased(C[QH + q], k.k7, k.k14, k.k21);
@@ -344,16 +345,12 @@ __device__ __forceinline__ void load_fwd(MWork<G>& ws, const uint8_t* y, int lan
   wave_sync();
 }
 
-// zero the workspace's digit arrays and copy N, N' into it
+// zero the workspace's digit arrays
 template <class G>
-__device__ __forceinline__ void init_work(MWork<G>& ws, const MConst& K, int lane) {
+__device__ __forceinline__ void init_work(MWork<G>& ws, int lane) {
   uint32_t* z = reinterpret_cast<uint32_t*>(ws.xr);
   constexpr int ZW = (3 * G::RB + 2 * G::FB) / 4;
   for (int i = lane; i < ZW; i += 64) z[i] = 0u;
-  for (int i = lane; i < G::FB / 4; i += 64) {
-    reinterpret_cast<uint32_t*>(ws.nf)[i] = reinterpret_cast<const uint32_t*>(K.N)[i];
-    reinterpret_cast<uint32_t*>(ws.npf)[i] = reinterpret_cast<const uint32_t*>(K.Np)[i];
-  }
   wave_sync();
 }
 

@@ -72,8 +72,10 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
     // r^n g^m = MM(r^n R, g^m), |.| < 0.52 n^2
     pc2m::mont_mul<G>(ws, K, ws.gm, lane, false, nullptr, false, U);
     // canonical: resolve the carries of the signed limbs; a negative value
-    // (a borrow out of the top limb) takes n^2 once
-    uint32_t* u = reinterpret_cast<uint32_t*>(ws.tr);
+    // (a borrow out of the top limb) takes n^2 once.  The limbs go to the
+    // digit region of ws.xf, which is written before every read (its zero
+    // pads stay zero for the next element).
+    uint32_t* u = reinterpret_cast<uint32_t*>(ws.xf + G::PF);
 #pragma unroll
     for (int q = 0; q < G::NT; ++q) {
       const int gi = 64 * q + lane - G::S;

@@ -67,7 +67,7 @@ struct MGeo {
   static_assert(QLO == QH && S - 64 * QH >= 2, "limbs S - 2 .. S in one tile");
   static_assert(D * 127 * 127 * 2 < (1ll << 31), "two products' column sums fit int32");
   static_assert((X0 & 3) == 3, "reversed limbs are dword aligned");
-  static_assert(4 * S <= RB, "the limb scratch fits in a reversed array");
+  static_assert(4 * S <= D8, "S limbs fit the digit region of a forward array");
 };
 
 // Per-wavefront LDS workspace.
@@ -119,6 +119,10 @@ __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, cons
 #pragma unroll
     for (int q = Q0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
   }
+  // a wavefront issuing matrix products goes first, so that the others'
+  // vector instructions fill the matrix cores' busy cycles (measured: 4 %
+  // faster at 2048 bits)
+  __builtin_amdgcn_s_setprio(1);
 #pragma unroll
   for (int part = 0; part < NPART; ++part) {
     const int ulo = G::UMIN + part * NUP;
@@ -162,6 +166,7 @@ __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, cons
       }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // the value of lane l (a constant) of a 64-bit register pair, wave-uniform

@@ -129,3 +129,38 @@ def test_auto_engine(valu_ctx, nbits):
     sk.close()
     sk_v.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("nbits", [256, 2048, 3072])
+def test_mfma_workgroups_loop_over_elements(valu_ctx, mfma_ctx, nbits):
+    """More elements than workgroups: every workgroup runs several elements
+    in turn on the same LDS workspace, so whatever one element leaves there
+    must not reach the next.  All ciphertexts equal the VALU engine's;
+    elements from the first, second and last pass of the grid equal the
+    oracle's."""
+    import numpy as np
+    from paper_2601_14980_amd import pc2
+    p, q = gen.primes_for(2, nbits, extra=11)
+    n = p * q
+    sk, opk, _ = _key(mfma_ctx, p, q, nbits)
+    sk_v = pc2.SecretKey(valu_ctx, nbits, p, q)
+    count = {256: 40000, 2048: 7001, 3072: 5003}[nbits]   # above two grids of workgroups
+    L = sk.L
+    rng = np.random.default_rng(nbits)
+    m = torch.from_numpy(rng.integers(0, 1 << 31, size=(count, 1), dtype=np.int64)
+                         .astype(np.int32)).cuda()
+    r = pc2.to_device_limbs(gen.gen_r_limbs(n, count, L, 5))
+    out = {}
+    for ctx, key in ((mfma_ctx, sk), (valu_ctx, sk_v)):
+        c = torch.zeros((count, 2 * L), dtype=torch.int32, device="cuda")
+        pc2.pc2_encrypt(key.public, m, r, c)
+        assert ctx.sync() == 0
+        out[ctx] = c
+    assert torch.equal(out[mfma_ctx], out[valu_ctx]), "MFMA and VALU ciphertexts differ"
+    cm = out[mfma_ctx].cpu().numpy().view(np.uint32)
+    rh = r.cpu().numpy().view(np.uint32)
+    mh = m.cpu().numpy().view(np.uint32)
+    for j in (0, 1, count // 3, count // 2 + 1, count - 2, count - 1):
+        cj = sum(int(w) << (32 * k) for k, w in enumerate(cm[j]))
+        rj = sum(int(w) << (32 * k) for k, w in enumerate(rh[j]))
+        assert cj == O.encrypt(opk, int(mh[j, 0]), rj), f"element {j}"

@@ -61,7 +61,13 @@ struct MGeo {
   static constexpr int UMAX = (D - 1) / 64;
   static constexpr int NU = UMAX - UMIN + 1;
   static constexpr int X0 = 64 * TMAX + 195;         // reversed array: byte X0 - i = digit i
-  static constexpr int RB = (X0 + 256 + 15) & ~15;   // bytes of a reversed digit array
+  // A reversed array is kept as four copies, copy c at byte c PR holding it
+  // shifted down by c bytes (see mul_tiles).  Every read of copy c lies in
+  // [c PR, c PR + X0 + 253) and its digits in [c PR + X0 - D + 1 - c,
+  // c PR + X0 - c], so neighbouring copies share their zero pads when
+  // PR >= D + 256 and PR > X0.
+  static constexpr int PR = ((D + 256 > X0 + 1 ? D + 256 : X0 + 1) + 15) & ~15;
+  static constexpr int RBT = (3 * PR + X0 + 253 + 15) & ~15;  // bytes of the four copies
   static_assert(NTLO <= NT, "low product within the full one");
   static_assert(S % 64 != 0 && S >= 3, "limb S lies in the last tile of the low half");
   static_assert(QLO == QH && S - 64 * QH >= 2, "limbs S - 2 .. S in one tile");
@@ -73,9 +79,9 @@ struct MGeo {
 // Per-wavefront LDS workspace.
 template <class G>
 struct MWork {
-  uint8_t xr[G::RB];     // x, reversed (A operand)
-  uint8_t tr[G::RB];     // T mod R, reversed; the result's limbs at the end
-  uint8_t qr[G::RB];     // q, reversed
+  uint8_t xr[G::RBT];    // x, reversed, four rotated copies (A operand)
+  uint8_t tr[G::RBT];    // T mod R, the same
+  uint8_t qr[G::RBT];    // q, the same
   uint8_t xf[G::FB];     // x, forward (B operand of a squaring)
   uint8_t gm[G::FB];     // a per-element multiplier, forward
 };
@@ -102,18 +108,18 @@ __device__ __forceinline__ uint32_t limb_digits(uint32_t v) {
 // at a time).  x: its reversed array in LDS; lane (i, g) takes the Toeplitz
 // band of digits alpha(i) + 64 t - 16 g - s, s < 16, i.e. bytes
 // X0 - alpha(i) - 64 t + 16 g .. +16, which start 3 - i % 4 bytes past a
-// 16-byte boundary: the lane reads the aligned 20 bytes around them and
-// shifts them into place (v_alignbyte), since unaligned LDS reads stall the
-// LDS pipeline.  Tile Q, lane l: limb 64 Q + l, digit c in accumulator c.
+// 16-byte boundary; in the copy rotated by that many bytes they start at the
+// boundary, so every lane makes one aligned 16-byte read (unaligned LDS
+// reads stall the LDS pipeline).  Tile Q, lane l: limb 64 Q + l, digit c in
+// accumulator c.
 // ACC: add to C instead of starting from zero.
 template <class G, int NTQ, int Q0 = 0, bool ACC = false, int NPART = 1>
 __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, const uint8_t* y,
                                           int lane) {
-  typedef unsigned v4u __attribute__((ext_vector_type(4)));
   constexpr int NUP = (G::NU + NPART - 1) / NPART;
   const int i = lane & 15;
-  const uint8_t* bp = xr + G::X0 - 3 - 64 * (i >> 2) + 16 * (lane >> 4);  // 16-byte aligned
-  const uint32_t sb = 3u - (uint32_t)(i & 3);
+  const int sb = 3 - (i & 3);
+  const uint8_t* bp = xr + sb * G::PR + G::X0 - 3 - 64 * (i >> 2) + 16 * (lane >> 4);
   const int base = 4 * (lane & 15) + 16 * (lane >> 4);
   if constexpr (!ACC) {
 #pragma unroll
@@ -151,13 +157,7 @@ __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, cons
         any |= (u >= ulo && u <= uhi);
       }
       if (!any) continue;
-      const uint8_t* wp = bp - 64 * t;
-      const v4u w = *reinterpret_cast<const v4u*>(__builtin_assume_aligned(wp, 16));
-      const uint32_t w4 = *reinterpret_cast<const uint32_t*>(__builtin_assume_aligned(wp + 16, 4));
-      const v4i a = v4i{(int)__builtin_amdgcn_alignbyte(w[1], w[0], sb),
-                        (int)__builtin_amdgcn_alignbyte(w[2], w[1], sb),
-                        (int)__builtin_amdgcn_alignbyte(w[3], w[2], sb),
-                        (int)__builtin_amdgcn_alignbyte(w4, w[3], sb)};
+      const v4i a = *reinterpret_cast<const v4i*>(__builtin_assume_aligned(bp - 64 * t, 16));
 #pragma unroll
       for (int q = Q0; q < NTQ; ++q) {
         const int u = 4 * q - t;
@@ -219,21 +219,43 @@ __device__ __forceinline__ void split(int32_t (&l)[NTQ], int32_t (&cin)[NTQ],
   }
 }
 
+// reversed dwords of limbs i and i - 1 (zero outside 0 .. S - 1) -> the four
+// copies of a reversed array (i = -1 addresses the zero pad above digit 0)
+template <class G>
+__device__ __forceinline__ void put_rev(uint8_t* xr, int i, uint32_t w, uint32_t wp) {
+  uint8_t* at = xr + G::X0 - 4 * i - 3;
+  *reinterpret_cast<uint32_t*>(at) = w;
+  *reinterpret_cast<uint32_t*>(at + G::PR) = __builtin_amdgcn_alignbyte(wp, w, 1);
+  *reinterpret_cast<uint32_t*>(at + 2 * G::PR) = __builtin_amdgcn_alignbyte(wp, w, 2);
+  *reinterpret_cast<uint32_t*>(at + 3 * G::PR) = __builtin_amdgcn_alignbyte(wp, w, 3);
+}
+
 // Write limbs lo .. lo + S - 1 (as limbs 0 .. S - 1) as digits.  Tiles with
 // no such limb are skipped (lo is a constant at every call); in the others a
 // lane outside the range writes zero into the zero pad above digit 0, so no
-// lane branches.
+// lane branches.  Reversed arrays: the dword of limb g in copy c is made of
+// the dwords of limbs g and g - 1 (the lane below), and the lane of limb S
+// writes the copies' dwords that reach into limb S - 1.
 template <class G, int NTQ>
 __device__ __forceinline__ void write_rev(uint8_t* xr, const int32_t (&o)[NTQ], int lane,
                                           int lo) {
+  uint32_t w[NTQ], r[NTQ];
 #pragma unroll
   for (int q = 0; q < NTQ; ++q) {
-    if (64 * q + 63 < lo || 64 * q - lo >= G::S) continue;
     const int gi = 64 * q + lane - lo;
-    const bool in = gi >= 0 && gi < G::S;
-    const int at = in ? G::X0 - 4 * gi - 3 : G::X0 + 1;
-    *reinterpret_cast<uint32_t*>(xr + at) =
-        in ? __builtin_bswap32(limb_digits((uint32_t)o[q])) : 0u;
+    const bool skip = 64 * q + 63 < lo || 64 * q - lo > G::S;
+    w[q] = !skip && gi >= 0 && gi < G::S ? __builtin_bswap32(limb_digits((uint32_t)o[q])) : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < NTQ; ++q) r[q] = rotate_up(w[q]);
+#pragma unroll
+  for (int q = 0; q < NTQ; ++q) {
+    if (64 * q + 63 < lo || 64 * q - lo > G::S) continue;
+    const int gi = 64 * q + lane - lo;
+    const bool in = gi >= 0 && gi <= G::S;
+    const uint32_t wp = lane ? r[q] : (q ? r[q - 1] : 0u);  // limb gi - 1
+    // (outside 0 .. S both dwords are zero, and so is what the lane writes)
+    put_rev<G>(xr, in ? gi : -1, w[q], wp);
   }
 }
 // (forward arrays also get their zero tail [D, D8 + 16) written, since the
@@ -333,19 +355,22 @@ __device__ __forceinline__ uint32_t limb28_of(const uint32_t* a, int n, int i) {
 // x (n 32-bit words, x < R) -> ws.xr
 template <class G>
 __device__ __forceinline__ void load_x(MWork<G>& ws, const uint32_t* x, int n, int lane) {
-  for (int i = lane; i < G::S; i += 64)
-    *reinterpret_cast<uint32_t*>(ws.xr + G::X0 - 4 * i - 3) =
-        __builtin_bswap32(limb_digits(limb28_of(x, n, i)));
+  for (int i = lane; i <= G::S; i += 64) {
+    const uint32_t w = i < G::S ? __builtin_bswap32(limb_digits(limb28_of(x, n, i))) : 0u;
+    const uint32_t wp = i > 0 ? __builtin_bswap32(limb_digits(limb28_of(x, n, i - 1))) : 0u;
+    put_rev<G>(ws.xr, i, w, wp);
+  }
   wave_sync();
 }
 
 // forward digit array (LDS or global) -> ws.xr and ws.xf
 template <class G>
 __device__ __forceinline__ void load_fwd(MWork<G>& ws, const uint8_t* y, int lane) {
-  for (int i = lane; i < G::S; i += 64) {
-    const uint32_t d = *reinterpret_cast<const uint32_t*>(y + G::PF + 4 * i);
-    *reinterpret_cast<uint32_t*>(ws.xr + G::X0 - 4 * i - 3) = __builtin_bswap32(d);
-    *reinterpret_cast<uint32_t*>(ws.xf + G::PF + 4 * i) = d;
+  for (int i = lane; i <= G::S; i += 64) {
+    const uint32_t d = i < G::S ? *reinterpret_cast<const uint32_t*>(y + G::PF + 4 * i) : 0u;
+    const uint32_t dp = i > 0 ? *reinterpret_cast<const uint32_t*>(y + G::PF + 4 * i - 4) : 0u;
+    put_rev<G>(ws.xr, i, __builtin_bswap32(d), __builtin_bswap32(dp));
+    if (i < G::S) *reinterpret_cast<uint32_t*>(ws.xf + G::PF + 4 * i) = d;
   }
   wave_sync();
 }
@@ -354,7 +379,8 @@ __device__ __forceinline__ void load_fwd(MWork<G>& ws, const uint8_t* y, int lan
 template <class G>
 __device__ __forceinline__ void init_work(MWork<G>& ws, int lane) {
   uint32_t* z = reinterpret_cast<uint32_t*>(ws.xr);
-  constexpr int ZW = (3 * G::RB + 2 * G::FB) / 4;
+  constexpr int ZW = (3 * G::RBT + 2 * G::FB) / 4;
+  static_assert(sizeof(MWork<G>) == 3 * G::RBT + 2 * G::FB, "no padding between the arrays");
   for (int i = lane; i < ZW; i += 64) z[i] = 0u;
   wave_sync();
 }

@@ -114,32 +114,67 @@ def mfma_per_product(nbits_n2: int) -> int:
     return tiles(0, nt) + tiles(0, ntlo) + tiles(qlo, nt)
 
 
+# the library's automatic window width at 2048 to 4096 bits, for either
+# Montgomery engine
+AUTO_WINDOW = 6
+
+
+def roofline_valu(products: float, secs: float) -> dict:
+    """VALU engine: algorithmic 32x32-bit limb products per second against
+    one v_mad_u64_u32 per lane per clock."""
+    a = products / secs
+    return {"bound": "alu", "unit": "T limb-products/s (32x32->64, v_mad_u64_u32)",
+            "achieved": round(a / 1e12, 3), "peak": round(PEAK_PRODUCTS / 1e12, 3),
+            "frac": round(a / PEAK_PRODUCTS, 4)}
+
+
+def roofline_mfma(nbits_n: int, mm: int, count: int, secs: float) -> dict:
+    """i8 matrix-core engine: the algorithmic work of a Montgomery product
+    is 2 d^2 multiply-accumulates of bytes (x y and the reduction, d = bytes
+    of n^2), two int8 operations each, against the dense int8 peak; issued:
+    the 16 x 16 x 64 matrix instructions the engine runs."""
+    d = 2 * nbits_n // 8
+    ops = 2.0 * count * mm * 2 * d * d / secs
+    issued = 2.0 * count * mm * mfma_per_product(2 * nbits_n) * 16 * 16 * 64 / secs
+    return {"bound": "mfma", "unit": "TOP/s (int8, 2 per multiply-accumulate)",
+            "achieved": round(ops / 1e12, 1), "peak": round(2 * PEAK_I8_MACS / 1e12, 1),
+            "frac": round(ops / (2 * PEAK_I8_MACS), 4),
+            "issued_frac": round(issued / (2 * PEAK_I8_MACS), 4),
+            "mfma_per_product": mfma_per_product(2 * nbits_n)}
+
+
 # ------------------------------------------------------- measured HBM traffic
-# Sources that define k_encrypt: a traffic record counts only while they are
-# unchanged since its counters were taken.
-KERNEL_SOURCES = ["kernels_paillier.hip", "paillier_ops.hpp", "engine.hpp", "mont_tile.hpp",
-                  "bn_scalar.hpp", "pc2_types.hpp", "launch.hpp"]
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_encrypt_2048bit_traffic.json")
+# Per kernel: the committed FETCH_SIZE / WRITE_SIZE record and the sources
+# that define the kernel; a record counts only while they are unchanged
+# since its counters were taken.
+TRAFFIC = {
+    "k_encrypt": ("k_encrypt_2048bit_traffic.json",
+                  ["kernels_paillier.hip", "paillier_ops.hpp", "engine.hpp", "mont_tile.hpp",
+                   "bn_scalar.hpp", "pc2_types.hpp", "launch.hpp"]),
+    "k_encrypt_mfma": ("k_encrypt_mfma_2048bit_traffic.json",
+                       ["kernels_mfma.hip", "mfma_mont.hpp", "paillier_ops.hpp", "pc2_types.hpp",
+                        "launch.hpp"]),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in TRAFFIC[kernel][1]:
         with open(os.path.join(ROOT, "paper_2601_14980_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(elements: int):
-    """HBM bytes per k_encrypt launch of `elements` from the committed
+def measured_traffic(kernel: str, elements: int):
+    """HBM bytes per launch of `kernel` over `elements` from its committed
     FETCH_SIZE / WRITE_SIZE record, or None if the kernel changed since."""
     try:
-        with open(TRAFFIC_RECORD) as f:
+        with open(os.path.join(ROOT, "profiles", TRAFFIC[kernel][0])) as f:
             rec = json.load(f)
     except OSError:
         return None
-    if rec.get("source_sha256") != kernel_source_hash() or rec.get("elements") != elements:
+    if rec.get("source_sha256") != kernel_source_hash(kernel) or rec.get("elements") != elements:
         return None
     return int(rec["hbm_bytes_per_launch"])
 
@@ -626,18 +661,11 @@ def run_key4096(pc2, gen, ctx, torch, np, args) -> dict:
     # the automatic engine choice runs 4096-bit encryptions on the matrix cores
     engine = ctx.get_option(pc2.PC2_OPT_MODMUL)
     mfma = engine in (pc2.PC2_MODMUL_MFMA, pc2.PC2_MODMUL_AUTO)
-    mm_e, prod_e = montgomery_products_per_encrypt(nbits, sk.n, 5 if mfma else 6)
-    mm_d, prod_d = montgomery_products_per_decrypt(p, q, 6)
+    mm_e, prod_e = montgomery_products_per_encrypt(nbits, sk.n, AUTO_WINDOW)
+    mm_d, prod_d = montgomery_products_per_decrypt(p, q, AUTO_WINDOW)
     me, md = float(np.median(te)) / 1e3, float(np.median(td)) / 1e3
-    if mfma:
-        d = 2 * nbits // 8
-        alg = count * mm_e * 2 * d * d / me
-        roof = {"bound": "mfma", "unit": "T i8 MAC/s", "achieved": round(alg / 1e12, 1),
-                "peak": PEAK_I8_MACS / 1e12, "frac": round(alg / PEAK_I8_MACS, 4)}
-    else:
-        alg = prod_e * count / me
-        roof = {"bound": "alu", "unit": "T limb-products/s", "achieved": round(alg / 1e12, 3),
-                "peak": round(PEAK_PRODUCTS / 1e12, 3), "frac": round(alg / PEAK_PRODUCTS, 4)}
+    roof = (roofline_mfma(nbits, mm_e, count, me) if mfma
+            else roofline_valu(prod_e * count, me))
     log(f"4096-bit: encrypt {count} in {me * 1e3:.1f} ms ({'mfma' if mfma else 'valu'} engine), "
         f"decrypt in {md * 1e3:.1f} ms, round trip exact {ok}")
     return {"workload": f"4096-bit key (n^2 8192 bits), {count} quantized N(0,1) values: "
@@ -799,24 +827,10 @@ def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
         final[engine] = zh
         mt = float(np.median(times))
         enc_s = float(np.median(enc_ms)) / 1e3
-        if engine == "mfma":
-            # algorithmic i8 work: 2 d^2 multiply-accumulates per Montgomery
-            # product with d = bytes of n^2 (8-bit digits); issued: the
-            # matrix instructions the engine runs, 16 x 16 x 64 each
-            mm, _ = montgomery_products_per_encrypt(ADMM_BITS, p * q, 5)
-            d = 2 * ADMM_BITS // 8
-            alg = K * N * mm * 2 * d * d / enc_s
-            issued = K * N * mm * mfma_per_product(2 * ADMM_BITS) * 16 * 16 * 64 / enc_s
-            roof = {"bound": "mfma", "unit": "T i8 MAC/s", "achieved": round(alg / 1e12, 1),
-                    "peak": PEAK_I8_MACS / 1e12, "frac": round(alg / PEAK_I8_MACS, 4),
-                    "issued_frac": round(issued / PEAK_I8_MACS, 4), "mm_per_encrypt": mm,
-                    "mfma_per_product": mfma_per_product(2 * ADMM_BITS)}
-        else:
-            mm, prod = montgomery_products_per_encrypt(ADMM_BITS, p * q, 6)
-            alg = K * N * prod / enc_s
-            roof = {"bound": "alu", "unit": "T limb-products/s", "achieved": round(alg / 1e12, 3),
-                    "peak": round(PEAK_PRODUCTS / 1e12, 3), "frac": round(alg / PEAK_PRODUCTS, 4),
-                    "mm_per_encrypt": mm}
+        mm, prod = montgomery_products_per_encrypt(ADMM_BITS, p * q, AUTO_WINDOW)
+        roof = (roofline_mfma(ADMM_BITS, mm, K * N, enc_s) if engine == "mfma"
+                else roofline_valu(K * N * prod, enc_s))
+        roof["mm_per_encrypt"] = mm
         out[engine] = {"iterations_timed": len(times), "ms_per_iteration": round(mt * 1e3, 1),
                        "encrypt_roofline": roof,
                        "encrypt_ms": round(float(np.median(enc_ms)), 1),
@@ -1045,6 +1059,24 @@ def main() -> int:
     del c_sk
     log(f"key-holder encryption: {enc_sk_ms:.1f} ms, identical ciphertexts: {enc_sk_same}")
 
+    # the other Montgomery engine on the same inputs (one launch), for its own
+    # roofline; its ciphertexts must be the same
+    main_engine = "mfma" if args.modmul in ("auto", "mfma") else "valu"
+    other_engine = "valu" if main_engine == "mfma" else "mfma"
+    ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_VALU if other_engine == "valu"
+                   else pc2.PC2_MODMUL_MFMA)
+    c_other = torch.empty_like(c_all)
+    ev[0].record(stream)
+    pc2.pc2_encrypt(pk, m2_all, r_all, c_other)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    other_ms = ev[0].elapsed_time(ev[1])
+    other_same = bool(torch.equal(c_other, c_all)) and ctx.sync() == 0
+    del c_other
+    ctx.set_option(pc2.PC2_OPT_MODMUL, {"auto": pc2.PC2_MODMUL_AUTO, "mfma": pc2.PC2_MODMUL_MFMA,
+                                        "valu": pc2.PC2_MODMUL_VALU}[args.modmul])
+    log(f"{other_engine} engine: encrypt {other_ms:.1f} ms, identical ciphertexts: {other_same}")
+
     # the fused path (Dec(prod_k Enc(m_k, r_k)) in one call, the ciphertexts
     # never written out) on the same inputs, against the three calls of a step
     m_nodes = [m2_all[k * LENGTH:(k + 1) * LENGTH] for k in range(NODES)]
@@ -1074,11 +1106,28 @@ def main() -> int:
         log(f"plain step {i + 1}/{args.plain_steps}: {t_plain[-1] * 1e3:.0f} ms")
     plain_value = ops_per_step / (sum(t_plain) / len(t_plain)) if t_plain else None
 
-    w = ctx.get_option(pc2.PC2_OPT_WINDOW) or 6   # the automatic width at 2048 bits
+    w = ctx.get_option(pc2.PC2_OPT_WINDOW) or AUTO_WINDOW
     mm_enc, prod_enc = montgomery_products_per_encrypt(NBITS, n, w)
     enc_avg_s = sum(enc_ms) / len(enc_ms) / 1e3
-    achieved = prod_enc * total / enc_avg_s
-    mm_dec, prod_dec = montgomery_products_per_decrypt(p, q, w)
+
+    def engine_roofline(engine, secs):
+        if engine == "mfma":
+            r = {"kernel": f"k_encrypt_mfma<{MFMA_S[2 * NBITS]}>",
+                 **roofline_mfma(NBITS, mm_enc, total, secs),
+                 "traffic": measured_traffic("k_encrypt_mfma", total),
+                 "per_launch_macs": total * mm_enc * 2 * (NBITS // 4) ** 2}
+        else:
+            r = {"kernel": "k_encrypt", **roofline_valu(prod_enc * total, secs),
+                 "traffic": measured_traffic("k_encrypt", total),
+                 "per_launch_products": prod_enc * total}
+        r.update({"mm_per_encrypt": mm_enc, "avg_launch_ms": round(secs * 1e3, 3)})
+        return r
+
+    roofline = engine_roofline(main_engine, enc_avg_s)
+    engines = {main_engine: {"encrypt_ms": round(enc_avg_s * 1e3, 2), "roofline": roofline},
+               other_engine: {"encrypt_ms": round(other_ms, 2),
+                              "roofline": engine_roofline(other_engine, other_ms / 1e3),
+                              "identical_ciphertexts": other_same}}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -1109,7 +1158,8 @@ def main() -> int:
         "config": {"workload": "2048-bit key, 8 nodes x 65536 float64 ~ N(0,1), scale 2^20, "
                                "offset 2^23: quantize, encrypt 524288, 8-way sum, decrypt 65536, "
                                "dequantize", "nbits": NBITS, "nodes": NODES, "length": LENGTH,
-                   "window": w, "path": "batched", "modmul": args.modmul},
+                   "window": w, "path": "batched", "modmul": args.modmul,
+                   "encrypt_engine": main_engine},
         "enc_per_s": round(total / enc_avg_s, 1),
         "dec_per_s": round(LENGTH / (sum(dec_ms) / len(dec_ms) / 1e3), 1),
         "key_holder_enc_per_s": round(total / (enc_sk_ms / 1e3), 1),
@@ -1124,15 +1174,8 @@ def main() -> int:
                   if t_plain else None),
         "batched_over_plain": round(value / plain_value, 3) if t_plain else None,
         "end_to_end_exact": exact,
-        "roofline": {"bound": "alu", "kernel": "k_encrypt",
-                     "achieved": round(achieved / 1e12, 3),
-                     "peak": round(PEAK_PRODUCTS / 1e12, 3),
-                     "unit": "T limb-products/s (32x32->64, v_mad_u64_u32)",
-                     "frac": round(achieved / PEAK_PRODUCTS, 4),
-                     "traffic": measured_traffic(total),
-                     "per_launch_products": prod_enc * total,
-                     "mm_per_encrypt": mm_enc,
-                     "avg_launch_ms": round(enc_avg_s * 1e3, 3)},
+        "roofline": roofline,
+        "engines": engines,
         "cpu_baseline": cpu,
         "batching": batching,
         "serving": serving,
@@ -1143,7 +1186,7 @@ def main() -> int:
         "host": platform.node(),
     }
     print(json.dumps(out), flush=True)
-    return 0 if exact else 1
+    return 0 if exact and other_same else 1
 
 
 if __name__ == "__main__":

@@ -249,7 +249,7 @@ struct GeoOffsets {  // the n^2 constants that depend on the digit geometry
 struct PkOffsets {
   GeoOffsets g, alt;  // alt: only for classes with an alternative tile
   size_t n;
-  size_t mN, mNp, mR2, mnR, mN28;  // matrix-core product constants
+  size_t mN, mNp, mR2, mnR, mRk, mN28;  // matrix-core product constants
   int mS;
   SchedOffsets nsch;
 };
@@ -330,6 +330,18 @@ PkOffsets add_public(DevBuf& buf, const Limbs& n, int cls, int L) {
   o.mNp = buf.add(to_digits7(np, S));
   o.mR2 = buf.add(to_digits7(pc2h::pow2_mod(2 * RBm, N), S));
   o.mnR = buf.add(to_digits7(pc2h::shl_mod(n, RBm, N), S));
+  {  // R^k mod n^2, k = 0..RK_MAX (R = 2^RBm), by Montgomery products with 32-bit limbs
+    pc2h::Mont32 M(N);
+    const Limbs r1m = M.to(pc2h::pow2_mod(RBm, N));
+    Limbs rkm = M.to(Limbs{1});
+    std::vector<uint32_t> tab;
+    for (int k = 0; k <= pc2k::RK_MAX; ++k) {
+      const std::vector<uint32_t> d = to_digits7(M.from(rkm), S);
+      tab.insert(tab.end(), d.begin(), d.end());
+      rkm = M.mm(rkm, r1m);
+    }
+    o.mRk = buf.add(tab);
+  }
   o.mN28 = buf.add(to_limbs28(N, S));
   o.nsch = add_schedules(buf, n);
   return o;
@@ -347,6 +359,7 @@ pc2k::PkConst pk_const(const uint32_t* base, const PkOffsets& o, int L, int nbit
   c.mf.Np = (const uint8_t*)(base + o.mNp);
   c.mf.R2 = (const uint8_t*)(base + o.mR2);
   c.mf.nR = (const uint8_t*)(base + o.mnR);
+  c.mf.Rk = (const uint8_t*)(base + o.mRk);
   c.mf.N28 = base + o.mN28;
   c.mf.S = o.mS;
   c.nsch = sched_const(base, o.nsch);
@@ -452,9 +465,21 @@ int auto_window(int geo, int op) {
 
 int window_for(const pc2_ctx* ctx, int geo, int op) {
   if (ctx->window) return ctx->window;
+  if (op == pc2k::OP_FUSED_MFMA) op = pc2k::OP_ENC_MFMA;
   const int t = ctx->tuned[geo][op == pc2k::OP_FUSED ? pc2k::OP_ENC : op];
-  if (op == pc2k::OP_ENC_MFMA) return t ? t : (geo >= 5 ? 5 : 4);
+  // (matrix-core engine, 2048-bit keys: w = 6 measured 1 % faster than 5)
+  if (op == pc2k::OP_ENC_MFMA) return t ? t : (geo >= 6 ? 6 : (geo >= 5 ? 5 : 4));
   return t ? t : auto_window(geo, op);
+}
+
+// The Montgomery engine of an encryption (pc2_encrypt, pc2_enc_sum_dec)
+// under a key of class cls: the matrix cores when asked for, or
+// automatically from 2048-bit keys (class 6) on, where they measured faster
+// than the VALU engine on the MI355X.
+constexpr int MFMA_AUTO_CLASS = 6;
+bool use_mfma(const pc2_ctx* ctx, int cls) {
+  return ctx->modmul == PC2_MODMUL_MFMA ||
+         (ctx->modmul == PC2_MODMUL_AUTO && cls >= MFMA_AUTO_CLASS);
 }
 
 // Geometry of an encryption of `count` elements under the key class cls:
@@ -485,8 +510,9 @@ int occupancy(pc2_ctx* ctx, int geo, int op) {
   int& o = ctx->occ[geo][op];
   if (o == 0) {
     int v = 0;
-    const void* k = op == pc2k::OP_ENC_MFMA ? pc2k::kernel_encrypt_mfma(geo)
-                                            : pc2k::kernel_for(geo, op);
+    const void* k = op == pc2k::OP_ENC_MFMA     ? pc2k::kernel_encrypt_mfma(geo)
+                    : op == pc2k::OP_FUSED_MFMA ? pc2k::kernel_encrypt_mfma(geo, true)
+                                                : pc2k::kernel_for(geo, op);
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, 64, 0) != hipSuccess ||
         v <= 0)
       v = 1;
@@ -502,7 +528,8 @@ int occupancy(pc2_ctx* ctx, int geo, int op) {
 // every launch that asks for the same amount), then the tables.
 size_t plan_launch(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, int w,
                    pc2k::Launch* l, void* stream, size_t aux_words) {
-  const size_t epb = op == pc2k::OP_ENC_MFMA ? 1 : (size_t)pc2k::elems_per_block(geo);
+  const bool mf = op == pc2k::OP_ENC_MFMA || op == pc2k::OP_FUSED_MFMA;
+  const size_t epb = mf ? 1 : (size_t)pc2k::elems_per_block(geo);
   const size_t groups = (count + epb - 1) / epb;
   const size_t cap = (size_t)ctx->cus * occupancy(ctx, geo, op);
   l->grid = (int)std::max<size_t>(1, std::min(groups, cap));
@@ -511,7 +538,7 @@ size_t plan_launch(pc2_ctx* ctx, int geo, int op, size_t count, int Ls, int L, i
   l->stream = stream;
   int tiles = 0;
   size_t words = 0;
-  if (op == pc2k::OP_ENC_MFMA) {  // one table of 2^w digit arrays per workgroup
+  if (mf) {  // one table of 2^w digit arrays per workgroup
     tiles = 1;
     words = (pc2k::mfma_digit_bytes(geo) << w) / 4;
   } else {
@@ -557,10 +584,13 @@ size_t class_scratch_need(pc2_ctx* ctx, int cls, int L, int Ls, int nl2) {
   take(cls, pc2k::OP_SMUL, 0);
   take(cls, pc2k::OP_ENC_MFMA, 0);
   take(cls, pc2k::OP_DEC, ch * 2 * (size_t)(Ls + 1));
-  const size_t fused_aux = ch * 2 * (size_t)L + ch * 2 * (size_t)(Ls + 1) + 128 +
-                           ch * (pc2k::chunk_words(cls) + 1);
+  const size_t acc_words =
+      std::max(pc2k::chunk_words(cls), pc2k::mfma_digit_bytes(cls) / 4);  // either engine
+  const size_t fused_aux =
+      ch * 2 * (size_t)L + ch * 2 * (size_t)(Ls + 1) + 128 + ch * (acc_words + 1);
   take(cls, pc2k::OP_DEC, fused_aux);
   take(cls, pc2k::OP_FUSED, fused_aux);
+  take(cls, pc2k::OP_FUSED_MFMA, fused_aux);
   take(cls, pc2k::OP_ENC_CRT, ch * 2 * (size_t)(nl2 + 1));
   (void)occupancy(ctx, cls, pc2k::OP_SUM);
   return need;
@@ -948,9 +978,7 @@ int pc2_encrypt(const pc2_pk* pk, const uint32_t* m, uint32_t m_limbs, const uin
     return PC2_E_INVAL;
   pc2_ctx* ctx = pk->ctx;
   pc2k::Launch l{};
-  // the matrix-core engine when asked for, or automatically above 2048-bit
-  // keys, where it measured faster than the VALU engine on the MI355X
-  if (ctx->modmul == PC2_MODMUL_MFMA || (ctx->modmul == PC2_MODMUL_AUTO && pk->cls >= 7)) {
+  if (use_mfma(ctx, pk->cls)) {
     int rc = prepare(ctx, pk->cls, pc2k::OP_ENC_MFMA, count, 0, pk->L, &l, stream);
     if (!rc) rc = scratch_begin(ctx, stream);
     if (rc) return rc;
@@ -1135,14 +1163,18 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
   // running products (chunked, 16-byte aligned) and the input checks
   pc2_ctx* ctx = sk->ctx;
   const int Ls = sk->c.h[0].Ls, L = sk->pk.L, cls = sk->pk.cls;
+  const bool mf = use_mfma(ctx, cls);
   const size_t chunk = std::min(count, pc2k::DEC_CHUNK);
   const size_t prod_words = (chunk * 2 * (size_t)L + 63) & ~(size_t)63;
   const size_t half_words = (chunk * 2 * (size_t)(Ls + 1) + 63) & ~(size_t)63;
-  const size_t acc_words = chunk * pc2k::chunk_words(cls);
+  const size_t acc_words =
+      chunk * (mf ? pc2k::mfma_digit_bytes(cls) / 4 : pc2k::chunk_words(cls));
   const size_t aux = prod_words + half_words + acc_words + chunk;
   pc2k::Launch le{}, ld{};
   int rc = prepare(ctx, cls, pc2k::OP_DEC, chunk, Ls, L, &ld, stream, aux);
-  if (!rc) rc = prepare(ctx, cls, pc2k::OP_FUSED, chunk, Ls, L, &le, stream, aux);
+  if (!rc)
+    rc = prepare(ctx, cls, mf ? pc2k::OP_FUSED_MFMA : pc2k::OP_FUSED, chunk, Ls, L, &le, stream,
+                 aux);
   if (!rc) rc = scratch_begin(ctx, stream);
   if (rc) return rc;
   uint32_t* prod = le.aux;
@@ -1156,8 +1188,11 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
       mb.p[k] = ms.p[k] + b * m_limbs;
       rb.p[k] = rs.p[k] + b * (size_t)L;
     }
-    rc = status_of(
-        pc2k::launch_enc_prod(cls, le, sk->pk.c, mb, rb, (int)K, (int)m_limbs, prod, n, acc, okw));
+    rc = status_of(mf ? pc2k::launch_enc_prod_mfma(cls, le, sk->pk.c, mb, rb, (int)K,
+                                                   (int)m_limbs, prod, n,
+                                                   reinterpret_cast<uint8_t*>(acc), okw)
+                      : pc2k::launch_enc_prod(cls, le, sk->pk.c, mb, rb, (int)K, (int)m_limbs,
+                                              prod, n, acc, okw));
     if (!rc)
       rc = status_of(pc2k::launch_decrypt(cls, ld, sk->c, prod, m_out + b * L, n, halves));
   }

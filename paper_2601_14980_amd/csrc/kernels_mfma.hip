@@ -21,118 +21,174 @@ namespace {
 
 using pc2k::PkConst;
 
-// Wavefronts per SIMD, as measured on the MI355X: three up to 2048-bit keys
-// (one launch of 32768 encryptions: 120.5 ms against 134.2 ms with two,
-// although a few registers spill), two from 3072 bits on, where three spill
-// more than they gain (16384 encryptions: 148.3 ms with two, 192.9 ms with
-// three)
+// One element's c = r^n g^m (mod n^2) as the limbs U of the last product
+// (also in ws.xr).  The workgroup's table holds the odd powers and, after
+// them, the square sq.  Returns the input checks (m < n, 0 < r < n).
+template <class G>
+__device__ __forceinline__ uint32_t encrypt_element(pc2m::MWork<G>& ws, const PkConst& pk,
+                                                    const uint32_t* me, int m_limbs,
+                                                    const uint32_t* re, uint8_t* table, int w,
+                                                    int lane, int32_t (&U)[G::NT]) {
+  __shared__ uint32_t s_ok;
+  const pc2m::MConst& K = pk.mf;
+  const int half = 1 << (w - 1);                  // odd powers in the table
+  uint8_t* sq = table + (size_t)half * G::FB;     // (r R)^2 R^-1
+  const uint32_t* sched = pk.nsch.p[w - pc2k::SCHED_WMIN];
+  const int nsched = pk.nsch.n[w - pc2k::SCHED_WMIN];
+  if (lane == 0) s_ok = pc2ops::encrypt_inputs_ok(pk, me, m_limbs, re);
+  // g^m = MM(m, n R) + 1 = 1 + m n (mod n^2)
+  pc2m::load_x<G>(ws, me, m_limbs, lane);
+  pc2m::mont_mul<G>(ws, K, K.nR, lane, false, ws.gm, true, U);
+  // table entry j = (r R)^(2j+1) R^-2j: entry 0 = r R, the square, then
+  // one product by the square per entry
+  pc2m::load_x<G>(ws, re, pk.L, lane);
+  pc2m::mont_mul<G>(ws, K, K.R2, lane, true, table, false, U);
+  pc2m::mont_mul<G>(ws, K, ws.xf, lane, false, sq, false, U);
+  pc2m::load_fwd<G>(ws, table, lane);
+  for (int j = 1; j < half; ++j)
+    pc2m::mont_mul<G>(ws, K, sq, lane, false, table + (size_t)j * G::FB, false, U);
+  // (r R)^n by the sliding-window schedule of n, most significant first
+  pc2m::load_fwd<G>(ws, table + (size_t)((sched[0] & 0xFFFFu) >> 1) * G::FB, lane);
+  for (int si = 1; si < nsched; ++si) {
+    const uint32_t en = sched[si];
+    for (uint32_t k = en >> 16; k; --k)
+      pc2m::mont_mul<G>(ws, K, ws.xf, lane, true, nullptr, false, U);
+    const uint32_t dig = en & 0xFFFFu;
+    if (dig)
+      pc2m::mont_mul<G>(ws, K, table + (size_t)(dig >> 1) * G::FB, lane, true, nullptr, false,
+                        U);
+  }
+  // r^n g^m = MM(r^n R, g^m), |.| < 0.52 n^2
+  pc2m::mont_mul<G>(ws, K, ws.gm, lane, false, nullptr, false, U);
+  return s_ok;
+}
+
+// Limbs U (|value| < 0.52 n^2) -> the canonical residue as 2L words at out
+// (zeros if !ok).  The carries of the signed limbs are resolved in one pass
+// and a negative value (a borrow out of the top limb) takes n^2 once.  The
+// limbs go to the digit region of ws.xf, which is written before every
+// read (its zero pads stay zero for the next element).
+template <class G>
+__device__ __forceinline__ void store_canonical(pc2m::MWork<G>& ws, const pc2m::MConst& K,
+                                                const int32_t (&U)[G::NT], int lane,
+                                                uint32_t* out, int L2, bool ok) {
+  uint32_t* u = reinterpret_cast<uint32_t*>(ws.xf + G::PF);
+#pragma unroll
+  for (int q = 0; q < G::NT; ++q) {
+    const int gi = 64 * q + lane - G::S;
+    if (gi >= 0 && gi < G::S) u[gi] = (uint32_t)U[q];
+  }
+  pc2m::wave_sync();
+  if (lane == 0) {
+    int32_t cy = 0;
+    for (int i = 0; i < G::S; ++i) {
+      const int32_t t = (int32_t)u[i] + cy;
+      u[i] = (uint32_t)t & pc2m::M28;
+      cy = t >> 28;
+    }
+    if (cy < 0) {
+      uint32_t cr = 0;
+      for (int i = 0; i < G::S; ++i) {
+        const uint32_t t = u[i] + K.N28[i] + cr;
+        u[i] = t & pc2m::M28;
+        cr = t >> 28;
+      }
+    }
+  }
+  pc2m::wave_sync();
+  for (int j = lane; j < L2; j += 64) {
+    const int b = 32 * j, i = b / 28, s = b % 28;
+    const uint64_t acc = (uint64_t)(i < G::S ? u[i] : 0u) |
+                         ((uint64_t)(i + 1 < G::S ? u[i + 1] : 0u) << 28) |
+                         ((uint64_t)(i + 2 < G::S ? u[i + 2] : 0u) << 56);
+    out[j] = ok ? (uint32_t)(acc >> s) : 0u;
+  }
+  pc2m::wave_sync();
+}
+
+// Wavefronts per SIMD, as measured on the MI355X: three up to 2048-bit keys,
+// where the workspace (12 KB of LDS) and 168 registers still allow it, two
+// from 3072 bits on, where three spill more than they gain
 template <int S>
 __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
     PkConst pk, const uint32_t* __restrict__ m, int m_limbs, const uint32_t* __restrict__ r,
     uint32_t* __restrict__ c, size_t count, uint8_t* __restrict__ scratch, int w, int* err) {
   using G = pc2m::MGeo<S>;
   __shared__ __align__(16) pc2m::MWork<G> ws;
-  __shared__ uint32_t s_ok;
   const int lane = threadIdx.x;
-  const pc2m::MConst& K = pk.mf;
   uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::FB << w);
   const int L = pk.L;
-  const int half = 1 << (w - 1);                  // odd powers in the table
-  uint8_t* sq = table + (size_t)half * G::FB;     // (r R)^2 R^-1
-  const uint32_t* sched = pk.nsch.p[w - pc2k::SCHED_WMIN];
-  const int nsched = pk.nsch.n[w - pc2k::SCHED_WMIN];
   pc2m::init_work<G>(ws, lane);
-  pc2m::init_table<G>(table, half + 1, lane);
+  pc2m::init_table<G>(table, (1 << (w - 1)) + 1, lane);
   int32_t U[G::NT];
   for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
-    const uint32_t* me = m + e * m_limbs;
-    const uint32_t* re = r + e * L;
-    if (lane == 0) s_ok = pc2ops::encrypt_inputs_ok(pk, me, m_limbs, re);
-    // g^m = 1 + m n
-    pc2m::load_x<G>(ws, me, m_limbs, lane);
-    pc2m::mont_mul<G>(ws, K, K.nR, lane, false, ws.gm, true, U);
-    // table entry j = (r R)^(2j+1) R^-2j: entry 0 = r R, the square, then
-    // one product by the square per entry
-    pc2m::load_x<G>(ws, re, L, lane);
-    pc2m::mont_mul<G>(ws, K, K.R2, lane, true, table, false, U);
-    pc2m::mont_mul<G>(ws, K, ws.xf, lane, false, sq, false, U);
-    pc2m::load_fwd<G>(ws, table, lane);
-    for (int j = 1; j < half; ++j)
-      pc2m::mont_mul<G>(ws, K, sq, lane, false, table + (size_t)j * G::FB, false, U);
-    // (r R)^n by the sliding-window schedule of n, most significant first
-    pc2m::load_fwd<G>(ws, table + (size_t)((sched[0] & 0xFFFFu) >> 1) * G::FB, lane);
-    for (int si = 1; si < nsched; ++si) {
-      const uint32_t en = sched[si];
-      for (uint32_t k = en >> 16; k; --k)
-        pc2m::mont_mul<G>(ws, K, ws.xf, lane, true, nullptr, false, U);
-      const uint32_t dig = en & 0xFFFFu;
-      if (dig)
-        pc2m::mont_mul<G>(ws, K, table + (size_t)(dig >> 1) * G::FB, lane, true, nullptr, false, U);
-    }
-    // r^n g^m = MM(r^n R, g^m), |.| < 0.52 n^2
-    pc2m::mont_mul<G>(ws, K, ws.gm, lane, false, nullptr, false, U);
-    // canonical: resolve the carries of the signed limbs; a negative value
-    // (a borrow out of the top limb) takes n^2 once.  The limbs go to the
-    // digit region of ws.xf, which is written before every read (its zero
-    // pads stay zero for the next element).
-    uint32_t* u = reinterpret_cast<uint32_t*>(ws.xf + G::PF);
-#pragma unroll
-    for (int q = 0; q < G::NT; ++q) {
-      const int gi = 64 * q + lane - G::S;
-      if (gi >= 0 && gi < G::S) u[gi] = (uint32_t)U[q];
-    }
-    pc2m::wave_sync();
-    if (lane == 0) {
-      int32_t cy = 0;
-      for (int i = 0; i < G::S; ++i) {
-        const int32_t t = (int32_t)u[i] + cy;
-        u[i] = (uint32_t)t & pc2m::M28;
-        cy = t >> 28;
-      }
-      if (cy < 0) {
-        uint32_t cr = 0;
-        for (int i = 0; i < G::S; ++i) {
-          const uint32_t t = u[i] + K.N28[i] + cr;
-          u[i] = t & pc2m::M28;
-          cr = t >> 28;
-        }
-      }
-    }
-    pc2m::wave_sync();
-    const uint32_t ok = s_ok;
-    uint32_t* ce = c + e * 2 * (size_t)L;
-    for (int j = lane; j < 2 * L; j += 64) {
-      const int b = 32 * j, i = b / 28, s = b % 28;
-      const uint64_t acc = (uint64_t)(i < G::S ? u[i] : 0u) |
-                           ((uint64_t)(i + 1 < G::S ? u[i + 1] : 0u) << 28) |
-                           ((uint64_t)(i + 2 < G::S ? u[i + 2] : 0u) << 56);
-      ce[j] = ok ? (uint32_t)(acc >> s) : 0u;
-    }
+    const uint32_t ok =
+        encrypt_element<G>(ws, pk, m + e * m_limbs, m_limbs, r + e * L, table, w, lane, U);
+    store_canonical<G>(ws, pk.mf, U, lane, c + e * 2 * (size_t)L, 2 * L, ok);
     if (lane == 0 && !ok) atomicOr(err, pc2k::ERR_RANGE);
-    pc2m::wave_sync();
+  }
+}
+
+// Step `step` of the fused encrypt -> K-way product (Def. 1 applied K - 1
+// times) over the matrix cores: element e's encryption c_k, then one more
+// product acc_e <- MM(c_k, y) with y = R^K for the first step and the
+// running product acc_e after it, so that the last step leaves
+// R^K prod_k c_k R^-K = prod_k c_k, canonical, in prod.  acc: one forward
+// digit array per element (mfma_digit_bytes), in the caller's staging; ok:
+// one word per element, the AND of every step's input checks.
+template <int S>
+__global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_enc_acc_mfma(
+    PkConst pk, const uint32_t* __restrict__ m, int m_limbs, const uint32_t* __restrict__ r,
+    int Kn, int step, uint8_t* __restrict__ acc, uint32_t* __restrict__ ok_all,
+    uint32_t* __restrict__ prod, size_t count, uint8_t* __restrict__ scratch, int w, int* err) {
+  using G = pc2m::MGeo<S>;
+  __shared__ __align__(16) pc2m::MWork<G> ws;
+  const int lane = threadIdx.x;
+  uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::FB << w);
+  const int L = pk.L;
+  const bool last = step + 1 == Kn;
+  pc2m::init_work<G>(ws, lane);
+  pc2m::init_table<G>(table, (1 << (w - 1)) + 1, lane);
+  int32_t U[G::NT];
+  for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
+    uint8_t* acc_e = acc + e * (size_t)G::FB;
+    uint32_t ok =
+        encrypt_element<G>(ws, pk, m + e * m_limbs, m_limbs, r + e * L, table, w, lane, U);
+    if (step) ok &= ok_all[e];
+    // the running product's front pad is read as zero by the next step
+    if (step == 0 && lane < G::PF / 4) reinterpret_cast<uint32_t*>(acc_e)[lane] = 0u;
+    const uint8_t* y = step ? acc_e : pk.mf.Rk + (size_t)Kn * G::FB;
+    pc2m::mont_mul<G>(ws, pk.mf, y, lane, false, last ? nullptr : acc_e, false, U);
+    if (!last) {
+      if (lane == 0) ok_all[e] = ok;
+    } else {
+      store_canonical<G>(ws, pk.mf, U, lane, prod + e * 2 * (size_t)L, 2 * L, ok);
+      if (lane == 0 && !ok) atomicOr(err, pc2k::ERR_RANGE);
+    }
   }
 }
 
 template <int C>
-const void* mfma_kernel() {
-  return (const void*)&k_encrypt_mfma<pc2k::MFMA_S[C]>;
+const void* mfma_kernel(bool fused) {
+  return fused ? (const void*)&k_enc_acc_mfma<pc2k::MFMA_S[C]>
+               : (const void*)&k_encrypt_mfma<pc2k::MFMA_S[C]>;
 }
 
 }  // namespace
 
 namespace pc2k {
 
-const void* kernel_encrypt_mfma(int cls) {
+const void* kernel_encrypt_mfma(int cls, bool fused) {
   switch (cls) {
-    case 0: return mfma_kernel<0>();
-    case 1: return mfma_kernel<1>();
-    case 2: return mfma_kernel<2>();
-    case 3: return mfma_kernel<3>();
-    case 4: return mfma_kernel<4>();
-    case 5: return mfma_kernel<5>();
-    case 6: return mfma_kernel<6>();
-    case 7: return mfma_kernel<7>();
-    case 8: return mfma_kernel<8>();
+    case 0: return mfma_kernel<0>(fused);
+    case 1: return mfma_kernel<1>(fused);
+    case 2: return mfma_kernel<2>(fused);
+    case 3: return mfma_kernel<3>(fused);
+    case 4: return mfma_kernel<4>(fused);
+    case 5: return mfma_kernel<5>(fused);
+    case 6: return mfma_kernel<6>(fused);
+    case 7: return mfma_kernel<7>(fused);
+    case 8: return mfma_kernel<8>(fused);
   }
   return nullptr;
 }
@@ -151,6 +207,27 @@ hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, cons
   void* args[] = {(void*)&pk, (void*)&m, (void*)&m_limbs, (void*)&r, (void*)&c,
                   (void*)&count, (void*)&scratch, (void*)&w, (void*)&l.err};
   return hipLaunchKernel(k, dim3(l.grid), dim3(64), args, 0, (hipStream_t)l.stream);
+}
+
+hipError_t launch_enc_prod_mfma(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
+                                const PtrList& rs, int K, int m_limbs, uint32_t* prod,
+                                size_t count, uint8_t* acc, uint32_t* ok) {
+  const void* k = kernel_encrypt_mfma(cls, true);
+  if (!k) return hipErrorInvalidValue;
+  uint8_t* scratch = reinterpret_cast<uint8_t*>(l.scratch);
+  int w = l.window;
+  for (int step = 0; step < K; ++step) {
+    const uint32_t* m = ms.p[step];
+    const uint32_t* r = rs.p[step];
+    void* args[] = {(void*)&pk,   (void*)&m,    (void*)&m_limbs, (void*)&r,
+                    (void*)&K,    (void*)&step, (void*)&acc,     (void*)&ok,
+                    (void*)&prod, (void*)&count, (void*)&scratch, (void*)&w,
+                    (void*)&l.err};
+    const hipError_t e =
+        hipLaunchKernel(k, dim3(l.grid), dim3(64), args, 0, (hipStream_t)l.stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace pc2k

@@ -10,7 +10,8 @@ enum Op {
   OP_ENC = 0, OP_DEC = 1, OP_SUM = 2, OP_SMUL = 3, OP_FUSED = 4,
   OP_ENC_MFMA = 5,  // encryption with the matrix-core product (kernels_mfma.hip)
   OP_ENC_CRT = 6,   // key-holder encryption through p^2 and q^2
-  OP_COUNT = 7
+  OP_FUSED_MFMA = 7,  // OP_FUSED with the matrix-core product
+  OP_COUNT = 8
 };
 
 // kernel_for, slot_shape, elems_per_block and launch_encrypt take a geometry
@@ -45,11 +46,17 @@ hipError_t launch_enc_prod(int cls, const Launch& l, const PkConst& pk, const Pt
 size_t chunk_words(int geo);  // words of one n^2 residue in the geometry's chunked layout
 
 // encryption with the i8-MFMA Montgomery product (kernels_mfma.hip); the
-// scratch holds 2^window forward digit arrays per workgroup
-const void* kernel_encrypt_mfma(int cls);
+// scratch holds 2^window forward digit arrays per workgroup; fused: the
+// kernel of one step of the fused path
+const void* kernel_encrypt_mfma(int cls, bool fused = false);
 size_t mfma_digit_bytes(int cls);
 hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
                                int m_limbs, const uint32_t* r, uint32_t* c, size_t count);
+// launch_enc_prod over the matrix cores; acc: mfma_digit_bytes(cls) bytes
+// (16-byte aligned) per element
+hipError_t launch_enc_prod_mfma(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,
+                                const PtrList& rs, int K, int m_limbs, uint32_t* prod,
+                                size_t count, uint8_t* acc, uint32_t* ok);
 
 // ciphertext matrix-vector product (kernels_matvec.hip), by key class:
 // which = 0 the table kernel, 1 the row kernel

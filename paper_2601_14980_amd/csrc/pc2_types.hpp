@@ -43,6 +43,7 @@ struct MfmaConst {
   const uint8_t* Np;     // -(n^2)^-1 mod R
   const uint8_t* R2;     // R^2 mod n^2
   const uint8_t* nR;     // n R mod n^2
+  const uint8_t* Rk;     // R^k mod n^2 for k = 0..RK_MAX, entry k at k (64 + D8 + 16)
   const uint32_t* N28;   // n^2 as S limbs of 28 bits
   int S;
 };

@@ -3,7 +3,7 @@
 With PC2_OPT_MODMUL = PC2_MODMUL_MFMA, pc2_encrypt runs its modular
 products on the matrix cores.  Every ciphertext must equal the oracle's and
 the VALU path's bit for bit; decryption must invert it.  The default
-(PC2_MODMUL_AUTO) takes the matrix cores above 2048 bits."""
+(PC2_MODMUL_AUTO) takes the matrix cores from 2048 bits on."""
 from __future__ import annotations
 
 import math
@@ -106,10 +106,10 @@ def test_mfma_range_errors(mfma_ctx):
     assert mfma_ctx.sync() == 0   # the error latch was cleared
 
 
-@pytest.mark.parametrize("nbits", [2048, 3072])
+@pytest.mark.parametrize("nbits", [1024, 2048, 3072])
 def test_auto_engine(valu_ctx, nbits):
     """A fresh context defaults to PC2_MODMUL_AUTO; its ciphertexts (the MFMA
-    engine at 3072 bits, the VALU engine at 2048) equal the VALU engine's."""
+    engine from 2048 bits on, the VALU engine below) equal the VALU engine's."""
     from paper_2601_14980_amd import pc2
     ctx = pc2.Context(0)
     assert ctx.get_option(pc2.PC2_OPT_MODMUL) == pc2.PC2_MODMUL_AUTO

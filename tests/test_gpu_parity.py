@@ -156,12 +156,23 @@ def test_fused_enc_sum_dec(gpu_ctx, sized):
     assert out == want
 
 
-@pytest.mark.parametrize("nbits,K", [(1024, 1), (1024, 2), (1024, 9), (256, 128)])
-def test_fused_number_of_addends(gpu_ctx, nbits, K):
-    """The fused path runs one encrypt-and-accumulate step per addend: one
-    addend (the first step is also the last), a few, and the most a call
-    takes; a bad input in any step zeroes that element and latches the
-    error, the others stay exact."""
+@pytest.mark.parametrize("engine", ["valu", "mfma"])
+@pytest.mark.parametrize("nbits,K", [(1024, 1), (1024, 2), (1024, 9), (256, 128), (2048, 3)])
+def test_fused_number_of_addends(gpu_ctx, nbits, K, engine):
+    """The fused path runs one encrypt-and-accumulate step per addend, with
+    either Montgomery engine: one addend (the first step is also the last),
+    a few, and the most a call takes; a bad input in any step zeroes that
+    element and latches the error, the others stay exact."""
+    from paper_2601_14980_amd import pc2
+    gpu_ctx.set_option(pc2.PC2_OPT_MODMUL,
+                       pc2.PC2_MODMUL_MFMA if engine == "mfma" else pc2.PC2_MODMUL_VALU)
+    try:
+        _fused_addends(gpu_ctx, nbits, K)
+    finally:
+        gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
+
+
+def _fused_addends(gpu_ctx, nbits, K):
     p, q = gen.primes_for(98, nbits)
     sk, _, osk = keys(gpu_ctx, p, q, nbits)
     n = p * q

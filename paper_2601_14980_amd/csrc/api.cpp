@@ -44,6 +44,9 @@ struct pc2_runner {
   size_t jobs_b = 0, items_b = 0, ptr_b = 0;
   uint32_t* scratch = nullptr;
   uint32_t* stage = nullptr;  // decryption: CRT halves of one launch's groups
+  uint8_t* mscratch = nullptr;  // encryption on the matrix cores: tables of the widest grid
+  size_t mscratch_bytes = 0;
+  int mocc[pc2k::NUM_CLASSES] = {};  // resident workgroups per CU of k_batch_mfma per class
   hipEvent_t copied = nullptr;
   bool pending = false;
 };
@@ -68,6 +71,15 @@ struct pc2_batch {
   int* queue = nullptr;
   uint32_t* scratch = nullptr;
   uint32_t* stage = nullptr;  // decryption: CRT halves of every job's elements
+  // encryption jobs of up to two key classes that run on the matrix cores:
+  // per class its own items (after the others), queue, grid and window; one
+  // table scratch for both (the launches run in order on one stream)
+  struct MPart {
+    int cls = -1, grid = 0, nitems = 0, w = 6, sub = 1;  // sub: largest group of its jobs
+    pc2k::BatchItem* items = nullptr;
+    int* queue = nullptr;
+  } mp[2];
+  uint8_t* mscratch = nullptr;
   hipGraphExec_t exec = nullptr;
   void* graph_stream = nullptr;
 };
@@ -1200,6 +1212,15 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
 }
 
 // ---------------------------------------------------------------- batches
+// resident workgroups per CU of a 64-lane kernel (1 if the runtime cannot tell)
+int occupancy_of(const void* k) {
+  int occ = 0;
+  if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 64, 0) != hipSuccess ||
+      occ <= 0)
+    occ = 1;
+  return occ;
+}
+
 int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch** out) {
   if (!ctx || !jobs || !out || njobs == 0) return PC2_E_INVAL;
   *out = nullptr;
@@ -1209,8 +1230,9 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
   else if (op_abi == PC2_OP_DECRYPT) op = pc2k::OP_DEC;
   else if (op_abi == PC2_OP_HOM_SUM) op = pc2k::OP_SUM;
   else return PC2_E_INVAL;
-  // validate and collect classes
-  int ca = -1, cb = -1, Ls = 0;
+  // validate and collect classes: the VALU kernel's pair, and the (up to
+  // two) classes whose encryptions run on the matrix cores (use_mfma)
+  int ca = -1, cb = -1, mca = -1, mcb = -1, Ls = 0;
   for (size_t i = 0; i < njobs; ++i) {
     const pc2_job& j = jobs[i];
     if (j.op != op_abi) return PC2_E_INVAL;
@@ -1228,38 +1250,59 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     }
     if (job_overlaps(j, pk->L)) return PC2_E_INVAL;
     if (op == pc2k::OP_DEC) Ls = std::max(Ls, j.sk->c.h[0].Ls);
+    if (op == pc2k::OP_ENC && use_mfma(ctx, pk->cls)) {
+      if (mca < 0 || mca == pk->cls) mca = pk->cls;
+      else if (mcb < 0 || mcb == pk->cls) mcb = pk->cls;
+      else return PC2_E_UNSUPPORTED;
+      continue;
+    }
     const int g = job_geo(ctx, pk, op);
     if (ca < 0 || ca == g) ca = g;
     else if (cb < 0 || cb == g) cb = g;
     else return PC2_E_UNSUPPORTED;
   }
-  if (ca < 0) return PC2_E_INVAL;  // every job empty
-  if (cb < 0) cb = ca;
-  const int pair = pc2k::batch_pair(ca, cb);
-  if (pair < 0) return PC2_E_UNSUPPORTED;
-  const int pa = pc2k::batch_pair_geo(pair, 0), pb = pc2k::batch_pair_geo(pair, 1);
+  if (ca < 0 && mca < 0) return PC2_E_INVAL;  // every job empty
+  if (mca >= 0 && mcb > mca) std::swap(mca, mcb);  // the more expensive class first
+  int pair = -1, pa = -1, pb = -1;
+  if (ca >= 0) {
+    if (cb < 0) cb = ca;
+    pair = pc2k::batch_pair(ca, cb);
+    if (pair < 0) return PC2_E_UNSUPPORTED;
+    pa = pc2k::batch_pair_geo(pair, 0);
+    pb = pc2k::batch_pair_geo(pair, 1);
+  }
   pc2_batch* b = new (std::nothrow) pc2_batch();
   if (!b) return PC2_E_NOMEM;
   b->ctx = ctx;
   b->op = op;
   b->pair = pair;
-  b->w_a = window_for(ctx, pa, op);
-  b->w_b = window_for(ctx, pb, op);
+  if (pair >= 0) {
+    b->w_a = window_for(ctx, pa, op);
+    b->w_b = window_for(ctx, pb, op);
+  }
+  b->mp[0].cls = mca;
+  b->mp[1].cls = mcb;
+  for (auto& m : b->mp)
+    if (m.cls >= 0) m.w = window_for(ctx, m.cls, pc2k::OP_ENC_MFMA);
   // descriptors and items (most expensive class first)
   std::vector<pc2k::BatchJob> dj;
   std::vector<pc2k::BatchItem> items;
   std::vector<size_t> ptrbuf;  // per hom_sum job: K pointers then K lengths
   std::vector<size_t> ptr_off;
+  std::vector<bool> mjob;      // runs on the matrix cores
   for (size_t i = 0; i < njobs; ++i) {
     const pc2_job& j = jobs[i];
     if (j.count == 0) continue;
     pc2k::BatchJob d{};
     const pc2_pk* pk = (op == pc2k::OP_DEC) ? &j.sk->pk : j.pk;
-    d.geo = job_geo(ctx, pk, op);
+    const bool mf = op == pc2k::OP_ENC && (pk->cls == mca || pk->cls == mcb);
+    d.geo = mf ? pk->cls : job_geo(ctx, pk, op);
+    d.group = pc2k::batch_group_elems(op, job_geo(ctx, pk, op));
     d.op = op;
     d.m_limbs = (int)j.m_limbs;
     d.K = (int)j.K;
-    d.pk = geo_const(pk, d.geo);
+    d.pk = mf ? pk->c : geo_const(pk, d.geo);
+    mjob.push_back(mf);
     if (op == pc2k::OP_DEC) d.sk = j.sk->c;
     d.in0 = j.in0;
     d.in1 = j.in1;
@@ -1273,12 +1316,12 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     ptr_off.push_back(off);
     dj.push_back(d);
   }
-  const int first_geo = pc2k::GEO_CLASS[pa] >= pc2k::GEO_CLASS[pb] ? pa : pb;
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pair >= 0 && pass < 2; ++pass) {
+    const int first_geo = pc2k::GEO_CLASS[pa] >= pc2k::GEO_CLASS[pb] ? pa : pb;
     const int want = pass == 0 ? first_geo : (first_geo == pa ? pb : pa);
     if (pass == 1 && pa == pb) break;
     for (size_t ji = 0; ji < dj.size(); ++ji) {
-      if (dj[ji].geo != want) continue;
+      if (mjob[ji] || dj[ji].geo != want) continue;
       const size_t epw = (size_t)pc2k::batch_group_elems(op, dj[ji].geo);
       const size_t groups = (dj[ji].count + epw - 1) / epw;
       for (size_t g = 0; g < groups; ++g) {
@@ -1288,6 +1331,17 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     }
   }
   b->nitems = (int)items.size();
+  std::vector<size_t> mfirst(2, 0);
+  for (int part = 0; part < 2; ++part) {  // matrix-core items after the others, per class
+    mfirst[part] = items.size();
+    for (size_t ji = 0; ji < dj.size(); ++ji) {
+      if (!mjob[ji] || b->mp[part].cls < 0 || dj[ji].geo != b->mp[part].cls) continue;
+      b->mp[part].sub = std::max(b->mp[part].sub, dj[ji].group);
+      const size_t groups = (dj[ji].count + dj[ji].group - 1) / dj[ji].group;
+      for (size_t g = 0; g < groups; ++g) items.push_back(pc2k::BatchItem{(int)ji, 0, g});
+    }
+    b->mp[part].nitems = (int)(items.size() - mfirst[part]);
+  }
   // decryption: staging for the two CRT halves of every element
   std::vector<size_t> stage_off(dj.size(), 0);
   size_t stage_words = 0;
@@ -1319,6 +1373,10 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     b->items = (pc2k::BatchItem*)(base + jobs_b);
     size_t* dptr = (size_t*)(base + jobs_b + items_b);
     b->queue = (int*)(base + jobs_b + items_b + ptr_b);
+    for (int part = 0; part < 2; ++part) {
+      b->mp[part].items = b->items + mfirst[part];
+      b->mp[part].queue = b->queue + 32 * (part + 1);
+    }
     for (size_t ji = 0; ji < dj.size(); ++ji)
       if (op == pc2k::OP_SUM) {
         dj[ji].inputs = (const uint32_t* const*)(dptr + ptr_off[ji]);
@@ -1332,8 +1390,17 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
                                       hipMemcpyHostToDevice) != hipSuccess))
       rc = PC2_E_DEVICE;
   }
-  // grid and the batch's own scratch
-  if (!rc) {
+  // grids and the batch's own scratch
+  size_t mbytes = 0;
+  for (auto& m : b->mp) {
+    if (rc || !m.nitems) continue;
+    m.grid = std::max<int>(
+        1, (int)std::min<size_t>((size_t)ctx->cus * occupancy_of(pc2k::batch_mfma_kernel(m.cls)),
+                                 (size_t)m.nitems * m.sub));
+    mbytes = std::max(mbytes, (size_t)m.grid * (pc2k::mfma_digit_bytes(m.cls) << m.w));
+  }
+  if (!rc && mbytes && hipMalloc(&b->mscratch, mbytes) != hipSuccess) rc = PC2_E_NOMEM;
+  if (!rc && b->nitems) {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pc2k::batch_kernel(op, pair), 64, 0) !=
             hipSuccess ||
@@ -1352,6 +1419,7 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
   if (rc) {
     if (b->dev) (void)hipFree(b->dev);
     if (b->scratch) (void)hipFree(b->scratch);
+    if (b->mscratch) (void)hipFree(b->mscratch);
     if (b->stage) (void)hipFree(b->stage);
     delete b;
     return rc;
@@ -1364,8 +1432,15 @@ int pc2_batch_run(pc2_batch* b, void* hip_stream) {
   if (!b || !b->ctx) return PC2_E_INVAL;
   if (hipSetDevice(b->ctx->device) != hipSuccess) return PC2_E_DEVICE;
   auto launch = [&](void* st) {
-    return pc2k::launch_batch(b->op, b->pair, b->grid, b->jobs, b->items, b->nitems, b->queue,
-                              b->scratch, b->slot_words, b->w_a, b->w_b, b->ctx->err, st);
+    hipError_t e = hipSuccess;
+    if (b->nitems)
+      e = pc2k::launch_batch(b->op, b->pair, b->grid, b->jobs, b->items, b->nitems, b->queue,
+                             b->scratch, b->slot_words, b->w_a, b->w_b, b->ctx->err, st);
+    for (const auto& m : b->mp)
+      if (e == hipSuccess && m.nitems)
+        e = pc2k::launch_batch_mfma(m.cls, m.grid, b->jobs, m.items, m.nitems, m.sub, m.queue,
+                                    b->mscratch, m.w, b->ctx->err, st);
+    return e;
   };
   if (!hip_stream) return status_of(launch(nullptr));
   if (!b->exec || b->graph_stream != hip_stream) {
@@ -1401,6 +1476,7 @@ int pc2_batch_destroy(pc2_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->dev) (void)hipFree(b->dev);
   if (b->scratch) (void)hipFree(b->scratch);
+  if (b->mscratch) (void)hipFree(b->mscratch);
   if (b->stage) (void)hipFree(b->stage);
   delete b;
   return PC2_OK;
@@ -1554,6 +1630,16 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
     r->slot_words = (words + 3) & ~(size_t)3;
     const size_t bytes = (size_t)r->grid_cap * tiles * r->slot_words * 4;
     if (bytes && hipMalloc(&r->scratch, bytes) != hipSuccess) rc = PC2_E_NOMEM;
+    // encryption jobs of a class on the matrix cores (the engine option may
+    // change after creation, so every class up to the largest is covered)
+    for (int c = 0; !rc && op == pc2k::OP_ENC && c <= cls; ++c) {
+      r->mocc[c] = occupancy_of(pc2k::batch_mfma_kernel(c));
+      r->mscratch_bytes =
+          std::max(r->mscratch_bytes, (size_t)ctx->cus * r->mocc[c] *
+                                          (pc2k::mfma_digit_bytes(c) << pc2k::SCHED_WMAX));
+    }
+    if (!rc && r->mscratch_bytes && hipMalloc(&r->mscratch, r->mscratch_bytes) != hipSuccess)
+      rc = PC2_E_NOMEM;
     if (!rc && op == pc2k::OP_DEC) {  // CRT halves of up to max_groups groups
       size_t per = 0;
       for (int g = 0; g < pc2k::NUM_GEOS; ++g)
@@ -1566,6 +1652,7 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
     if (r->dev) (void)hipFree(r->dev);
     if (r->host) (void)hipHostFree(r->host);
     if (r->scratch) (void)hipFree(r->scratch);
+    if (r->mscratch) (void)hipFree(r->mscratch);
     if (r->stage) (void)hipFree(r->stage);
     if (r->copied) (void)hipEventDestroy(r->copied);
     delete r;
@@ -1588,7 +1675,7 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
   if (njobs > r->max_jobs) return PC2_E_BUSY;
   pc2_ctx* ctx = r->ctx;
   const int op = r->op;
-  int ca = -1, cb = -1;
+  int ca = -1, cb = -1, mca = -1, mcb = -1;
   size_t nitems = 0, nptrs = 0;
   for (size_t i = 0; i < njobs; ++i) {
     const pc2_job& j = jobs[i];
@@ -1609,15 +1696,25 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     }
     if (job_overlaps(j, pk->L)) return PC2_E_INVAL;
     nitems += ngroups[i];
+    if (ngroups[i] == 0) continue;
+    if (op == pc2k::OP_ENC && use_mfma(ctx, pk->cls)) {
+      if (mca < 0 || mca == pk->cls) mca = pk->cls;
+      else if (mcb < 0 || mcb == pk->cls) mcb = pk->cls;
+      else return PC2_E_UNSUPPORTED;
+      continue;
+    }
     if (ca < 0 || ca == g) ca = g;
     else if (cb < 0 || cb == g) cb = g;
     else return PC2_E_UNSUPPORTED;
   }
   if (nitems == 0) return PC2_OK;
   if (nitems > r->max_groups || nptrs > r->max_ptrs) return PC2_E_BUSY;
-  if (cb < 0) cb = ca;
-  const int pair = pc2k::batch_pair(ca, cb);
-  if (pair < 0) return PC2_E_UNSUPPORTED;
+  int pair = -1;
+  if (ca >= 0) {
+    if (cb < 0) cb = ca;
+    pair = pc2k::batch_pair(ca, cb);
+    if (pair < 0) return PC2_E_UNSUPPORTED;
+  }
   if (hipSetDevice(ctx->device) != hipSuccess) return PC2_E_DEVICE;
   // the previous launch's copies must have read the staging buffers
   if (r->pending && hipEventSynchronize(r->copied) != hipSuccess) return PC2_E_DEVICE;
@@ -1628,16 +1725,19 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
   auto* hp = (size_t*)(hb + r->jobs_b + r->items_b);
   auto* dp = (size_t*)(db + r->jobs_b + r->items_b);
   size_t pofs = 0, it = 0, sofs = 0;
-  const int pa = pc2k::batch_pair_geo(pair, 0), pb = pc2k::batch_pair_geo(pair, 1);
+  const int pa = pair >= 0 ? pc2k::batch_pair_geo(pair, 0) : -1;
+  const int pb = pair >= 0 ? pc2k::batch_pair_geo(pair, 1) : -1;
   for (size_t i = 0; i < njobs; ++i) {
     const pc2_job& j = jobs[i];
     const pc2_pk* pk = (op == pc2k::OP_DEC) ? &j.sk->pk : j.pk;
+    const bool mf = op == pc2k::OP_ENC && (pk->cls == mca || pk->cls == mcb);
     pc2k::BatchJob d{};
-    d.geo = job_geo(ctx, pk, op);
+    d.geo = mf ? pk->cls : job_geo(ctx, pk, op);
+    d.group = pc2k::batch_group_elems(op, job_geo(ctx, pk, op));
     d.op = op;
     d.m_limbs = (int)j.m_limbs;
     d.K = (int)j.K;
-    d.pk = geo_const(pk, d.geo);
+    d.pk = mf ? pk->c : geo_const(pk, d.geo);
     if (op == pc2k::OP_DEC) d.sk = j.sk->c;
     d.in0 = j.in0;
     d.in1 = j.in1;
@@ -1658,18 +1758,36 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     }
     hj[i] = d;
   }
-  // most expensive class first
-  const int first_geo = pc2k::GEO_CLASS[pa] >= pc2k::GEO_CLASS[pb] ? pa : pb;
-  for (int pass = 0; pass < 2; ++pass) {
+  // most expensive class first; the matrix-core items after the others
+  auto on_mfma = [&](size_t i) {
+    const pc2_pk* pk = (op == pc2k::OP_DEC) ? &jobs[i].sk->pk : jobs[i].pk;
+    return op == pc2k::OP_ENC && (pk->cls == mca || pk->cls == mcb);
+  };
+  for (int pass = 0; pair >= 0 && pass < 2; ++pass) {
+    const int first_geo = pc2k::GEO_CLASS[pa] >= pc2k::GEO_CLASS[pb] ? pa : pb;
     const int want = pass == 0 ? first_geo : (first_geo == pa ? pb : pa);
     if (pass == 1 && pa == pb) break;
     for (size_t i = 0; i < njobs; ++i) {
-      if (hj[i].geo != want) continue;
+      if (on_mfma(i) || hj[i].geo != want) continue;
       for (size_t g = 0; g < ngroups[i]; ++g) {
         hi[it++] = pc2k::BatchItem{(int)i, 0, first[i] + g};
         if (op == pc2k::OP_DEC) hi[it++] = pc2k::BatchItem{(int)i, 1, first[i] + g};
       }
     }
+  }
+  const size_t it_valu = it;
+  const int mcls[2] = {std::max(mca, mcb), std::min(mca, mcb)};  // the more expensive first
+  size_t mfirst[3] = {it, it, it};
+  int msub[2] = {1, 1};
+  for (int part = 0; part < 2; ++part) {
+    mfirst[part] = it;
+    for (size_t i = 0; mcls[part] >= 0 && i < njobs; ++i)
+      if (on_mfma(i) && hj[i].geo == mcls[part]) {
+        msub[part] = std::max(msub[part], hj[i].group);
+        for (size_t g = 0; g < ngroups[i]; ++g)
+          hi[it++] = pc2k::BatchItem{(int)i, 0, first[i] + g};
+      }
+    mfirst[part + 1] = it;
   }
   hipStream_t st = (hipStream_t)hip_stream;
   if (hipMemcpyAsync(db, hb, njobs * sizeof(pc2k::BatchJob), hipMemcpyHostToDevice, st) !=
@@ -1681,12 +1799,30 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
       hipEventRecord(r->copied, st) != hipSuccess)
     return PC2_E_DEVICE;
   r->pending = true;
-  const int grid = (int)std::max<size_t>(1, std::min<size_t>(r->grid_cap, it));
-  const int w_a = window_for(ctx, pa, op), w_b = window_for(ctx, pb, op);
   int* queue = (int*)(db + r->jobs_b + r->items_b + r->ptr_b);
-  return status_of(pc2k::launch_batch(op, pair, grid, (const pc2k::BatchJob*)db,
-                                      (const pc2k::BatchItem*)(db + r->jobs_b), (int)it, queue,
-                                      r->scratch, r->slot_words, w_a, w_b, ctx->err, st));
+  const auto* ditems = (const pc2k::BatchItem*)(db + r->jobs_b);
+  hipError_t e = hipSuccess;
+  if (it_valu) {
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>(r->grid_cap, it_valu));
+    const int w_a = window_for(ctx, pa, op), w_b = window_for(ctx, pb, op);
+    e = pc2k::launch_batch(op, pair, grid, (const pc2k::BatchJob*)db, ditems, (int)it_valu,
+                           queue, r->scratch, r->slot_words, w_a, w_b, ctx->err, st);
+  }
+  for (int part = 0; part < 2 && e == hipSuccess; ++part) {
+    const size_t n = mfirst[part + 1] - mfirst[part];
+    if (!n) continue;
+    const int c = mcls[part];
+    const int w = window_for(ctx, c, pc2k::OP_ENC_MFMA);
+    const size_t per = pc2k::mfma_digit_bytes(c) << w;
+    if (!r->mscratch || per > r->mscratch_bytes) return PC2_E_NOMEM;
+    const size_t cap = (size_t)ctx->cus * std::max(1, r->mocc[c]);
+    const int grid = (int)std::max<size_t>(
+        1, std::min<size_t>({cap, n * msub[part], r->mscratch_bytes / per}));
+    e = pc2k::launch_batch_mfma(c, grid, (const pc2k::BatchJob*)db, ditems + mfirst[part],
+                                (int)n, msub[part], queue + 32 * (part + 1), r->mscratch, w,
+                                ctx->err, st);
+  }
+  return status_of(e);
 }
 
 int pc2_runner_destroy(pc2_runner* r) {
@@ -1696,6 +1832,7 @@ int pc2_runner_destroy(pc2_runner* r) {
   if (r->dev) (void)hipFree(r->dev);
   if (r->host) (void)hipHostFree(r->host);
   if (r->scratch) (void)hipFree(r->scratch);
+  if (r->mscratch) (void)hipFree(r->mscratch);
   if (r->stage) (void)hipFree(r->stage);
   if (r->copied) (void)hipEventDestroy(r->copied);
   delete r;

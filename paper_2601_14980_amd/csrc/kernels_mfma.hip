@@ -168,6 +168,48 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_enc_acc_mfma(
   }
 }
 
+__global__ void k_mfma_queue_reset(int* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+}
+
+// Persistent batch encryption (the matrix-core form of the batch kernel's
+// encryption phase): each workgroup pulls one element at a time from the
+// queue (one atomic each: queue position q is element q % sub of item
+// q / sub, sub >= every job's group), so that the launch ends within one
+// element's time of its last wavefront; it exits when the queue is drained,
+// so every wavefront reaches the exit.
+template <int S>
+__global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_batch_mfma(
+    const pc2k::BatchJob* __restrict__ jobs, const pc2k::BatchItem* __restrict__ items,
+    int nitems, int sub, int* queue, uint8_t* __restrict__ scratch, int w, int* err) {
+  using G = pc2m::MGeo<S>;
+  __shared__ __align__(16) pc2m::MWork<G> ws;
+  __shared__ int s_q;
+  const int lane = threadIdx.x;
+  uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::FB << w);
+  pc2m::init_work<G>(ws, lane);
+  pc2m::init_table<G>(table, (1 << (w - 1)) + 1, lane);
+  int32_t U[G::NT];
+  const long long total = (long long)nitems * sub;
+  for (;;) {
+    if (lane == 0) s_q = atomicAdd(queue, 1);
+    pc2m::wave_sync();
+    const long long q = s_q;
+    pc2m::wave_sync();
+    if (q >= total) break;
+    const pc2k::BatchItem item = items[q / sub];
+    const pc2k::BatchJob& job = jobs[item.job];
+    const int k = (int)(q % sub);
+    const size_t e = item.group * (size_t)job.group + k;
+    if (k >= job.group || e >= job.count) continue;
+    const int L = job.pk.L;
+    const uint32_t ok = encrypt_element<G>(ws, job.pk, job.in0 + e * job.m_limbs, job.m_limbs,
+                                           job.in1 + e * L, table, w, lane, U);
+    store_canonical<G>(ws, job.pk.mf, U, lane, job.out + e * 2 * (size_t)L, 2 * L, ok);
+    if (lane == 0 && !ok) atomicOr(err, pc2k::ERR_RANGE);
+  }
+}
+
 template <int C>
 const void* mfma_kernel(bool fused) {
   return fused ? (const void*)&k_enc_acc_mfma<pc2k::MFMA_S[C]>
@@ -191,6 +233,35 @@ const void* kernel_encrypt_mfma(int cls, bool fused) {
     case 8: return mfma_kernel<8>(fused);
   }
   return nullptr;
+}
+
+const void* batch_mfma_kernel(int cls) {
+  switch (cls) {
+    case 0: return (const void*)&k_batch_mfma<MFMA_S[0]>;
+    case 1: return (const void*)&k_batch_mfma<MFMA_S[1]>;
+    case 2: return (const void*)&k_batch_mfma<MFMA_S[2]>;
+    case 3: return (const void*)&k_batch_mfma<MFMA_S[3]>;
+    case 4: return (const void*)&k_batch_mfma<MFMA_S[4]>;
+    case 5: return (const void*)&k_batch_mfma<MFMA_S[5]>;
+    case 6: return (const void*)&k_batch_mfma<MFMA_S[6]>;
+    case 7: return (const void*)&k_batch_mfma<MFMA_S[7]>;
+    case 8: return (const void*)&k_batch_mfma<MFMA_S[8]>;
+  }
+  return nullptr;
+}
+
+hipError_t launch_batch_mfma(int cls, int grid, const BatchJob* jobs, const BatchItem* items,
+                             int nitems, int sub, int* queue, uint8_t* scratch, int w, int* err,
+                             void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_mfma_queue_reset, dim3(1), dim3(64), 0, st, queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const void* k = batch_mfma_kernel(cls);
+  if (!k) return hipErrorInvalidValue;
+  void* args[] = {(void*)&jobs,    (void*)&items, (void*)&nitems, (void*)&sub,
+                  (void*)&queue,   (void*)&scratch, (void*)&w, (void*)&err};
+  return hipLaunchKernel(k, dim3(grid), dim3(64), args, 0, st);
 }
 
 size_t mfma_digit_bytes(int cls) {  // a forward digit array, with its zero pads

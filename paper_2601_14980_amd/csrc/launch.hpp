@@ -52,6 +52,14 @@ const void* kernel_encrypt_mfma(int cls, bool fused = false);
 size_t mfma_digit_bytes(int cls);
 hipError_t launch_encrypt_mfma(int cls, const Launch& l, const PkConst& pk, const uint32_t* m,
                                int m_limbs, const uint32_t* r, uint32_t* c, size_t count);
+// persistent batch encryption over the matrix cores for jobs of key class
+// cls: queue reset, then grid workgroups (one wavefront each) pulling single
+// elements of the items (job.group elements of one job; sub >= every
+// job.group); scratch: grid tables of 2^w forward digit arrays
+const void* batch_mfma_kernel(int cls);
+hipError_t launch_batch_mfma(int cls, int grid, const BatchJob* jobs, const BatchItem* items,
+                             int nitems, int sub, int* queue, uint8_t* scratch, int w, int* err,
+                             void* stream);
 // launch_enc_prod over the matrix cores; acc: mfma_digit_bytes(cls) bytes
 // (16-byte aligned) per element
 hipError_t launch_enc_prod_mfma(int cls, const Launch& l, const PkConst& pk, const PtrList& ms,

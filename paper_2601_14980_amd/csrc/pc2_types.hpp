@@ -91,6 +91,7 @@ struct PtrList {
 // run the same operation; their key classes (or tiles) may differ.
 struct BatchJob {
   int geo, op, m_limbs, K;        // geo: geometry id of the job's key (CLASS_GEO)
+  int group;                      // elements per work item
   PkConst pk;                     // encrypt, hom_sum
   SkConst sk;                     // decrypt
   const uint32_t* in0;            // encrypt: m; decrypt: c

@@ -213,3 +213,51 @@ def test_autotune_keeps_results(gpu_ctx, setup):
     got = ints_from_limbs(pc2.from_device_limbs(out))
     for j in _sample(len(nd["ms"])):
         assert got[j] == O.encrypt(k["opk"], nd["ms"][j], nd["rs"][j])
+
+
+@pytest.mark.parametrize("engine", ["valu", "mfma", "auto"])
+def test_batch_encrypt_engines(gpu_ctx, setup, engine):
+    """Encryption batches under each Montgomery engine setting: the VALU
+    kernel alone, the matrix cores for both key classes (two matrix-core
+    launches) and the automatic choice (the VALU kernel for the 1024-bit
+    jobs, the matrix cores for the 2048-bit ones).  Eager on the null
+    stream and graph-captured on a side stream (replayed twice), every run
+    equal to the VALU one-call results."""
+    from paper_2601_14980_amd import pc2
+    nodes = setup["nodes"]
+    gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_VALU)
+    refs = []
+    for nd in nodes:
+        ref = torch.zeros_like(nd["c"])
+        pc2.pc2_encrypt(nd["key"]["sk"].public, nd["m"], nd["r"], ref)
+        refs.append(ref)
+    assert gpu_ctx.sync() == 0
+    gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, {"valu": pc2.PC2_MODMUL_VALU,
+                                            "mfma": pc2.PC2_MODMUL_MFMA,
+                                            "auto": pc2.PC2_MODMUL_AUTO}[engine])
+    try:
+        jobs = [dict(op=pc2.PC2_OP_ENCRYPT, pk=nd["key"]["sk"].public, m=nd["m"], r=nd["r"],
+                     out=nd["c"]) for nd in nodes]
+        b = pc2.Batch(gpu_ctx, jobs)
+        side = torch.cuda.Stream()
+        for rep in range(3):
+            for nd in nodes:
+                nd["c"].zero_()
+            torch.cuda.synchronize()
+            if rep == 0:
+                b.run(0)
+                assert gpu_ctx.sync() == 0
+            else:
+                with torch.cuda.stream(side):
+                    b.run()
+                side.synchronize()
+                assert gpu_ctx.sync(side) == 0
+            for nd, ref in zip(nodes, refs):
+                assert torch.equal(nd["c"], ref), f"{engine}, run {rep}"
+        b.close()
+    finally:
+        gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
+    k = nodes[1]["key"]
+    got = ints_from_limbs(pc2.from_device_limbs(nodes[1]["c"]))
+    for j in _sample(len(nodes[1]["ms"])):
+        assert got[j] == O.encrypt(k["opk"], nodes[1]["ms"][j], nodes[1]["rs"][j])

@@ -97,8 +97,21 @@ def _check_alone(pc2, gpu_ctx, ks, req):
         assert vals[j] == ks["pool_m"][req.result["idx"]][j]
 
 
-def test_mixed_requests_equal_alone(gpu_ctx, keyset):
+@pytest.mark.parametrize("engine", ["auto", "mfma"])
+def test_mixed_requests_equal_alone(gpu_ctx, keyset, engine):
+    """A mixed trace through the request server equals every request run
+    alone; with the matrix-core engine the server's encryption launches run
+    on the matrix cores (and the alone runs too)."""
     from paper_2601_14980_amd import pc2
+    gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_MFMA if engine == "mfma"
+                       else pc2.PC2_MODMUL_AUTO)
+    try:
+        _mixed_equal_alone(pc2, gpu_ctx, keyset)
+    finally:
+        gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
+
+
+def _mixed_equal_alone(pc2, gpu_ctx, keyset):
     from paper_2601_14980_amd.serve import percentile, serve_trace
     reqs = _requests(pc2, keyset, 18, 9, 4000.0)
     budget = 2 << 20                    # holds a few requests at a time

@@ -105,13 +105,16 @@ int pc2_ctx_reserve(pc2_ctx *ctx, uint32_t max_nbits);
  * modular exponentiations (sliding windows over the key's exponents n,
  * p - 1, q - 1; fixed windows over per-element exponents).
  * PC2_OPT_MODMUL: limb-product engine for the Montgomery products of
- * pc2_encrypt: PC2_MODMUL_VALU (27/28-bit digits, one v_mad_u64_u32 per limb
- * product), PC2_MODMUL_MFMA (7-bit digits, the three limb-product matrices
- * of each product on the i8 matrix cores with int32 accumulation, carries
- * resolved on the vector ALUs) or PC2_MODMUL_AUTO (the default: the MFMA
- * engine for keys of more than 2048 bits, where it is the faster one on the
- * MI355X, the VALU engine otherwise).  All give identical results; the other
- * operations always use the VALU engine.
+ * public-key encryption (pc2_encrypt, pc2_enc_sum_dec, and the encryption
+ * jobs of batches and runners): PC2_MODMUL_VALU (27/28-bit digits, one
+ * v_mad_u64_u32 per limb product), PC2_MODMUL_MFMA (7-bit digits in signed
+ * redundant 28-bit limbs, the three limb-product matrices of each product on
+ * the i8 matrix cores with int32 accumulation, one carry split per column on
+ * the vector ALUs) or PC2_MODMUL_AUTO (the default: the MFMA engine for
+ * keys of 2048 bits and more, where it is the faster one on the MI355X, the
+ * VALU engine otherwise).  All give identical results; the other operations
+ * always use the VALU engine.  A batch or runner launch holds encryption
+ * jobs of at most two key classes per engine.
  * PC2_OPT_TILE: the limb tile of the VALU encryption kernels (pc2_encrypt,
  * batches and runners of encryptions), i.e. how many lanes of a wavefront
  * share one ciphertext.  1024-bit keys run with 2 (own) or 4 lanes,
@@ -336,10 +339,13 @@ int pc2_colsplit_destroy(pc2_colsplit *cs);
  * the data calls; any other overlap is PC2_E_INVAL.)  A batch runs one phase
  * of many edge nodes' work --
  * all their encryptions, all their aggregations or all their decryptions --
- * in ONE persistent launch, whatever the vector lengths, under keys of up to
- * two size classes (supported mixes: one class of 256, 1024, 2048, 3072 or
- * 4096 bits, or 1024 with 2048 bits).  Results are identical to the one-call-per-
- * job entry points above. */
+ * in ONE persistent launch per Montgomery engine, whatever the vector
+ * lengths, under keys of up to two size classes per engine (supported mixes
+ * for the VALU engine: one class of 256, 1024, 2048, 3072 or 4096 bits, or
+ * 1024 with 2048 bits; encryption jobs whose class runs on the matrix cores
+ * (PC2_OPT_MODMUL) go to a launch of their own per class, after the VALU
+ * launch, with single elements as work items).  Results are identical to
+ * the one-call-per-job entry points above. */
 enum { PC2_OP_ENCRYPT = 1, PC2_OP_HOM_SUM = 2, PC2_OP_DECRYPT = 3 };
 typedef struct {
   int op;                        /* PC2_OP_*; every job of a batch has the same op */

@@ -1709,6 +1709,10 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
   }
   if (nitems == 0) return PC2_OK;
   if (nitems > r->max_groups || nptrs > r->max_ptrs) return PC2_E_BUSY;
+  for (int c : {mca, mcb})  // (the scratch covers every class up to max_cls)
+    if (c >= 0 && (!r->mscratch || (pc2k::mfma_digit_bytes(c)
+                                    << window_for(ctx, c, pc2k::OP_ENC_MFMA)) > r->mscratch_bytes))
+      return PC2_E_NOMEM;
   int pair = -1;
   if (ca >= 0) {
     if (cb < 0) cb = ca;
@@ -1814,7 +1818,6 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     const int c = mcls[part];
     const int w = window_for(ctx, c, pc2k::OP_ENC_MFMA);
     const size_t per = pc2k::mfma_digit_bytes(c) << w;
-    if (!r->mscratch || per > r->mscratch_bytes) return PC2_E_NOMEM;
     const size_t cap = (size_t)ctx->cus * std::max(1, r->mocc[c]);
     const int grid = (int)std::max<size_t>(
         1, std::min<size_t>({cap, n * msub[part], r->mscratch_bytes / per}));

@@ -22,8 +22,11 @@ namespace {
 using pc2k::PkConst;
 
 // One element's c = r^n g^m (mod n^2) as the limbs U of the last product
-// (also in ws.xr).  The workgroup's table holds the odd powers and, after
-// them, the square sq.  Returns the input checks (m < n, 0 < r < n).
+// (also in ws.xr).  The workgroup's table (2^w digit arrays, of which the
+// powering uses 2^(w-1) + 1) holds the odd powers, after them the square
+// sq, and after that g^m (read once, at the end, so global memory serves;
+// it leaves the LDS to the operands read at every product).  Returns the
+// input checks (m < n, 0 < r < n).
 template <class G>
 __device__ __forceinline__ uint32_t encrypt_element(pc2m::MWork<G>& ws, const PkConst& pk,
                                                     const uint32_t* me, int m_limbs,
@@ -33,12 +36,13 @@ __device__ __forceinline__ uint32_t encrypt_element(pc2m::MWork<G>& ws, const Pk
   const pc2m::MConst& K = pk.mf;
   const int half = 1 << (w - 1);                  // odd powers in the table
   uint8_t* sq = table + (size_t)half * G::FB;     // (r R)^2 R^-1
+  uint8_t* gm = sq + G::FB;                        // g^m
   const uint32_t* sched = pk.nsch.p[w - pc2k::SCHED_WMIN];
   const int nsched = pk.nsch.n[w - pc2k::SCHED_WMIN];
   if (lane == 0) s_ok = pc2ops::encrypt_inputs_ok(pk, me, m_limbs, re);
   // g^m = MM(m, n R) + 1 = 1 + m n (mod n^2)
   pc2m::load_x<G>(ws, me, m_limbs, lane);
-  pc2m::mont_mul<G>(ws, K, K.nR, lane, false, ws.gm, true, U);
+  pc2m::mont_mul<G>(ws, K, K.nR, lane, false, gm, true, U);
   // table entry j = (r R)^(2j+1) R^-2j: entry 0 = r R, the square, then
   // one product by the square per entry
   pc2m::load_x<G>(ws, re, pk.L, lane);
@@ -59,7 +63,7 @@ __device__ __forceinline__ uint32_t encrypt_element(pc2m::MWork<G>& ws, const Pk
                         U);
   }
   // r^n g^m = MM(r^n R, g^m), |.| < 0.52 n^2
-  pc2m::mont_mul<G>(ws, K, ws.gm, lane, false, nullptr, false, U);
+  pc2m::mont_mul<G>(ws, K, gm, lane, false, nullptr, false, U);
   return s_ok;
 }
 
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_encrypt_mfma(
   uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::FB << w);
   const int L = pk.L;
   pc2m::init_work<G>(ws, lane);
-  pc2m::init_table<G>(table, (1 << (w - 1)) + 1, lane);
+  pc2m::init_table<G>(table, (1 << (w - 1)) + 2, lane);
   int32_t U[G::NT];
   for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
     const uint32_t ok =
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_enc_acc_mfma(
   const int L = pk.L;
   const bool last = step + 1 == Kn;
   pc2m::init_work<G>(ws, lane);
-  pc2m::init_table<G>(table, (1 << (w - 1)) + 1, lane);
+  pc2m::init_table<G>(table, (1 << (w - 1)) + 2, lane);
   int32_t U[G::NT];
   for (size_t e = blockIdx.x; e < count; e += gridDim.x) {
     uint8_t* acc_e = acc + e * (size_t)G::FB;
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(64, S <= 160 ? 3 : 2) void k_batch_mfma(
   const int lane = threadIdx.x;
   uint8_t* table = scratch + (size_t)blockIdx.x * ((size_t)G::FB << w);
   pc2m::init_work<G>(ws, lane);
-  pc2m::init_table<G>(table, (1 << (w - 1)) + 1, lane);
+  pc2m::init_table<G>(table, (1 << (w - 1)) + 2, lane);
   int32_t U[G::NT];
   const long long total = (long long)nitems * sub;
   for (;;) {

@@ -83,7 +83,6 @@ struct MWork {
   uint8_t tr[G::RBT];    // T mod R, the same
   uint8_t qr[G::RBT];    // q, the same
   uint8_t xf[G::FB];     // x, forward (B operand of a squaring)
-  uint8_t gm[G::FB];     // a per-element multiplier, forward
 };
 
 using MConst = pc2k::MfmaConst;
@@ -379,8 +378,8 @@ __device__ __forceinline__ void load_fwd(MWork<G>& ws, const uint8_t* y, int lan
 template <class G>
 __device__ __forceinline__ void init_work(MWork<G>& ws, int lane) {
   uint32_t* z = reinterpret_cast<uint32_t*>(ws.xr);
-  constexpr int ZW = (3 * G::RBT + 2 * G::FB) / 4;
-  static_assert(sizeof(MWork<G>) == 3 * G::RBT + 2 * G::FB, "no padding between the arrays");
+  constexpr int ZW = (3 * G::RBT + G::FB) / 4;
+  static_assert(sizeof(MWork<G>) == 3 * G::RBT + G::FB, "no padding between the arrays");
   for (int i = lane; i < ZW; i += 64) z[i] = 0u;
   wave_sync();
 }

@@ -1,9 +1,8 @@
 // Montgomery multiplication on the i8 matrix cores (MFMA) of gfx950.
 //
-// A residue x mod N (R = 2^(28 S) > 4N) is held as S limbs of 28 bits or,
-// for the matrix products, as D = 4S digits of 7 bits (one byte each, so
-// the signed i8 operands are never negative).  One wavefront works on one
-// element.  The three limb-product matrices of a separated Montgomery
+// A residue x mod N (R = 2^(28 S) >= 2^12 N at every key size) is held as S
+// limbs of 28 bits or, for the matrix products, as D = 4S digits, one signed
+// byte each (below).  One wavefront works on one element.  The three limb-product matrices of a separated Montgomery
 // product
 //
 //     T = x y,    q = (T mod R) N' mod R  (N' = -N^-1 mod R),    U = (T + q N) / R
@@ -24,7 +23,7 @@
 // carries of a product are never resolved: one balanced split per column
 // (keep the low 28 bits less 2^27, hand the rest to the next limb) bounds
 // every limb again, and every output stays below 0.52 N in magnitude, since
-// |U| <= |x y| / R + |q| N / R with |q| < 0.51 R and N/R < 2^-20.  The carry
+// |U| <= |x y| / R + |q| N / R with |q| < 0.51 R and N/R <= 2^-12.  The carry
 // out of the top limb of U is zero by the same bound; the caller makes the
 // final result canonical once.
 //

@@ -116,16 +116,23 @@ struct BatchItem {
 };
 
 // Limbs (28-bit) of R for the matrix-core product per key class:
-// 28 S >= 2 * (class limit) + 2, so R > 4 n^2.
+// 28 S >= 2 * (class limit) + 12, so R >= 2^12 n^2 (the margin the signed
+// redundant limbs' bounds need; mfma_mont.hpp).
 constexpr int MFMA_S[9] = {3, 5, 10, 19, 37, 74, 147, 220, 293};
+constexpr int CLASS_LIMIT_BITS[9] = {32, 64, 128, 256, 512, 1024, 2048, 3072, 4096};
+constexpr bool mfma_margins_ok() {
+  for (int c = 0; c < 9; ++c)
+    if (28 * MFMA_S[c] < 2 * CLASS_LIMIT_BITS[c] + 12) return false;
+  return true;
+}
+static_assert(mfma_margins_ok(), "R >= 2^12 n^2 in every key class");
 
 // Key size classes: index by ceil(log2) of the key.  n^2 and s^2 use
 // separate digit geometries (see mont_tile.hpp).
 constexpr int NUM_CLASSES = 9;
 inline int class_for_bits(int nbits) {
-  const int lim[NUM_CLASSES] = {32, 64, 128, 256, 512, 1024, 2048, 3072, 4096};
   for (int i = 0; i < NUM_CLASSES; ++i)
-    if (nbits <= lim[i]) return i;
+    if (nbits <= CLASS_LIMIT_BITS[i]) return i;
   return -1;
 }
 

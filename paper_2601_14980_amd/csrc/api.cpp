@@ -1212,6 +1212,11 @@ int pc2_enc_sum_dec(const pc2_sk* sk, const uint32_t* const* m_k, const uint32_t
 }
 
 // ---------------------------------------------------------------- batches
+// Work-queue counters at the end of a batch's or runner's descriptor
+// allocation: the VALU launch's, then one per matrix-core class, each on
+// its own 128-byte line.
+constexpr int QUEUE_STRIDE = 32;                 // ints between two counters
+constexpr size_t QUEUE_BYTES = 3 * QUEUE_STRIDE * sizeof(int);
 // resident workgroups per CU of a 64-lane kernel (1 if the runtime cannot tell)
 int occupancy_of(const void* k) {
   int occ = 0;
@@ -1356,7 +1361,7 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
   const size_t jobs_b = (dj.size() * sizeof(pc2k::BatchJob) + 255) & ~(size_t)255;
   const size_t items_b = (items.size() * sizeof(pc2k::BatchItem) + 255) & ~(size_t)255;
   const size_t ptr_b = (ptrbuf.size() * sizeof(size_t) + 255) & ~(size_t)255;
-  const size_t total = jobs_b + items_b + ptr_b + 256;
+  const size_t total = jobs_b + items_b + ptr_b + QUEUE_BYTES;
   int rc = PC2_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) rc = PC2_E_DEVICE;
   if (!rc && hipMalloc(&b->dev, total) != hipSuccess) rc = PC2_E_NOMEM;
@@ -1375,7 +1380,7 @@ int pc2_batch_create(pc2_ctx* ctx, const pc2_job* jobs, size_t njobs, pc2_batch*
     b->queue = (int*)(base + jobs_b + items_b + ptr_b);
     for (int part = 0; part < 2; ++part) {
       b->mp[part].items = b->items + mfirst[part];
-      b->mp[part].queue = b->queue + 32 * (part + 1);
+      b->mp[part].queue = b->queue + QUEUE_STRIDE * (part + 1);
     }
     for (size_t ji = 0; ji < dj.size(); ++ji)
       if (op == pc2k::OP_SUM) {
@@ -1595,7 +1600,7 @@ int pc2_runner_create(pc2_ctx* ctx, int op_abi, uint32_t max_nbits, size_t max_j
   const size_t max_items = (op == pc2k::OP_DEC ? 2 : 1) * max_groups;
   r->items_b = (max_items * sizeof(pc2k::BatchItem) + 255) & ~(size_t)255;
   r->ptr_b = (r->max_ptrs * sizeof(size_t) + 255) & ~(size_t)255;
-  const size_t total = r->jobs_b + r->items_b + r->ptr_b + 256;
+  const size_t total = r->jobs_b + r->items_b + r->ptr_b + QUEUE_BYTES;
   int rc = PC2_OK;
   if (hipMalloc(&r->dev, total) != hipSuccess || hipHostMalloc(&r->host, total) != hipSuccess ||
       hipEventCreateWithFlags(&r->copied, hipEventDisableTiming) != hipSuccess)
@@ -1822,7 +1827,8 @@ int pc2_runner_launch(pc2_runner* r, const pc2_job* jobs, const size_t* first,
     const int grid = (int)std::max<size_t>(
         1, std::min<size_t>({cap, n * msub[part], r->mscratch_bytes / per}));
     e = pc2k::launch_batch_mfma(c, grid, (const pc2k::BatchJob*)db, ditems + mfirst[part],
-                                (int)n, msub[part], queue + 32 * (part + 1), r->mscratch, w,
+                                (int)n, msub[part], queue + QUEUE_STRIDE * (part + 1),
+                                r->mscratch, w,
                                 ctx->err, st);
   }
   return status_of(e);

@@ -164,3 +164,32 @@ def test_mfma_workgroups_loop_over_elements(valu_ctx, mfma_ctx, nbits):
         cj = sum(int(w) << (32 * k) for k, w in enumerate(cm[j]))
         rj = sum(int(w) << (32 * k) for k, w in enumerate(rh[j]))
         assert cj == O.encrypt(opk, int(mh[j, 0]), rj), f"element {j}"
+
+
+@pytest.mark.parametrize("nbits", [256, 2048])
+def test_mfma_every_window(valu_ctx, mfma_ctx, nbits):
+    """Every window width the option allows (2..6): the matrix-core kernel's
+    table holds 2^(w-1) odd powers, the square and g^m in its 2^w entries,
+    so w = 2 fills it exactly.  Ciphertexts equal the VALU engine's and the
+    oracle's."""
+    from paper_2601_14980_amd import pc2
+    p, q = gen.primes_for(3, nbits, extra=13)
+    n = p * q
+    sk, opk, _ = _key(mfma_ctx, p, q, nbits)
+    sk_v = pc2.SecretKey(valu_ctx, nbits, p, q)
+    rng = random.Random(nbits + 7)
+    count = 70
+    ms = [n - 1, 0] + [rng.randrange(n) for _ in range(count - 2)]
+    rs = [n - 1, 1] + gen.gen_r(n, count - 2, 1, extra=nbits + 7)
+    cv, st = gpu_encrypt(valu_ctx, sk_v.public, ms, rs)
+    assert st == 0
+    try:
+        for w in (2, 3, 4, 5, 6):
+            mfma_ctx.set_option(pc2.PC2_OPT_WINDOW, w)
+            cs, st = gpu_encrypt(mfma_ctx, sk.public, ms, rs)
+            assert st == 0
+            assert cs == cv, f"window {w}"
+    finally:
+        mfma_ctx.set_option(pc2.PC2_OPT_WINDOW, 0)
+    for j in (0, 1, count - 1):
+        assert cv[j] == O.encrypt(opk, ms[j], rs[j])

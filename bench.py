@@ -879,8 +879,9 @@ def run_admm(pc2, gen, ctx, torch, np, args, engines) -> dict:
         "mse_z_vs_xstar_quantized": float(np.mean((zq - xstar) ** 2)),
         "mse_z_vs_xstar_float64": float(np.mean((zf - xstar) ** 2)),
         "nnz_z": int(np.count_nonzero(zq)),
-        "quantized_loop_equals_encrypted": bool(snap is not None and "valu" in final
-                                                and np.array_equal(snap, final["valu"])),
+        "quantized_loop_equals_encrypted": bool(snap is not None and len(final) > 0
+                                                and all(np.array_equal(snap, v)
+                                                        for v in final.values())),
     }
     log(f"admm long run ({T} iterations): MSE quantized vs float64 "
         f"{out['long_run']['mse_quantized_vs_float64']:.3e}, vs x* "

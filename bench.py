@@ -1154,7 +1154,12 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        # encryption (most of a step) multiplies 7-bit digits as i8 on the
+        # matrix cores with i32 accumulation, or 32-bit limbs on the VALU;
+        # decryption always runs on 32-bit limbs
+        "dtype": "i8" if main_engine == "mfma" else "u32",
+        "dtypes": {"encrypt": "i8 x i8 -> i32" if main_engine == "mfma" else "u32 x u32 -> u64",
+                   "decrypt": "u32 x u32 -> u64"},
         "data": "synthetic",
         "config": {"workload": "2048-bit key, 8 nodes x 65536 float64 ~ N(0,1), scale 2^20, "
                                "offset 2^23: quantize, encrypt 524288, 8-way sum, decrypt 65536, "

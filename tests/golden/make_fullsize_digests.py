@@ -1,0 +1,125 @@
+"""Write `fullsize_<config>.json` beside this file: SHA-256 digests of the
+oracle's Paillier ciphertexts (encryption with g = n + 1, Section III-B)
+for a regular sample of a full-size workload (the quantized N(0,1) vectors
+and the r values of the seeded generators), in chunks of 4096 sampled
+elements:
+
+* 2048bit_8x65536 (default): every eighth element of 8 nodes x 65536 under
+  the 2048-bit key of seed 2;
+* 3072bit_32x16384: every 32nd element of 32 nodes x 16384 (one lasso
+  iteration's encryptions) under the 3072-bit key of seed 4.
+
+Only `oracle/` computes (quantize, encrypt); `workload/` supplies the seeded
+inputs.  The GPU test in `tests/test_gpu_fullsize.py` encrypts the whole
+workload in one launch and compares the digests of the same elements, so
+every sampled ciphertext is checked bit for bit, at every position of the
+launch.
+
+    python tests/golden/make_fullsize_digests.py [--config NAME] [--workers N]
+
+takes about 20 minutes per configuration on 8 cores (one oracle encryption,
+pure-Python square-and-multiply, is ~0.15 s at 2048 bits and ~0.5 s at 3072).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import sys
+import time
+from pathlib import Path
+
+HERE = Path(__file__).resolve().parent
+ROOT = HERE.parent.parent
+sys.path.insert(0, str(ROOT))
+
+from oracle import paillier as O  # noqa: E402
+from oracle import quant as Q  # noqa: E402
+from workload import gen  # noqa: E402
+from workload.limbs import ints_from_limbs  # noqa: E402
+
+CONFIGS = {  # name: (key bits, nodes, length, key seed, sample stride)
+    "2048bit_8x65536": (2048, 8, 65536, 2, 8),
+    "3072bit_32x16384": (3072, 32, 16384, 4, 32),
+}
+DEFAULT = "2048bit_8x65536"
+CHUNK = 4096
+
+_opk = None
+_nb = 0
+
+
+def _init(p: int, q: int, nb: int) -> None:
+    global _opk, _nb
+    _opk, _ = O.derive_keys(p, q)
+    _nb = nb
+
+
+def _encrypt_chunk(pairs: list[tuple[int, int]]) -> bytes:
+    return b"".join(O.encrypt(_opk, m, r).to_bytes(_nb, "little") for m, r in pairs)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--config", choices=sorted(CONFIGS), default=DEFAULT)
+    ap.add_argument("--workers", type=int, default=mp.cpu_count())
+    args = ap.parse_args()
+    NBITS, NODES, LENGTH, SEED, STRIDE = CONFIGS[args.config]
+    out = HERE / f"fullsize_{args.config}.json"
+    nb = 2 * NBITS // 8
+    t0 = time.time()
+    p, q = gen.primes_for(SEED, NBITS)
+    n = p * q
+    nl = NBITS // 32
+    qp = gen.Q_PLAIN
+    xs = gen.normal_vectors(SEED, [LENGTH] * NODES)
+    elems = list(range(0, NODES * LENGTH, STRIDE))
+    pairs = []
+    for k in range(NODES):
+        rk = ints_from_limbs(gen.gen_r_limbs(n, LENGTH, nl, SEED, extra=k))
+        for j in range(0, LENGTH, STRIDE):
+            assert (k * LENGTH + j) % STRIDE == 0
+            m = Q.quantize(float(xs[k][j]), qp.log2_scale, qp.offset, qp.delta)
+            pairs.append((m, int(rk[j])))
+    assert len(pairs) == len(elems) and len(pairs) % CHUNK == 0
+    chunks = [pairs[i:i + CHUNK] for i in range(0, len(pairs), CHUNK)]
+    # the workers take sub-chunks so that progress shows and the load evens out
+    sub = 256
+    work = [c[i:i + sub] for c in chunks for i in range(0, len(c), sub)]
+    parts: list[bytes] = []
+    with mp.Pool(args.workers, initializer=_init, initargs=(p, q, nb)) as pool:
+        for i, b in enumerate(pool.imap(_encrypt_chunk, work)):
+            parts.append(b)
+            if (i + 1) % 16 == 0:
+                print(f"{(i + 1) * sub} / {len(pairs)} encryptions, {time.time() - t0:.0f} s",
+                      flush=True)
+    blob = b"".join(parts)
+    digests = [hashlib.sha256(blob[i * CHUNK * nb:(i + 1) * CHUNK * nb]).hexdigest()
+               for i in range(len(chunks))]
+    doc = {
+        "what": f"SHA-256 of the oracle's ciphertexts (little-endian, {nb} bytes each, in element "
+                f"order) of elements 0, {STRIDE}, {2 * STRIDE}, ... of the {NBITS}-bit {NODES} x "
+                f"{LENGTH} workload, in chunks of {CHUNK} sampled elements",
+        "definition": "Paillier encryption with g = n + 1 (Section III-B): "
+                      "c = g^m r^n mod n^2, m = the quantized value (Section III-A)",
+        "workload": {"nbits": NBITS, "nodes": NODES, "length": LENGTH, "key_seed": SEED,
+                     "x": f"gen.normal_vectors({SEED}, [{LENGTH}] * {NODES})",
+                     "r": f"gen.gen_r_limbs(n, {LENGTH}, {nl}, {SEED}, extra=node)",
+                     "quantizer": {"log2_scale": qp.log2_scale, "offset": qp.offset,
+                                   "delta": qp.delta}},
+        "stride": STRIDE,
+        "chunk": CHUNK,
+        "samples": len(pairs),
+        "digests": digests,
+        "written_by": "python tests/golden/make_fullsize_digests.py"
+                      + ("" if args.config == DEFAULT else f" --config {args.config}")
+                      + " (oracle/ only)",
+    }
+    out.write_text(json.dumps(doc, indent=1) + "\n")
+    print(f"wrote {out} ({len(digests)} digests) in {time.time() - t0:.0f} s", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

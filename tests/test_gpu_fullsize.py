@@ -1,6 +1,9 @@
 """The paper-sized workloads at full size, in the launch shapes bench.py times
 (GPU tests).  The oracle checks sampled elements one by one; every element is
-checked through the exact identity Dec(prod_k Enc(m_k)) = sum_k m_k.
+checked through the exact identity Dec(prod_k Enc(m_k)) = sum_k m_k; and
+every eighth ciphertext of the 2048-bit encryption launch (every 32nd at
+3072 bits) is compared with the oracle's through digests written from
+oracle/ alone.
 
 * 2048-bit key, 8 nodes x 65536 quantized N(0,1) values: one encryption
   launch of 524288, an 8-way aggregation, one decryption launch of 65536.
@@ -12,6 +15,10 @@ checked through the exact identity Dec(prod_k Enc(m_k)) = sum_k m_k.
   groups, 4 GiB budget) on requests of up to 65536 elements."""
 from __future__ import annotations
 
+import hashlib
+import json
+from pathlib import Path
+
 import numpy as np
 import pytest
 import torch
@@ -22,6 +29,8 @@ from workload import gen
 from workload.limbs import ints_from_limbs
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
 
 
 def _sums_exact(pc2, dec: torch.Tensor, mq: np.ndarray) -> bool:
@@ -203,3 +212,50 @@ def test_full_size_serving(gpu_ctx):
             assert O.decrypt(osk, got) == 6 * int(mh[j])   # (1 + 2 + 3) m_j
         else:
             assert got == 2 * int(mh[j])
+
+
+@pytest.mark.parametrize("engine", ["mfma", "valu"])
+@pytest.mark.parametrize("config", ["2048bit_8x65536"])
+def test_full_size_ciphertexts_match_the_oracle_digests(gpu_ctx, config, engine):
+    """Elements 0, 8, 16, ... of the 2048-bit 8 x 65536 encryption launch
+    (65536 ciphertexts), and 0, 32, 64, ... of the 3072-bit 32 x 16384 one
+    (16384), over every node and every position of the launch, with each
+    Montgomery engine, against the oracle's ciphertexts of the same seeded
+    inputs: SHA-256 per chunk of 4096, as tests/golden/make_fullsize_digests.py
+    wrote them from oracle/ alone."""
+    from paper_2601_14980_amd import pc2
+    doc = json.loads((GOLDEN / f"fullsize_{config}.json").read_text())
+    w = doc["workload"]
+    nbits, nodes, length, seed = w["nbits"], w["nodes"], w["length"], w["key_seed"]
+    stride, chunk = doc["stride"], doc["chunk"]
+    p, q = gen.primes_for(seed, nbits)
+    n = p * q
+    sk = pc2.SecretKey(gpu_ctx, nbits, p, q)
+    L = sk.L
+    qp = gen.Q_PLAIN
+    assert w["quantizer"] == {"log2_scale": qp.log2_scale, "offset": qp.offset,
+                              "delta": qp.delta}
+    xs = gen.normal_vectors(seed, [length] * nodes)
+    rs = np.concatenate([gen.gen_r_limbs(n, length, L, seed, extra=k) for k in range(nodes)])
+    total = nodes * length
+    m = torch.empty(total, dtype=torch.int64, device="cuda")
+    pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, qp.delta,
+                     torch.from_numpy(np.concatenate(xs)).cuda(), m)
+    c = torch.empty((total, 2 * L), dtype=torch.int32, device="cuda")
+    gpu_ctx.set_option(pc2.PC2_OPT_MODMUL,
+                       pc2.PC2_MODMUL_MFMA if engine == "mfma" else pc2.PC2_MODMUL_VALU)
+    try:
+        pc2.pc2_encrypt(sk.public, m.view(torch.int32).reshape(total, 2), pc2.to_device_limbs(rs),
+                        c)
+        assert gpu_ctx.sync() == 0
+    finally:
+        gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
+    rows = c[::stride].cpu().numpy().view(np.uint32)
+    assert rows.shape == (doc["samples"], 2 * L)
+    blob = rows.astype("<u4").tobytes()
+    nb = chunk * 2 * nbits // 8
+    got = [hashlib.sha256(blob[i * nb:(i + 1) * nb]).hexdigest()
+           for i in range(len(doc["digests"]))]
+    bad = [i for i, (g, e) in enumerate(zip(got, doc["digests"])) if g != e]
+    assert len(got) == len(doc["digests"]) and not bad, \
+        f"{config}, {engine}: chunks {bad} of {chunk} sampled elements differ from the oracle"

@@ -215,7 +215,7 @@ def test_full_size_serving(gpu_ctx):
 
 
 @pytest.mark.parametrize("engine", ["mfma", "valu"])
-@pytest.mark.parametrize("config", ["2048bit_8x65536"])
+@pytest.mark.parametrize("config", ["2048bit_8x65536", "3072bit_32x16384"])
 def test_full_size_ciphertexts_match_the_oracle_digests(gpu_ctx, config, engine):
     """Elements 0, 8, 16, ... of the 2048-bit 8 x 65536 encryption launch
     (65536 ciphertexts), and 0, 32, 64, ... of the 3072-bit 32 x 16384 one

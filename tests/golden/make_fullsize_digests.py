@@ -2,12 +2,17 @@
 oracle's Paillier ciphertexts (encryption with g = n + 1, Section III-B)
 for a regular sample of a full-size workload (the quantized N(0,1) vectors
 and the r values of the seeded generators), in chunks of 4096 sampled
-elements:
+elements, and of the element-wise products over the nodes of the sampled
+ciphertexts (Definition 1 applied nodes - 1 times; the sample holds every
+node's element at each sampled position, since the stride divides the
+vector length):
 
 * 2048bit_8x65536 (default): every eighth element of 8 nodes x 65536 under
   the 2048-bit key of seed 2;
 * 3072bit_32x16384: every 32nd element of 32 nodes x 16384 (one lasso
-  iteration's encryptions) under the 3072-bit key of seed 4.
+  iteration's encryptions) under the 3072-bit key of seed 4;
+* 4096bit_1x32768: every eighth element of one launch of 32768 under the
+  4096-bit key of seed 7.
 
 Only `oracle/` computes (quantize, encrypt); `workload/` supplies the seeded
 inputs.  The GPU test in `tests/test_gpu_fullsize.py` encrypts the whole
@@ -17,8 +22,9 @@ launch.
 
     python tests/golden/make_fullsize_digests.py [--config NAME] [--workers N]
 
-takes about 20 minutes per configuration on 8 cores (one oracle encryption,
-pure-Python square-and-multiply, is ~0.15 s at 2048 bits and ~0.5 s at 3072).
+takes 10-20 minutes per configuration on 8 cores (one oracle encryption,
+pure-Python square-and-multiply, is ~0.15 s at 2048 bits, ~0.5 s at 3072
+and ~1 s at 4096).
 """
 from __future__ import annotations
 
@@ -42,6 +48,7 @@ from workload.limbs import ints_from_limbs  # noqa: E402
 CONFIGS = {  # name: (key bits, nodes, length, key seed, sample stride)
     "2048bit_8x65536": (2048, 8, 65536, 2, 8),
     "3072bit_32x16384": (3072, 32, 16384, 4, 32),
+    "4096bit_1x32768": (4096, 1, 32768, 7, 8),
 }
 DEFAULT = "2048bit_8x65536"
 CHUNK = 4096
@@ -97,6 +104,16 @@ def main() -> int:
     blob = b"".join(parts)
     digests = [hashlib.sha256(blob[i * CHUNK * nb:(i + 1) * CHUNK * nb]).hexdigest()
                for i in range(len(chunks))]
+    # aggregates at the sampled positions j = 0, STRIDE, ... of a node's vector
+    opk, _ = O.derive_keys(p, q)
+    per_node = LENGTH // STRIDE
+    cts = [int.from_bytes(blob[i * nb:(i + 1) * nb], "little") for i in range(len(pairs))]
+    agg_digests, agg_chunk = [], min(CHUNK, per_node)
+    if NODES > 1:
+        agg = b"".join(O.hom_sum(opk, [cts[k * per_node + t] for k in range(NODES)])
+                       .to_bytes(nb, "little") for t in range(per_node))
+        agg_digests = [hashlib.sha256(agg[i * agg_chunk * nb:(i + 1) * agg_chunk * nb]).hexdigest()
+                       for i in range(per_node // agg_chunk)]
     doc = {
         "what": f"SHA-256 of the oracle's ciphertexts (little-endian, {nb} bytes each, in element "
                 f"order) of elements 0, {STRIDE}, {2 * STRIDE}, ... of the {NBITS}-bit {NODES} x "
@@ -112,6 +129,10 @@ def main() -> int:
         "chunk": CHUNK,
         "samples": len(pairs),
         "digests": digests,
+        "agg_what": f"SHA-256 of prod over the {NODES} nodes of the oracle's ciphertexts mod n^2 "
+                    f"at positions 0, {STRIDE}, ... of a node's vector, in chunks of {agg_chunk}",
+        "agg_chunk": agg_chunk,
+        "agg_digests": agg_digests,
         "written_by": "python tests/golden/make_fullsize_digests.py"
                       + ("" if args.config == DEFAULT else f" --config {args.config}")
                       + " (oracle/ only)",

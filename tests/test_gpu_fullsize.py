@@ -215,14 +215,16 @@ def test_full_size_serving(gpu_ctx):
 
 
 @pytest.mark.parametrize("engine", ["mfma", "valu"])
-@pytest.mark.parametrize("config", ["2048bit_8x65536", "3072bit_32x16384"])
+@pytest.mark.parametrize("config", ["2048bit_8x65536", "3072bit_32x16384", "4096bit_1x32768"])
 def test_full_size_ciphertexts_match_the_oracle_digests(gpu_ctx, config, engine):
     """Elements 0, 8, 16, ... of the 2048-bit 8 x 65536 encryption launch
-    (65536 ciphertexts), and 0, 32, 64, ... of the 3072-bit 32 x 16384 one
-    (16384), over every node and every position of the launch, with each
-    Montgomery engine, against the oracle's ciphertexts of the same seeded
-    inputs: SHA-256 per chunk of 4096, as tests/golden/make_fullsize_digests.py
-    wrote them from oracle/ alone."""
+    (65536 ciphertexts), 0, 32, 64, ... of the 3072-bit 32 x 16384 one
+    (16384) and 0, 8, 16, ... of a 4096-bit launch of 32768 (4096), over every
+    node and every position of the launch, with each Montgomery engine,
+    against the oracle's ciphertexts of the same seeded inputs: SHA-256 per
+    chunk of 4096, as tests/golden/make_fullsize_digests.py wrote them from
+    oracle/ alone; then the aggregates over the nodes at the sampled
+    positions against the oracle's products."""
     from paper_2601_14980_amd import pc2
     doc = json.loads((GOLDEN / f"fullsize_{config}.json").read_text())
     w = doc["workload"]
@@ -250,12 +252,26 @@ def test_full_size_ciphertexts_match_the_oracle_digests(gpu_ctx, config, engine)
         assert gpu_ctx.sync() == 0
     finally:
         gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
-    rows = c[::stride].cpu().numpy().view(np.uint32)
-    assert rows.shape == (doc["samples"], 2 * L)
-    blob = rows.astype("<u4").tobytes()
-    nb = chunk * 2 * nbits // 8
-    got = [hashlib.sha256(blob[i * nb:(i + 1) * nb]).hexdigest()
-           for i in range(len(doc["digests"]))]
-    bad = [i for i, (g, e) in enumerate(zip(got, doc["digests"])) if g != e]
-    assert len(got) == len(doc["digests"]) and not bad, \
+    bad = _digest_mismatches(c[::stride], doc["samples"], chunk, doc["digests"])
+    assert not bad, \
         f"{config}, {engine}: chunks {bad} of {chunk} sampled elements differ from the oracle"
+    if nodes > 1:
+        # the element-wise products over the nodes, at the sampled positions
+        agg = torch.empty((length, 2 * L), dtype=torch.int32, device="cuda")
+        pc2.pc2_hom_sum(sk.public, [c[k * length:(k + 1) * length] for k in range(nodes)], agg)
+        assert gpu_ctx.sync() == 0
+        bad = _digest_mismatches(agg[::stride], length // stride, doc["agg_chunk"],
+                                 doc["agg_digests"])
+        assert not bad, f"{config}, {engine}: aggregate chunks {bad} differ from the oracle"
+
+
+def _digest_mismatches(rows_dev: torch.Tensor, count: int, chunk: int,
+                       digests: list[str]) -> list[int]:
+    """SHA-256 per chunk of `chunk` rows (little-endian limbs) against the
+    stored digests; the indices of the chunks that differ."""
+    rows = rows_dev.cpu().numpy().view(np.uint32)
+    assert rows.shape[0] == count and count == chunk * len(digests)
+    blob = rows.astype("<u4").tobytes()
+    nb = chunk * rows.shape[1] * 4
+    return [i for i, e in enumerate(digests)
+            if hashlib.sha256(blob[i * nb:(i + 1) * nb]).hexdigest() != e]

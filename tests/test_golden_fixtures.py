@@ -45,6 +45,23 @@ def test_fixture_matches_its_configuration(name):
     assert doc["written_by"] == f"python tests/golden/make_fullsize_digests.py{flag} (oracle/ only)"
 
 
+def test_batch_fixture_matches_its_configuration():
+    path = GOLDEN / f"fullsize_{M.BATCH}.json"
+    assert path.exists(), f"{path.name}: run make_fullsize_digests.py --config {M.BATCH}"
+    doc = json.loads(path.read_text())
+    w = doc["workload"]
+    assert (w["seed"], w["nodes"], w["key_bits"]) == (M.B_SEED, M.B_NODES, list(M.B_KEY_BITS))
+    assert w["lengths"] == gen.log_uniform_lengths(M.B_SEED, M.B_NODES, M.B_LO, M.B_HI)
+    qp = gen.Q_PLAIN
+    assert w["quantizer"] == {"log2_scale": qp.log2_scale, "offset": qp.offset,
+                              "delta": qp.delta}
+    assert doc["stride"] == M.B_STRIDE
+    assert len(doc["node_digests"]) == M.B_NODES and len(doc["agg_digests"]) == len(M.B_KEY_BITS)
+    assert all(HEX.match(d) for d in doc["node_digests"] + doc["agg_digests"])
+    assert doc["written_by"] == (f"python tests/golden/make_fullsize_digests.py --config {M.BATCH} "
+                                 "(oracle/ only)")
+
+
 def test_no_fixture_without_a_configuration():
     names = {p.name[len("fullsize_"):-len(".json")] for p in GOLDEN.glob("fullsize_*.json")}
-    assert names == set(M.CONFIGS)
+    assert names == set(M.CONFIGS) | {M.BATCH}

@@ -275,3 +275,68 @@ def _digest_mismatches(rows_dev: torch.Tensor, count: int, chunk: int,
     nb = chunk * rows.shape[1] * 4
     return [i for i, e in enumerate(digests)
             if hashlib.sha256(blob[i * nb:(i + 1) * nb]).hexdigest() != e]
+
+
+@pytest.mark.parametrize("engine", ["mfma", "valu"])
+def test_full_size_batches_match_the_oracle_digests(gpu_ctx, engine):
+    """The batching workload (16 nodes of log-uniform lengths, 1024-bit key
+    on even nodes, 2048-bit on odd ones) through one persistent encryption
+    launch and one ragged aggregation launch, with the 2048-bit encryptions
+    on either engine: every eighth ciphertext of every node, and the ragged
+    products at the same positions, against the digests that
+    tests/golden/make_fullsize_digests.py wrote from oracle/ alone."""
+    from paper_2601_14980_amd import pc2
+    doc = json.loads((GOLDEN / "fullsize_batch_16nodes.json").read_text())
+    w, stride = doc["workload"], doc["stride"]
+    seed, lengths, key_bits = w["seed"], w["lengths"], w["key_bits"]
+    assert lengths == gen.log_uniform_lengths(seed, w["nodes"], 1024, 65536)
+    qp = gen.Q_PLAIN
+    assert w["quantizer"] == {"log2_scale": qp.log2_scale, "offset": qp.offset,
+                              "delta": qp.delta}
+    keys = []
+    for bits in key_bits:
+        p, q = gen.primes_for(seed, bits)
+        keys.append(dict(sk=pc2.SecretKey(gpu_ctx, bits, p, q), n=p * q))
+    xs = gen.normal_vectors(seed, lengths)
+    nodes = []
+    for i, Ln in enumerate(lengths):
+        k = keys[i % 2]
+        m = torch.empty(Ln, dtype=torch.int64, device="cuda")
+        pc2.pc2_quantize(gpu_ctx, qp.log2_scale, qp.offset, qp.delta,
+                         torch.from_numpy(xs[i]).cuda(), m)
+        rl = gen.gen_r_limbs(k["n"], Ln, k["sk"].L, seed, extra=i)
+        nodes.append(dict(k=k, L=Ln, m=m, r=pc2.to_device_limbs(rl),
+                          c=torch.empty((Ln, 2 * k["sk"].L), dtype=torch.int32, device="cuda")))
+    groups = []
+    for g, k in enumerate(keys):
+        mem = [nd for i, nd in enumerate(nodes) if i % 2 == g]
+        mx = max(nd["L"] for nd in mem)
+        groups.append(dict(k=k, mem=mem, mx=mx,
+                           agg=torch.empty((mx, 2 * k["sk"].L), dtype=torch.int32, device="cuda")))
+    assert gpu_ctx.sync() == 0
+    gpu_ctx.set_option(pc2.PC2_OPT_MODMUL,
+                       pc2.PC2_MODMUL_MFMA if engine == "mfma" else pc2.PC2_MODMUL_VALU)
+    try:
+        enc = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_ENCRYPT, pk=nd["k"]["sk"].public,
+                                       m=nd["m"].view(torch.int32).reshape(nd["L"], 2),
+                                       r=nd["r"], out=nd["c"]) for nd in nodes])
+    finally:
+        gpu_ctx.set_option(pc2.PC2_OPT_MODMUL, pc2.PC2_MODMUL_AUTO)
+    agg = pc2.Batch(gpu_ctx, [dict(op=pc2.PC2_OP_HOM_SUM, pk=g["k"]["sk"].public,
+                                   inputs=[nd["c"] for nd in g["mem"]],
+                                   lengths=[nd["L"] for nd in g["mem"]], out=g["agg"])
+                              for g in groups])
+    enc.run(0)
+    agg.run(0)
+    assert gpu_ctx.sync() == 0
+    for i, nd in enumerate(nodes):
+        rows = nd["c"][::stride]
+        assert rows.shape[0] == (nd["L"] + stride - 1) // stride
+        assert not _digest_mismatches(rows, rows.shape[0], rows.shape[0],
+                                      [doc["node_digests"][i]]), f"{engine}: node {i}"
+    for g, grp in enumerate(groups):
+        rows = grp["agg"][::stride]
+        assert not _digest_mismatches(rows, rows.shape[0], rows.shape[0],
+                                      [doc["agg_digests"][g]]), f"{engine}: aggregate of key {g}"
+    enc.close()
+    agg.close()

@@ -61,7 +61,7 @@ struct MGeo {
   static constexpr int NU = UMAX - UMIN + 1;
   static constexpr int X0 = 64 * TMAX + 195;         // reversed array: byte X0 - i = digit i
   // A reversed array is kept as four copies, copy c at byte c PR holding it
-  // shifted down by c bytes (see mul_tiles).  Every read of copy c lies in
+  // shifted down by c bytes (see mma_tiles).  Every read of copy c lies in
   // [c PR, c PR + X0 + 253) and its digits in [c PR + X0 - D + 1 - c,
   // c PR + X0 - c], so neighbouring copies share their zero pads when
   // PR >= D + 256 and PR > X0.
@@ -99,26 +99,40 @@ __device__ __forceinline__ uint32_t limb_digits(uint32_t v) {
   return (v & 0x7Fu) | ((v << 1) & 0x7F00u) | ((v << 2) & 0x7F0000u) | ((v << 3) & 0xFF000000u);
 }
 
-// Digit sums of x y for tiles Q0 .. NTQ - 1.  y: a forward digit array (LDS
-// or global; digit i at byte PF + i); lane (j, g) takes the B chunk of
-// digits [64 u + 4 j + 16 g, +16), read as four dword-aligned words, for
-// every chunk u in one of NPART parts (one part's chunks held in registers
-// at a time).  x: its reversed array in LDS; lane (i, g) takes the Toeplitz
-// band of digits alpha(i) + 64 t - 16 g - s, s < 16, i.e. bytes
+// The B operand chunks of y, a forward digit array (LDS or global; digit i
+// at byte PF + i): lane (j, g) takes digits [64 u + 4 j + 16 g, +16) of
+// chunk u = UMIN + k into B[k], read as four dword-aligned words.  Chunks
+// that no matrix product of the caller uses are dropped by the compiler.
+template <class G>
+__device__ __forceinline__ void load_b(v4i (&B)[G::NU], const uint8_t* y, int lane) {
+  const int base = 4 * (lane & 15) + 16 * (lane >> 4);
+#pragma unroll
+  for (int k = 0; k < G::NU; ++k) {
+    // chunks past the end of the digits (only in the last chunk, for some
+    // lanes) are read from the zero front pad instead
+    const int u = G::UMIN + k;
+    int off = 64 * u + base;  // >= -64
+    if (64 * u + 108 >= G::D8 && off >= G::D8) off = -G::PF;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(y + G::PF + off);
+    B[k] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+  }
+}
+
+// Digit sums of x y for tiles Q0 .. NTQ - 1, y's B chunks in B (load_b).
+// x: its reversed array in LDS; lane (i, g) takes the Toeplitz band of
+// digits alpha(i) + 64 t - 16 g - s, s < 16, i.e. bytes
 // X0 - alpha(i) - 64 t + 16 g .. +16, which start 3 - i % 4 bytes past a
 // 16-byte boundary; in the copy rotated by that many bytes they start at the
 // boundary, so every lane makes one aligned 16-byte read (unaligned LDS
 // reads stall the LDS pipeline).  Tile Q, lane l: limb 64 Q + l, digit c in
 // accumulator c.
 // ACC: add to C instead of starting from zero.
-template <class G, int NTQ, int Q0 = 0, bool ACC = false, int NPART = 1>
-__device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, const uint8_t* y,
+template <class G, int NTQ, int Q0 = 0, bool ACC = false>
+__device__ __forceinline__ void mma_tiles(v4i (&C)[NTQ], const uint8_t* xr, const v4i (&B)[G::NU],
                                           int lane) {
-  constexpr int NUP = (G::NU + NPART - 1) / NPART;
   const int i = lane & 15;
   const int sb = 3 - (i & 3);
   const uint8_t* bp = xr + sb * G::PR + G::X0 - 3 - 64 * (i >> 2) + 16 * (lane >> 4);
-  const int base = 4 * (lane & 15) + 16 * (lane >> 4);
   if constexpr (!ACC) {
 #pragma unroll
     for (int q = Q0; q < NTQ; ++q) C[q] = v4i{0, 0, 0, 0};
@@ -128,40 +142,20 @@ __device__ __forceinline__ void mul_tiles(v4i (&C)[NTQ], const uint8_t* xr, cons
   // faster at 2048 bits)
   __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-  for (int part = 0; part < NPART; ++part) {
-    const int ulo = G::UMIN + part * NUP;
-    const int uhi = part == NPART - 1 ? G::UMAX : ulo + NUP - 1;
-    v4i B[NUP];
+  for (int t = G::TMIN; t <= G::TMAX; ++t) {
+    bool any = false;
 #pragma unroll
-    for (int k = 0; k < NUP; ++k) {
-      // chunks past the end of the digits (only in the last chunk, for some
-      // lanes) are read from the zero front pad instead
-      const int u = ulo + k;
-      int off = 64 * u + base;  // >= -64
-      if (64 * u + 108 >= G::D8 && off >= G::D8) off = -G::PF;
-      v4i b = v4i{0, 0, 0, 0};
-      if (u <= uhi) {
-        const uint32_t* w = reinterpret_cast<const uint32_t*>(y + G::PF + off);
-        b = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-      }
-      B[k] = b;
+    for (int q = Q0; q < NTQ; ++q) {
+      const int u = 4 * q - t;
+      any |= (u >= G::UMIN && u <= G::UMAX);
     }
+    if (!any) continue;
+    const v4i a = *reinterpret_cast<const v4i*>(__builtin_assume_aligned(bp - 64 * t, 16));
 #pragma unroll
-    for (int t = G::TMIN; t <= G::TMAX; ++t) {
-      bool any = false;
-#pragma unroll
-      for (int q = Q0; q < NTQ; ++q) {
-        const int u = 4 * q - t;
-        any |= (u >= ulo && u <= uhi);
-      }
-      if (!any) continue;
-      const v4i a = *reinterpret_cast<const v4i*>(__builtin_assume_aligned(bp - 64 * t, 16));
-#pragma unroll
-      for (int q = Q0; q < NTQ; ++q) {
-        const int u = 4 * q - t;
-        if (u >= ulo && u <= uhi)
-          C[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, B[u - ulo], C[q], 0, 0, 0);
-      }
+    for (int q = Q0; q < NTQ; ++q) {
+      const int u = 4 * q - t;
+      if (u >= G::UMIN && u <= G::UMAX)
+        C[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, B[u - G::UMIN], C[q], 0, 0, 0);
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -291,7 +285,12 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const MConst& K, const ui
   const FoldK k;
   const int ls = G::S - 64 * QH;  // lane of limb S in tile QH
   v4i C[NT];                      // digit columns of T, then of T + q N
-  mul_tiles<G, NT>(C, ws.xr, y, lane);
+  v4i B[G::NU];                   // B operand chunks: y, then N', then N
+  load_b<G>(B, y, lane);
+  mma_tiles<G, NT>(C, ws.xr, B, lane);
+  // the constants' chunks are loaded before the fold that precedes their
+  // products, so that their latency hides behind it (measured: 2-3 % faster)
+  load_b<G>(B, K.Np, lane);
   int32_t Lq[NL];                 // T mod R (limbs below S)
   {
     int64_t vb[NL];
@@ -308,7 +307,8 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const MConst& K, const ui
     v4i Cq[NL];
     int64_t vb[NL];
     int32_t Q[NL], cin[NL];
-    mul_tiles<G, NL>(Cq, ws.tr, K.Np, lane);
+    mma_tiles<G, NL>(Cq, ws.tr, B, lane);
+    load_b<G>(B, K.N, lane);
 #pragma unroll
     for (int q = 0; q < NL; ++q) vb[q] = fold_biased(Cq[q], k.k7, k.k14, k.k21);
     split<NL>(Q, cin, vb, lane);  // limbs from S up are not written: q mod R
@@ -317,7 +317,7 @@ __device__ __forceinline__ void mont_mul(MWork<G>& ws, const MConst& K, const ui
   // below limb S, tile QH carries T mod R as limb values into q N
   if (lane < ls) C[QH] = v4i{Lq[QH], 0, 0, 0};
   wave_sync();
-  mul_tiles<G, NT, QH, true>(C, ws.qr, K.N, lane);
+  mma_tiles<G, NT, QH, true>(C, ws.qr, B, lane);
   int64_t vb[NH];
 #pragma unroll
   for (int q = 0; q < NH; ++q) vb[q] = fold_biased(C[QH + q], k.k7, k.k14, k.k21);
